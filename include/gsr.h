@@ -1,0 +1,174 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) sorted Gaussian-splatting rasterizer.
+ *
+ * The library renders 3D Gaussians for a pinhole camera with the hierarchical
+ * per-pixel resorting of "StopThePop: Sorted Gaussian Splatting for
+ * View-Consistent Real-time Rendering" (Sec. 3.4), or with the global depth
+ * order of 3D Gaussian Splatting (Sec. 2.1) for comparison.
+ *
+ * Conventions for every entry point:
+ *  - Array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *    except where a comment says host.  The caller allocates and owns every
+ *    input, output and workspace buffer; the library keeps no device memory
+ *    between calls.
+ *  - All work is enqueued on the caller's stream and the call returns at once;
+ *    there is no hidden host synchronisation.  Results are ready when the
+ *    stream reaches that point.
+ *  - Return value: GSR_OK (0) or a negative GSR_E* code; a message for the
+ *    last error of the calling thread is available from gsr_last_error().
+ *  - Data-dependent overflow (more tile entries than the workspace holds) is
+ *    reported on the device, in bit 0 of *status_dev, which the library only
+ *    ever ORs into; the caller clears it.  Outputs of such a call are
+ *    undefined; size the workspace up and call again.
+ *  - A Gaussian with a non-finite parameter, a non-positive scale or an
+ *    opacity below 1/255 is culled; it is not an error.
+ *  - Floating point is IEEE binary32 throughout: no contraction into fused
+ *    multiply-adds, correctly rounded division and square root, and one
+ *    project-written exp (Cody-Waite reduction + degree-7 polynomial).
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gsr_stream_t; /* a hipStream_t; NULL is the null stream */
+
+enum {
+    GSR_OK = 0,
+    GSR_EINVAL = -1,       /* null pointer, bad size or invalid configuration */
+    GSR_ECAPACITY = -2,    /* workspace smaller than gsr_workspace_bytes() requires */
+    GSR_EDEVICE = -3,      /* a HIP call failed; see gsr_last_error() */
+    GSR_EUNSUPPORTED = -4  /* device is not gfx950 */
+};
+
+enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1 };
+
+enum { GSR_STATUS_OVERFLOW = 1 };
+
+/* Gaussians of one scene (Sec. 2.1): N rows per array, row-major, float32.
+ *   means     [N,3]  centre mu
+ *   scales    [N,3]  activated scales s (> 0)
+ *   rots      [N,4]  quaternion (w, x, y, z), normalised inside; zero -> identity
+ *   opacities [N]    activated opacity in [0, 1]
+ *   sh        [N,(d+1)^2,3] real SH coefficients of degree d in 0..3 */
+typedef struct gsr_scene {
+    int32_t n;
+    int32_t sh_degree;
+    const float* means;
+    const float* scales;
+    const float* rots;
+    const float* opacities;
+    const float* sh;
+} gsr_scene;
+
+/* Pinhole camera.  p_cam = R p + t with R world->camera (row-major), camera
+ * looking along +z, x right, y down; `center` is the camera centre -R^T t.
+ * Pixel (i, j) has its centre at image coordinates (i, j). */
+typedef struct gsr_camera {
+    float R[9];
+    float t[3];
+    float center[3];
+    float fx, fy, cx, cy;
+    float znear;
+    int32_t W, H;
+} gsr_camera;
+
+/* Render configuration (Sec. 3.4).  Queue sizes change results:
+ *   batch     tail batch B (32; the kernel is built for 32)
+ *   tail      tail capacity, 32 n + 32 with n >= 1 (64)
+ *   pop       tail -> mid chunk (16)
+ *   mid       mid capacity, 4 m + 4 with m >= 1 (8)
+ *   mid_batch mid sub-batch (4)
+ *   head      per-pixel head capacity K in 1..24 (4)
+ * lb_threshold only changes speed (tiles above which preprocessing and
+ * duplication share a Gaussian across the wavefront; 32).
+ * bg is the background colour. */
+typedef struct gsr_config {
+    int32_t mode;
+    int32_t batch, tail, pop, mid, mid_batch, head;
+    int32_t lb_threshold;
+    float bg[3];
+    uint32_t flags; /* reserved, must be 0 */
+} gsr_config;
+
+/* Byte offsets of the regions of a workspace, for inspection and debugging.
+ * Records (App. B.4), one row per Gaussian:
+ *   xy       float2 2D mean            conic_o  float4 (a, b, c, opacity)
+ *   sw       float[12] Sigma^-1 (s00 s01 s02 s11 s12 s22), w = Sigma^-1 (mu - o), rgb
+ *   zd       float2 (view depth, |mu - o|)
+ *   rect     int32[4] tile rectangle (x0, y0, x1, y1), inclusive
+ *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
+ * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
+ * (Gaussian id), ranges uint32[tiles][2] = [start, end) per tile; counters
+ * uint32[4] = (entries, entries consumed by the renderer, unused, unused). */
+typedef struct gsr_layout {
+    int64_t xy, conic_o, sw, zd, rect, touched, offsets;
+    int64_t keys, values, ranges, counters;
+    int64_t entry_capacity;
+    int64_t total_bytes;
+} gsr_layout;
+
+/* Workspace needed to render n Gaussians at W x H with room for
+ * entries_max (tile, Gaussian) entries.  Returns 0 for invalid sizes. */
+size_t gsr_workspace_bytes(int64_t n, int32_t W, int32_t H, int64_t entries_max);
+
+/* Layout of a workspace of ws_bytes for n Gaussians at W x H.  The entry
+ * capacity is whatever the workspace holds beyond the per-Gaussian and
+ * per-tile regions.  Returns GSR_ECAPACITY if not even one entry fits. */
+int gsr_workspace_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* out /* host */);
+
+/* Default configuration (hierarchical, 32/64/16/8/4/4, black background). */
+void gsr_default_config(gsr_config* cfg /* host */);
+
+/* Validate a configuration (Sec. 3.4: tail = 32 n + 32, mid = 4 m + 4).
+ * Returns GSR_OK or GSR_EINVAL. */
+int gsr_check_config(const gsr_config* cfg /* host */);
+
+/* Render one frame: preprocess, count and duplicate (tile, depth) entries,
+ * radix-sort them, find tile ranges, and blend every pixel front to back with
+ * early termination (Eq. volume_desc).  In GSR_MODE_HIER the blend order is
+ * the hierarchical tail / mid / head resorting on per-level t_opt (Eq. dopt);
+ * in GSR_MODE_GLOBAL it is the 3DGS view-space-depth order.
+ *   rgb     [3,H,W] float32 out   colour + T_final * bg
+ *   depth   [H,W]   float32 out   sum of t_opt alpha T (GLOBAL: |mu - o|)
+ *   count   [H,W]   int32   out   number of Gaussians blended
+ *   T_final [H,W]   float32 out   final transmittance
+ *   status_dev      int32   in/out, see above
+ * ws must stay unmodified between a forward call and its backward. */
+int gsr_render(const gsr_scene* scene /* host struct, device arrays */, const gsr_camera* cam /* host */,
+               const gsr_config* cfg /* host */, void* ws, size_t ws_bytes, float* rgb, float* depth,
+               int32_t* count, float* T_final, int32_t* status_dev, gsr_stream_t stream);
+
+/* As gsr_render, and also writes the first max_k blended Gaussian ids of
+ * every pixel, in blend order, to blend_ids [H,W,max_k] (int32, -1 padded). */
+int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                     size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
+                     int32_t* blend_ids, int32_t max_k, int32_t* status_dev, gsr_stream_t stream);
+
+/* As gsr_render, and records five caller-created HIP events (hipEvent_t,
+ * passed as void*) on the stream at the stage boundaries of Sec. 4.3's
+ * breakdown: events[0] before Preprocess, [1] after Preprocess, [2] after
+ * Duplicate (prefix sum + key emission), [3] after Sort (radix sort + tile
+ * ranges), [4] after Render.  The caller owns and destroys the events. */
+int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                      size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
+                      int32_t* status_dev, gsr_stream_t stream, void* const* events);
+
+/* Element-wise arithmetic probe of the device (diagnostic): for n inputs
+ * a[i], b[i] writes out[k*n + i] for k = 0..5:
+ *   a/b, sqrt(a), project exp(a), project ln(a) (a >= 1), rint(a), a*b+a. */
+int gsr_probe_math(const float* a, const float* b, int32_t n, float* out, gsr_stream_t stream);
+
+const char* gsr_last_error(void);
+const char* gsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

@@ -52,7 +52,7 @@ class OFrameOut(C.Structure):
                 ("values", C.c_void_p), ("capacity", C.c_int64), ("n_entries", C.c_int64),
                 ("ranges", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p),
                 ("count", C.c_void_p), ("T", C.c_void_p), ("blend_ids", C.c_void_p),
-                ("max_k", C.c_int32), ("delta", C.c_void_p), ("stats", C.c_int64 * 12)]
+                ("max_k", C.c_int32), ("delta", C.c_void_p), ("stats", C.c_int64 * 12), ("tile_mask", C.c_void_p)]
 
 
 def lib():
@@ -127,8 +127,10 @@ def _scene_arrays(scene):
             (scene.means, scene.scales, scene.rots, scene.opacities, scene.sh)]
 
 
-def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", **cfgkw) -> FrameResult:
-    """Run the whole frame on the CPU and return every intermediate."""
+def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mask=None, **cfgkw) -> FrameResult:
+    """Run the whole frame on the CPU and return every intermediate.  With
+    ``tile_mask`` (uint8 per tile) only those tiles are rendered; per-Gaussian
+    records and the sorted entries are always complete."""
     L = lib()
     n = scene.n
     arrs = _scene_arrays(scene)
@@ -157,6 +159,8 @@ def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", **cfgkw)
         o.keys, o.values, o.capacity = _p(keys), _p(values), cap
         o.ranges, o.count, o.delta = _p(ranges), _p(count), _p(delta)
         o.blend_ids, o.max_k = _p(bids), max_k
+        mask = None if tile_mask is None else np.ascontiguousarray(tile_mask, dtype=np.uint8)
+        o.tile_mask = _p(mask)
         oc, of = ocam(cam), ocfg(mode=mode, head=head, **cfgkw)
         if precision == "f32":
             o.rgb, o.depth, o.T = _p(rgb), _p(depth), _p(T)

@@ -355,10 +355,13 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
 
     // Sigma = R S S^T R^T (Sec. 2.1).
     F s2[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+    // Each symmetric matrix is formed on and above the diagonal and mirrored.
     F Sg[3][3];
     for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 3; ++k)
+        for (int k = j; k < 3; ++k) {
             Sg[j][k] = ((Rq[j][0] * s2[0]) * Rq[k][0] + (Rq[j][1] * s2[1]) * Rq[k][1]) + (Rq[j][2] * s2[2]) * Rq[k][2];
+            Sg[k][j] = Sg[j][k];
+        }
 
     // Sigma^-1 = R S^-2 R^T with the entries of S^-1 bounded by 10^3 (Sec. 3.2, App. A).
     F si2[3];
@@ -369,8 +372,10 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
     }
     F Si[3][3];
     for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 3; ++k)
+        for (int k = j; k < 3; ++k) {
             Si[j][k] = ((Rq[j][0] * si2[0]) * Rq[k][0] + (Rq[j][1] * si2[1]) * Rq[k][1]) + (Rq[j][2] * si2[2]) * Rq[k][2];
+            Si[k][j] = Si[j][k];
+        }
 
     F dm[3] = {mu[0] - cam.o[0], mu[1] - cam.o[1], mu[2] - cam.o[2]};
     F w[3];
@@ -404,15 +409,12 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
     F c = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + F(0.3);
     F det = a * c - b * b;
     if (!(det > F(0))) return;
-    g.ca = c / det;
-    g.cb = (-b) / det;
-    g.cc = a / det;
-    g.x = cam.fx * txtz + cam.cx;
-    g.y = cam.fy * tytz + cam.cy;
+    const F ca = c / det, cb = (-b) / det, cc = a / det;
+    const F mx = cam.fx * txtz + cam.cx;
+    const F my = cam.fy * tytz + cam.cy;
 
     // Opacity below eps_O can never contribute.
     if (!(op >= eps_o<F>())) return;
-    g.op = op;
 
     // Bounding radius from the largest eigenvalue of Sigma_2.
     F mid = F(0.5) * (a + c);
@@ -425,20 +427,19 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
         // Opacity-aware bound t_O = sqrt(2 ln(o / eps_O)) (App. B.2), widened by
         // 1/256 and one pixel so that only exact culling decides the kept set.
         F tO = std::sqrt(F(2) * lnE(op / eps_o<F>()));
-        F r = tO * std::sqrt(lam);
+        F r = tO * std::sqrt(lam);  // radius
         rr = r * F(1.00390625) + F(1);
     }
     // Tiles whose pixel-centre hull meets [x - rr, x + rr] x [y - rr, y + rr].
-    F fx0 = std::ceil(((g.x - rr) - F(15)) / F(16));
-    F fx1 = std::floor((g.x + rr) / F(16));
-    F fy0 = std::ceil(((g.y - rr) - F(15)) / F(16));
-    F fy1 = std::floor((g.y + rr) / F(16));
+    F fx0 = std::ceil(((mx - rr) - F(15)) / F(16));
+    F fx1 = std::floor((mx + rr) / F(16));
+    F fy0 = std::ceil(((my - rr) - F(15)) / F(16));
+    F fy1 = std::floor((my + rr) / F(16));
     fx0 = sclamp(fx0, F(0), (F)cam.tiles_x);
     fy0 = sclamp(fy0, F(0), (F)cam.tiles_y);
     fx1 = sclamp(fx1, F(-1), (F)(cam.tiles_x - 1));
     fy1 = sclamp(fy1, F(-1), (F)(cam.tiles_y - 1));
-    if (!(fx0 <= fx1) || !(fy0 <= fy1)) { g.op = 0; g.x = g.y = 0; g.ca = g.cb = g.cc = 0; return; }
-    g.rect[0] = (int)fx0; g.rect[1] = (int)fy0; g.rect[2] = (int)fx1; g.rect[3] = (int)fy1;
+    if (!(fx0 <= fx1) || !(fy0 <= fy1)) return;
 
     // View-dependent colour from SH with the direction camera -> mean (App. B.4).
     F len = std::sqrt((dm[0] * dm[0] + dm[1] * dm[1]) + dm[2] * dm[2]);
@@ -446,14 +447,21 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
     F bas[16];
     sh_basis<F>(deg, dir[0], dir[1], dir[2], bas);
     int K = (deg + 1) * (deg + 1);
+    F rgb[3];
+    bool clamped[3];
     for (int ch = 0; ch < 3; ++ch) {
         F acc = bas[0] * (F)sh_in[ch];
         for (int k = 1; k < K; ++k) acc = acc + bas[k] * (F)sh_in[3 * k + ch];
         acc = acc + F(0.5);
-        g.clamp_rgb[ch] = acc < F(0);
-        g.rgb[ch] = acc < F(0) ? F(0) : acc;
-        if (!std::isfinite(g.rgb[ch])) { std::memset(&g, 0, sizeof(g)); return; }
+        if (!std::isfinite(acc)) return;
+        clamped[ch] = acc < F(0);
+        rgb[ch] = acc < F(0) ? F(0) : acc;
     }
+    // Visible: write the record.
+    g.x = mx; g.y = my;
+    g.ca = ca; g.cb = cb; g.cc = cc; g.op = op;
+    g.rect[0] = (int)fx0; g.rect[1] = (int)fy0; g.rect[2] = (int)fx1; g.rect[3] = (int)fy1;
+    for (int ch = 0; ch < 3; ++ch) { g.rgb[ch] = rgb[ch]; g.clamp_rgb[ch] = clamped[ch]; }
     g.s[0] = Si[0][0]; g.s[1] = Si[0][1]; g.s[2] = Si[0][2];
     g.s[3] = Si[1][1]; g.s[4] = Si[1][2]; g.s[5] = Si[2][2];
     g.w[0] = w[0]; g.w[1] = w[1]; g.w[2] = w[2];
@@ -724,7 +732,7 @@ template <class F> struct Frame {
 
 template <class F>
 void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* scales, const float* rots,
-               const float* opac, const float* sh) {
+               const float* opac, const float* sh, const uint8_t* tile_mask) {
     const Cam<F>& cam = fr.cam;
     const int mode = fr.cfg.mode;
     const int K = (deg + 1) * (deg + 1);
@@ -787,6 +795,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
         // Each pixel blends its tile's list in key order (3DGS).
 #pragma omp parallel for schedule(dynamic, 1)
         for (int tile = 0; tile < ntiles; ++tile) {
+            if (tile_mask && !tile_mask[tile]) continue;
             int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
             for (int y = ty * 16; y < std::min(ty * 16 + 16, cam.H); ++y)
                 for (int x = tx * 16; x < std::min(tx * 16 + 16, cam.W); ++x) {
@@ -811,6 +820,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
     for (int s = 0; s < sub_x * sub_y; ++s) {
         int sx = s % sub_x, sy = s / sub_x;
         int tile = (sy / 4) * cam.tiles_x + (sx / 4);
+        if (tile_mask && !tile_mask[tile]) continue;
         HierSubtile<F> H(cam, fr.cfg, fr.recs, sx * 4, sy * 4, fr.pix, sts[s]);
         H.run(ids.data(), fr.range_lo[tile], fr.range_hi[tile]);
     }
@@ -850,6 +860,7 @@ struct OFrameOut {
     int32_t max_k;
     float* delta;        // [H,W] per-pixel sort error
     int64_t stats[12];   // out: tail_in, mid_in, head_in, blends, max_tail, max_mid, max_head, min_tail_after_pop, entries
+    const uint8_t* tile_mask;  // optional [tiles]: render only these tiles
 };
 
 template <class F, class OUT>
@@ -858,7 +869,7 @@ static int frame_impl(int n, int deg, const float* means, const float* scales, c
                       OUT* rgb_out, OUT* depth_out, OUT* T_out) {
     if (n < 0 || deg < 0 || deg > 3 || cam->W <= 0 || cam->H <= 0) return -1;
     Frame<F> fr(*cam, *cfg);
-    run_frame<F>(fr, n, deg, means, scales, rots, opac, sh);
+    run_frame<F>(fr, n, deg, means, scales, rots, opac, sh, o->tile_mask);
     for (int i = 0; i < n; ++i) {
         const Rec<F>& g = fr.recs[i];
         if (o->xy) { o->xy[2 * i] = (float)g.x; o->xy[2 * i + 1] = (float)g.y; }

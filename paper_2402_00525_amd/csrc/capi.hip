@@ -1,0 +1,295 @@
+// Host side of the C ABI: argument validation, workspace layout and the
+// stream-ordered launch sequence of a frame.
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/gsr.h"
+#include "gsr_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return GSR_EDEVICE;
+}
+
+inline int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Layout for a given entry capacity.
+void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_partial, int64_t* hist,
+                int64_t* keys1, int64_t* vals1) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L->xy = take(8 * n);
+    L->conic_o = take(16 * n);
+    L->sw = take(48 * n);
+    L->zd = take(8 * n);
+    L->rect = take(16 * n);
+    L->touched = take(4 * n);
+    L->offsets = take(4 * n);
+    L->ranges = take(8 * (int64_t)tiles);
+    L->counters = take(64);
+    const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
+    const int64_t sp = (int64_t)std::max(gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)nb * 256)) + 2;
+    *scan_partial = take(4 * sp);
+    *hist = take(4 * 256 * nb);
+    L->keys = take(8 * cap);
+    *keys1 = take(8 * cap);
+    L->values = take(4 * cap);
+    *vals1 = take(4 * cap);
+    L->entry_capacity = cap;
+    L->total_bytes = off;
+}
+
+int tiles_of(int W, int H) { return ((W + 15) / 16) * ((H + 15) / 16); }
+
+int compute_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* L, int64_t* sp, int64_t* hist,
+                   int64_t* k1, int64_t* v1) {
+    if (n < 0 || W <= 0 || H <= 0 || W > 32768 || H > 32768) return GSR_EINVAL;
+    const int tiles = tiles_of(W, H);
+    // Largest capacity whose layout fits (the layout size grows with it).
+    int64_t lo = 0, hi = ((int64_t)1 << 31) - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        layout_for(n, tiles, mid, L, sp, hist, k1, v1);
+        if (L->total_bytes <= (int64_t)ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    if (lo <= 0) return GSR_ECAPACITY;
+    layout_for(n, tiles, lo, L, sp, hist, k1, v1);
+    return GSR_OK;
+}
+
+gsr::DevCam make_cam(const gsr_camera* c) {
+    gsr::DevCam d;
+    for (int i = 0; i < 9; ++i) d.R[i] = c->R[i];
+    for (int i = 0; i < 3; ++i) {
+        d.t[i] = c->t[i];
+        d.o[i] = c->center[i];
+    }
+    d.fx = c->fx;
+    d.fy = c->fy;
+    d.cx = c->cx;
+    d.cy = c->cy;
+    d.znear = c->znear;
+    d.W = c->W;
+    d.H = c->H;
+    d.tiles_x = (c->W + 15) / 16;
+    d.tiles_y = (c->H + 15) / 16;
+    // Frustum clamp of the EWA Jacobian: 1.3 x tan(half field of view).
+    d.limx = 1.3f * ((float)c->W / (2.0f * c->fx));
+    d.limy = 1.3f * ((float)c->H / (2.0f * c->fy));
+    return d;
+}
+
+int bits_for_tiles(int tiles) {
+    int b = 0;
+    while ((1 << b) < tiles) ++b;
+    return b;
+}
+
+int check_scene(const gsr_scene* s) {
+    if (!s) return fail(GSR_EINVAL, "scene is NULL");
+    if (s->n < 0) return fail(GSR_EINVAL, "scene n < 0");
+    if (s->sh_degree < 0 || s->sh_degree > 3) return fail(GSR_EINVAL, "sh_degree must be 0..3");
+    if (s->n > 0 && (!s->means || !s->scales || !s->rots || !s->opacities || !s->sh))
+        return fail(GSR_EINVAL, "scene array is NULL");
+    return GSR_OK;
+}
+
+int check_camera(const gsr_camera* c) {
+    if (!c) return fail(GSR_EINVAL, "camera is NULL");
+    if (c->W <= 0 || c->H <= 0 || c->W > 32768 || c->H > 32768) return fail(GSR_EINVAL, "bad image size");
+    if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) return fail(GSR_EINVAL, "focal lengths must be > 0");
+    return GSR_OK;
+}
+
+int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+                float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
+                int32_t* status_dev, gsr_stream_t stream, void* const* events) {
+    int rc = check_scene(scene);
+    if (rc) return rc;
+    if ((rc = check_camera(cam))) return rc;
+    if (!cfg) return fail(GSR_EINVAL, "config is NULL");
+    if ((rc = gsr_check_config(cfg))) return rc;
+    if (!ws || !rgb || !depth || !count || !T_final || !status_dev) return fail(GSR_EINVAL, "output or workspace is NULL");
+    if (blend_ids && max_k <= 0) return fail(GSR_EINVAL, "max_k must be > 0");
+    if (cfg->mode == GSR_MODE_HIER && !gsr::hier_head_supported(cfg->head))
+        return fail(GSR_EUNSUPPORTED, "head size not built (1,2,3,4,6,8,12,16,20,24)");
+    gsr_layout L;
+    int64_t sp, hist, k1, v1;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &sp, &hist, &k1, &v1);
+    if (rc) return fail(rc, "workspace too small");
+    char* base = (char*)ws;
+    if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
+    gsr::FrameBufs b;
+    b.xy = (float2*)(base + L.xy);
+    b.co = (float4*)(base + L.conic_o);
+    b.sw = (float4*)(base + L.sw);
+    b.zd = (float2*)(base + L.zd);
+    b.rect = (int4*)(base + L.rect);
+    b.touched = (uint32_t*)(base + L.touched);
+    b.offsets = (uint32_t*)(base + L.offsets);
+    b.scan_partial = (uint32_t*)(base + sp);
+    b.hist = (uint32_t*)(base + hist);
+    b.keys[0] = (uint64_t*)(base + L.keys);
+    b.keys[1] = (uint64_t*)(base + k1);
+    b.vals[0] = (uint32_t*)(base + L.values);
+    b.vals[1] = (uint32_t*)(base + v1);
+    b.ranges = (uint32_t*)(base + L.ranges);
+    b.counters = (uint32_t*)(base + L.counters);
+    b.capacity = (uint32_t)L.entry_capacity;
+
+    hipStream_t s = (hipStream_t)stream;
+    const gsr::DevCam dc = make_cam(cam);
+    const int tiles = dc.tiles_x * dc.tiles_y;
+    const int mode = cfg->mode;
+    const int key_bits = 32 + bits_for_tiles(tiles);
+    const int passes = (key_bits + 7) / 8;
+    gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
+
+    hipError_t e;
+    auto mark = [&](int k) -> hipError_t {
+        return events ? hipEventRecord((hipEvent_t)events[k], s) : hipSuccess;
+    };
+    if ((e = mark(0)) != hipSuccess) return fail_hip(e, "event");
+    if ((e = gsr::launch_fill_u32(b.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
+    if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, b, s)) != hipSuccess) return fail_hip(e, "preprocess");
+    if ((e = mark(1)) != hipSuccess) return fail_hip(e, "event");
+    if ((e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
+                              s)) != hipSuccess)
+        return fail_hip(e, "scan");
+    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, b, passes & 1, status_dev, s)) != hipSuccess)
+        return fail_hip(e, "duplicate");
+    if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
+    int res = 0;
+    if ((e = gsr::launch_sort(b, key_bits, &res, s)) != hipSuccess) return fail_hip(e, "sort");
+    if ((e = gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess)
+        return fail_hip(e, "ranges");
+    if ((e = mark(3)) != hipSuccess) return fail_hip(e, "event");
+    gsr::RenderArgs ra;
+    ra.cam = dc;
+    ra.n = (uint32_t)scene->n;
+    ra.xy = b.xy;
+    ra.co = b.co;
+    ra.sw = b.sw;
+    ra.zd = b.zd;
+    ra.vals = b.vals[res];
+    ra.ranges = b.ranges;
+    ra.counters = b.counters;
+    ra.rgb = rgb;
+    ra.depth = depth;
+    ra.count = count;
+    ra.T = T_final;
+    ra.blend_ids = blend_ids;
+    ra.max_k = blend_ids ? max_k : 0;
+    ra.bg0 = cfg->bg[0];
+    ra.bg1 = cfg->bg[1];
+    ra.bg2 = cfg->bg[2];
+    if (mode == GSR_MODE_HIER)
+        e = gsr::launch_render_hier(ra, cfg->head, s);
+    else
+        e = gsr::launch_render_global(ra, s);
+    if (e != hipSuccess) return fail_hip(e, "render");
+    if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
+    return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gsr_workspace_bytes(int64_t n, int32_t W, int32_t H, int64_t entries_max) {
+    if (n < 0 || W <= 0 || H <= 0 || entries_max < 1 || entries_max > ((int64_t)1 << 31) - 1) return 0;
+    gsr_layout L;
+    int64_t sp, hist, k1, v1;
+    layout_for(n, tiles_of(W, H), entries_max, &L, &sp, &hist, &k1, &v1);
+    return (size_t)L.total_bytes;
+}
+
+int gsr_workspace_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* out) {
+    if (!out) return fail(GSR_EINVAL, "layout is NULL");
+    int64_t sp, hist, k1, v1;
+    const int rc = compute_layout(n, W, H, ws_bytes, out, &sp, &hist, &k1, &v1);
+    if (rc) return fail(rc, "workspace too small or bad size");
+    return GSR_OK;
+}
+
+void gsr_default_config(gsr_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->mode = GSR_MODE_HIER;
+    c->batch = 32;
+    c->tail = 64;
+    c->pop = 16;
+    c->mid = 8;
+    c->mid_batch = 4;
+    c->head = 4;
+    c->lb_threshold = 32;
+}
+
+int gsr_check_config(const gsr_config* c) {
+    if (!c) return fail(GSR_EINVAL, "config is NULL");
+    if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER) return fail(GSR_EINVAL, "unknown mode");
+    if (c->flags != 0) return fail(GSR_EINVAL, "flags must be 0");
+    if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
+    if (c->mode == GSR_MODE_HIER) {
+        if (c->tail < 64 || (c->tail - 32) % 32 != 0) return fail(GSR_EINVAL, "tail must be 32n+32, n>=1");
+        if (c->mid < 8 || (c->mid - 4) % 4 != 0) return fail(GSR_EINVAL, "mid must be 4m+4, m>=1");
+        if (c->head < 1) return fail(GSR_EINVAL, "head must be >= 1");
+        if (c->batch != 32 || c->tail != 64 || c->pop != 16 || c->mid != 8 || c->mid_batch != 4 || c->head > 24)
+            return fail(GSR_EUNSUPPORTED, "only batch/tail/pop/mid/mid_batch = 32/64/16/8/4 and head <= 24 are built");
+    }
+    return GSR_OK;
+}
+
+int gsr_render(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+               float* rgb, float* depth, int32_t* count, float* T_final, int32_t* status_dev, gsr_stream_t stream) {
+    return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
+                       nullptr);
+}
+
+int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+                      float* rgb, float* depth, int32_t* count, float* T_final, int32_t* status_dev,
+                      gsr_stream_t stream, void* const* events) {
+    if (!events) return fail(GSR_EINVAL, "events is NULL");
+    for (int k = 0; k < 5; ++k)
+        if (!events[k]) return fail(GSR_EINVAL, "event is NULL");
+    return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
+                       events);
+}
+
+int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+                     float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
+                     int32_t* status_dev, gsr_stream_t stream) {
+    if (!blend_ids) return fail(GSR_EINVAL, "blend_ids is NULL");
+    return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, blend_ids, max_k, status_dev, stream,
+                       nullptr);
+}
+
+int gsr_probe_math(const float* a, const float* b, int32_t n, float* out, gsr_stream_t stream) {
+    if (n < 0 || (n > 0 && (!a || !b || !out))) return fail(GSR_EINVAL, "bad probe arguments");
+    const hipError_t e = gsr::launch_probe_math(a, b, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail_hip(e, "probe");
+    return GSR_OK;
+}
+
+const char* gsr_last_error(void) { return g_last_error.c_str(); }
+
+const char* gsr_version(void) { return "gsr 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,575 @@
+// Per-Gaussian stages of a frame: preprocessing (EWA splat, SH colour,
+// clamped inverse covariance, opacity-aware bound, exact tile count),
+// prefix sum of the counts, duplication into (tile, depth) keys, and tile
+// ranges of the sorted keys.
+#include "gsr_internal.h"
+
+namespace gsr {
+
+namespace {
+
+// Real SH constants sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) with signs.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC2a = 1.0925484305920792f;   // xy, yz (neg), xz (neg)
+constexpr float kC2b = 0.31539156525252005f;  // 2zz - xx - yy
+constexpr float kC2c = 0.5462742152960396f;   // xx - yy
+constexpr float kC3a = 0.5900435899266435f;
+constexpr float kC3b = 2.8906114426405543f;
+constexpr float kC3c = 0.4570457994644658f;
+constexpr float kC3d = 0.37317633259011546f;
+constexpr float kC3e = 1.4453057213202771f;
+
+__device__ __forceinline__ uint32_t wave_reduce_add(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+struct PreOut {
+    float2* xy;
+    float4* co;
+    float4* sw;
+    float2* zd;
+    int4* rect;
+};
+
+// Projection and colour of Gaussian i (Sec. 2.1, App. A, App. B.2, App. B.4).
+// Returns false (and writes a zero record) when the Gaussian is culled.
+__device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, int i, const PreOut& out,
+                            Splat& g, int4& rc) {
+    const float mu0 = sc.means[3 * i], mu1 = sc.means[3 * i + 1], mu2 = sc.means[3 * i + 2];
+    const float s0 = sc.scales[3 * i], s1 = sc.scales[3 * i + 1], s2 = sc.scales[3 * i + 2];
+    const float4 qv = reinterpret_cast<const float4*>(sc.rots)[i];
+    const float op = sc.opac[i];
+    bool ok = isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
+              s0 > 0.0f && s1 > 0.0f && s2 > 0.0f && isfinite(qv.x) && isfinite(qv.y) && isfinite(qv.z) &&
+              isfinite(qv.w) && isfinite(op);
+    float rgb[3] = {0.0f, 0.0f, 0.0f};
+    float Si[3][3];
+    float w[3];
+    float pz = 0.0f, dist = 0.0f;
+    float ca = 0.0f, cb = 0.0f, cc = 0.0f, mx = 0.0f, my = 0.0f;
+    float fx0 = 0.0f, fy0 = 0.0f, fx1 = 0.0f, fy1 = 0.0f;
+    if (ok) {
+        // Unit quaternion (w, x, y, z) -> rotation; zero -> identity.
+        const float n2 = ((qv.x * qv.x + qv.y * qv.y) + qv.z * qv.z) + qv.w * qv.w;
+        float qw = 1.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+        if (n2 != 0.0f) {
+            const float nrm = sqrtf(n2);
+            qw = qv.x / nrm; qx = qv.y / nrm; qy = qv.z / nrm; qz = qv.w / nrm;
+        }
+        float Rq[3][3];
+        Rq[0][0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+        Rq[0][1] = 2.0f * (qx * qy - qw * qz);
+        Rq[0][2] = 2.0f * (qx * qz + qw * qy);
+        Rq[1][0] = 2.0f * (qx * qy + qw * qz);
+        Rq[1][1] = 1.0f - 2.0f * (qx * qx + qz * qz);
+        Rq[1][2] = 2.0f * (qy * qz - qw * qx);
+        Rq[2][0] = 2.0f * (qx * qz - qw * qy);
+        Rq[2][1] = 2.0f * (qy * qz + qw * qx);
+        Rq[2][2] = 1.0f - 2.0f * (qx * qx + qy * qy);
+
+        // Sigma = R S^2 R^T and Sigma^-1 = R min(S^-1, 10^3)^2 R^T, upper
+        // triangle formed and mirrored.
+        const float sq[3] = {s0 * s0, s1 * s1, s2 * s2};
+        float si2[3];
+        const float sv[3] = {s0, s1, s2};
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            float si = 1.0f / sv[l];
+            si = (si > 1000.0f) ? 1000.0f : si;
+            si2[l] = si * si;
+        }
+        float Sg[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = j; k < 3; ++k) {
+                Sg[j][k] = ((Rq[j][0] * sq[0]) * Rq[k][0] + (Rq[j][1] * sq[1]) * Rq[k][1]) + (Rq[j][2] * sq[2]) * Rq[k][2];
+                Sg[k][j] = Sg[j][k];
+                Si[j][k] = ((Rq[j][0] * si2[0]) * Rq[k][0] + (Rq[j][1] * si2[1]) * Rq[k][1]) +
+                           (Rq[j][2] * si2[2]) * Rq[k][2];
+                Si[k][j] = Si[j][k];
+            }
+        const float dm[3] = {mu0 - cam.o[0], mu1 - cam.o[1], mu2 - cam.o[2]};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) w[j] = (Si[j][0] * dm[0] + Si[j][1] * dm[1]) + Si[j][2] * dm[2];
+
+        float p[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            p[j] = ((cam.R[3 * j] * mu0 + cam.R[3 * j + 1] * mu1) + cam.R[3 * j + 2] * mu2) + cam.t[j];
+        ok = p[2] > cam.znear;
+        if (ok) {
+            // EWA: Jacobian of the perspective map with the 1.3x frustum clamp.
+            const float txtz = p[0] / p[2], tytz = p[1] / p[2];
+            const float xcl = sel_clamp(txtz, -cam.limx, cam.limx) * p[2];
+            const float ycl = sel_clamp(tytz, -cam.limy, cam.limy) * p[2];
+            const float pz2 = p[2] * p[2];
+            const float J00 = cam.fx / p[2], J02 = -(cam.fx * xcl) / pz2;
+            const float J11 = cam.fy / p[2], J12 = -(cam.fy * ycl) / pz2;
+            float T[2][3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T[0][k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
+                T[1][k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+            }
+            float U[2][3];
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) U[j][k] = (T[j][0] * Sg[0][k] + T[j][1] * Sg[1][k]) + T[j][2] * Sg[2][k];
+            const float a = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3f;
+            const float b = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
+            const float c = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3f;
+            const float det = a * c - b * b;
+            ok = det > 0.0f;
+            if (ok) {
+                ca = c / det;
+                cb = (-b) / det;
+                cc = a / det;
+                mx = cam.fx * txtz + cam.cx;
+                my = cam.fy * tytz + cam.cy;
+                ok = op >= kEpsO;
+            }
+            if (ok) {
+                const float mid = 0.5f * (a + c);
+                const float disc = mid * mid - det;
+                const float lam = mid + sqrtf(0.1f > disc ? 0.1f : disc);
+                float rr;
+                if (mode == kModeGlobal) {
+                    rr = ceilf(3.0f * sqrtf(lam));
+                } else {
+                    // Opacity-aware bound t_O = sqrt(2 ln(o / eps_O)), widened by
+                    // 1/256 and a pixel so that only exact culling decides.
+                    const float tO = sqrtf(2.0f * ln_atanh(op / kEpsO));
+                    const float r = tO * sqrtf(lam);
+                    rr = r * 1.00390625f + 1.0f;
+                }
+                fx0 = ceilf(((mx - rr) - 15.0f) / 16.0f);
+                fx1 = floorf((mx + rr) / 16.0f);
+                fy0 = ceilf(((my - rr) - 15.0f) / 16.0f);
+                fy1 = floorf((my + rr) / 16.0f);
+                fx0 = sel_clamp(fx0, 0.0f, (float)cam.tiles_x);
+                fy0 = sel_clamp(fy0, 0.0f, (float)cam.tiles_y);
+                fx1 = sel_clamp(fx1, -1.0f, (float)(cam.tiles_x - 1));
+                fy1 = sel_clamp(fy1, -1.0f, (float)(cam.tiles_y - 1));
+                ok = (fx0 <= fx1) && (fy0 <= fy1);
+            }
+            if (ok) {
+                // Colour: SH along the direction camera -> mean (App. B.4).
+                const float len = sqrtf((dm[0] * dm[0] + dm[1] * dm[1]) + dm[2] * dm[2]);
+                const float x = dm[0] / len, y = dm[1] / len, z = dm[2] / len;
+                dist = len;
+                pz = p[2];
+                float bas[16];
+                bas[0] = kC0;
+                const int deg = sc.deg;
+                if (deg >= 1) {
+                    bas[1] = (-kC1) * y;
+                    bas[2] = kC1 * z;
+                    bas[3] = (-kC1) * x;
+                }
+                if (deg >= 2) {
+                    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+                    bas[4] = kC2a * xy;
+                    bas[5] = (-kC2a) * yz;
+                    bas[6] = kC2b * ((2.0f * zz - xx) - yy);
+                    bas[7] = (-kC2a) * xz;
+                    bas[8] = kC2c * (xx - yy);
+                    if (deg >= 3) {
+                        bas[9] = (-kC3a) * (y * (3.0f * xx - yy));
+                        bas[10] = kC3b * (xy * z);
+                        bas[11] = (-kC3c) * (y * ((4.0f * zz - xx) - yy));
+                        bas[12] = kC3d * (z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
+                        bas[13] = (-kC3c) * (x * ((4.0f * zz - xx) - yy));
+                        bas[14] = kC3e * (z * (xx - yy));
+                        bas[15] = (-kC3a) * (x * (xx - 3.0f * yy));
+                    }
+                }
+                const int K = (deg + 1) * (deg + 1);
+                const float* shp = sc.sh + (size_t)i * 3 * K;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    float acc = bas[0] * shp[ch];
+                    for (int k = 1; k < K; ++k) acc = acc + bas[k] * shp[3 * k + ch];
+                    acc = acc + 0.5f;
+                    if (!isfinite(acc)) ok = false;
+                    rgb[ch] = acc < 0.0f ? 0.0f : acc;
+                }
+            }
+        }
+    }
+    if (ok) {
+        g.x = mx; g.y = my; g.ca = ca; g.cb = cb; g.cc = cc; g.op = op;
+        g.s00 = Si[0][0]; g.s01 = Si[0][1]; g.s02 = Si[0][2]; g.s11 = Si[1][1]; g.s12 = Si[1][2]; g.s22 = Si[2][2];
+        g.w0 = w[0]; g.w1 = w[1]; g.w2 = w[2];
+        rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
+        out.xy[i] = make_float2(mx, my);
+        out.co[i] = make_float4(ca, cb, cc, op);
+        out.sw[3 * i] = make_float4(Si[0][0], Si[0][1], Si[0][2], Si[1][1]);
+        out.sw[3 * i + 1] = make_float4(Si[1][2], Si[2][2], w[0], w[1]);
+        out.sw[3 * i + 2] = make_float4(w[2], rgb[0], rgb[1], rgb[2]);
+        out.zd[i] = make_float2(pz, dist);
+        out.rect[i] = rc;
+    } else {
+        const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out.xy[i] = make_float2(0.0f, 0.0f);
+        out.co[i] = z4;
+        out.sw[3 * i] = z4;
+        out.sw[3 * i + 1] = z4;
+        out.sw[3 * i + 2] = z4;
+        out.zd[i] = make_float2(0.0f, 0.0f);
+        out.rect[i] = make_int4(0, 0, 0, 0);
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void tile_hull(const DevCam& cam, int tx, int ty, float& x0, float& x1, float& y0,
+                                          float& y1) {
+    x0 = (float)(tx * 16);
+    x1 = (float)min(tx * 16 + 15, cam.W - 1);
+    y0 = (float)(ty * 16);
+    y1 = (float)min(ty * 16 + 15, cam.H - 1);
+}
+
+__device__ __forceinline__ bool tile_kept(const Splat& g, const DevCam& cam, int tx, int ty, float2& xh) {
+    float x0, x1, y0, y1;
+    tile_hull(cam, tx, ty, x0, x1, y0, y1);
+    return keeps_block(g, x0, x1, y0, y1, xh);
+}
+
+struct PreArgs {
+    SceneArgs sc;
+    DevCam cam;
+    int mode, lb;
+    PreOut out;
+    uint32_t* touched;
+};
+
+// One lane per Gaussian.  Gaussians whose rectangle holds more than `lb`
+// tiles are counted in a second phase by the whole wavefront (Sec. 3.4,
+// load balancing), one Gaussian at a time, tiles spread over the lanes.
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = __lane_id();
+    Splat g;
+    int4 rc = make_int4(0, 0, -1, -1);
+    bool vis = false;
+    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, i, a.out, g, rc);
+    const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
+    const int area = vis ? wdt * hgt : 0;
+    uint32_t cnt = 0;
+    const bool deferred = vis && a.mode == kModeHier && area > a.lb;
+    if (vis && !deferred) {
+        if (a.mode == kModeGlobal) {
+            cnt = (uint32_t)area;
+        } else {
+            for (int ty = rc.y; ty <= rc.w; ++ty)
+                for (int tx = rc.x; tx <= rc.z; ++tx) {
+                    float2 xh;
+                    cnt += tile_kept(g, a.cam, tx, ty, xh) ? 1u : 0u;
+                }
+        }
+    }
+    uint64_t pend = __ballot(deferred);
+    while (pend) {
+        const int src = __builtin_ctzll(pend);
+        pend &= pend - 1;
+        Splat h;
+        h.x = __shfl(g.x, src); h.y = __shfl(g.y, src);
+        h.ca = __shfl(g.ca, src); h.cb = __shfl(g.cb, src); h.cc = __shfl(g.cc, src); h.op = __shfl(g.op, src);
+        const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
+        const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
+        uint32_t c = 0;
+        for (int k = lane; k < rarea; k += 64) {
+            float2 xh;
+            c += tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw, xh) ? 1u : 0u;
+        }
+        c = wave_reduce_add(c);
+        if (lane == src) cnt = c;
+    }
+    if (i < a.sc.n) a.touched[i] = cnt;
+}
+
+struct DupArgs {
+    DevCam cam;
+    int n, mode, lb;
+    const float2* xy;
+    const float4* co;
+    const float4* sw;
+    const float2* zd;
+    const int4* rect;
+    const uint32_t* touched;
+    const uint32_t* offsets;
+    uint64_t* keys;
+    uint32_t* vals;
+    uint32_t capacity;
+    int32_t* status;
+};
+
+__device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32_t tile, uint32_t dbits, uint32_t id) {
+    if (pos < a.capacity) {
+        a.keys[pos] = ((uint64_t)tile << 32) | (uint64_t)dbits;
+        a.vals[pos] = id;
+    } else {
+        atomicOr(a.status, 1);
+    }
+}
+
+// One lane per Gaussian: every kept tile of the rectangle becomes a key
+// (tile << 32 | depth bits), depth = t_opt along the ray through the tile's
+// maximum point (tile-depth adjustment, Sec. 3.4), or the view depth in the
+// global mode.  Large Gaussians go through the cooperative second phase with
+// ballot-compacted writes (App. B.4).
+__global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = __lane_id();
+    uint32_t cnt = 0;
+    if (i < a.n) cnt = a.touched[i];
+    Splat g;
+    int4 rc = make_int4(0, 0, -1, -1);
+    uint32_t off = 0;
+    float zdepth = 0.0f;
+    if (cnt > 0) {
+        g = load_splat(a.xy, a.co, a.sw, (uint32_t)i);
+        rc = a.rect[i];
+        off = a.offsets[i];
+        zdepth = a.zd[i].x;
+    }
+    const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
+    const int area = cnt > 0 ? wdt * hgt : 0;
+    const bool deferred = cnt > 0 && a.mode == kModeHier && area > a.lb;
+    if (cnt > 0 && !deferred) {
+        uint32_t k = 0;
+        for (int ty = rc.y; ty <= rc.w; ++ty)
+            for (int tx = rc.x; tx <= rc.z; ++tx) {
+                const uint32_t tile = (uint32_t)(ty * a.cam.tiles_x + tx);
+                if (a.mode == kModeGlobal) {
+                    put_entry(a, off + k, tile, depth_bits(zdepth), (uint32_t)i);
+                    ++k;
+                    continue;
+                }
+                float2 xh;
+                if (!tile_kept(g, a.cam, tx, ty, xh)) continue;
+                const float t = t_opt(g, cam_ray(a.cam, xh.x, xh.y));
+                put_entry(a, off + k, tile, depth_bits(t), (uint32_t)i);
+                ++k;
+            }
+    }
+    uint64_t pend = __ballot(deferred);
+    while (pend) {
+        const int src = __builtin_ctzll(pend);
+        pend &= pend - 1;
+        Splat h;
+        h.x = __shfl(g.x, src); h.y = __shfl(g.y, src);
+        h.ca = __shfl(g.ca, src); h.cb = __shfl(g.cb, src); h.cc = __shfl(g.cc, src); h.op = __shfl(g.op, src);
+        h.s00 = __shfl(g.s00, src); h.s01 = __shfl(g.s01, src); h.s02 = __shfl(g.s02, src);
+        h.s11 = __shfl(g.s11, src); h.s12 = __shfl(g.s12, src); h.s22 = __shfl(g.s22, src);
+        h.w0 = __shfl(g.w0, src); h.w1 = __shfl(g.w1, src); h.w2 = __shfl(g.w2, src);
+        const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
+        const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
+        uint32_t base = __shfl(off, src);
+        const uint32_t id = (uint32_t)__shfl(i, src);
+        for (int k0 = 0; k0 < rarea; k0 += 64) {
+            const int k = k0 + lane;
+            bool keep = false;
+            float t = 0.0f;
+            int tx = 0, ty = 0;
+            if (k < rarea) {
+                tx = rx0 + k % rw;
+                ty = ry0 + k / rw;
+                float2 xh;
+                keep = tile_kept(h, a.cam, tx, ty, xh);
+                if (keep) t = t_opt(h, cam_ray(a.cam, xh.x, xh.y));
+            }
+            const uint64_t m = __ballot(keep);
+            if (keep) put_entry(a, base + (uint32_t)__popcll(m & lanemask_lt()), (uint32_t)(ty * a.cam.tiles_x + tx),
+                                depth_bits(t), id);
+            base += (uint32_t)__popcll(m);
+        }
+    }
+}
+
+// ----- exclusive scan -----
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves, uint32_t& total) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds_waves[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) {
+        const uint32_t s = lds_waves[w];
+        if (w < wave) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, size_t n,
+                                                              uint32_t* __restrict__ partial) {
+    __shared__ uint32_t lw[kScanThreads / 64];
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const size_t j = base + (size_t)r * kScanThreads + threadIdx.x;
+        if (j < n) s += in[j];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, lw, tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the partial sums (64-bit running total).
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, size_t np, uint32_t* total_out,
+                                                        uint32_t clamp, int32_t* status) {
+    __shared__ uint32_t lw[16];
+    unsigned long long carry = 0;
+    for (size_t b0 = 0; b0 < np; b0 += blockDim.x) {
+        const size_t j = b0 + threadIdx.x;
+        const uint32_t v = j < np ? partial[j] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, lw, tot);
+        if (j < np) partial[j] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) {
+        if (carry > (unsigned long long)clamp) {
+            if (status) atomicOr(status, 1);
+            *total_out = clamp;
+        } else {
+            *total_out = (uint32_t)carry;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                            size_t n, const uint32_t* __restrict__ partial) {
+    __shared__ uint32_t lw[kScanThreads / 64];
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        v[r] = (base + r < n) ? in[base + r] : 0u;
+        s += v[r];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, lw, tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        if (base + r < n) out[base + r] = run;
+        run += v[r];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ n_ptr, uint32_t* ranges) {
+    const uint32_t n = *n_ptr;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = (uint32_t)(keys[i] >> 32);
+    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (size_t)t] = (uint32_t)i;
+    if (i + 1 == n || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(i + 1);
+}
+
+__global__ void k_probe_math(const float* a, const float* b, int n, float* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = a[i], y = b[i];
+    out[i] = x / y;
+    out[n + i] = sqrtf(x);
+    out[2 * n + i] = exp_cw(x);
+    out[3 * n + i] = x >= 1.0f ? ln_atanh(x) : 0.0f;
+    out[4 * n + i] = rintf(x);
+    out[5 * n + i] = x * y + x;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
+                             hipStream_t s) {
+    if (sc.n == 0) return hipSuccess;
+    PreArgs a;
+    a.sc = sc;
+    a.cam = cam;
+    a.mode = mode;
+    a.lb = lb;
+    a.out = PreOut{b.xy, b.co, b.sw, b.zd, b.rect};
+    a.touched = b.touched;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* partial, uint32_t* total,
+                       uint32_t clamp, int32_t* status, hipStream_t s) {
+    const size_t nb = scan_partial_len(n);
+    if (n == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, total, (size_t)1, 0u);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, total, clamp, status);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    DupArgs a;
+    a.cam = cam;
+    a.n = n;
+    a.mode = mode;
+    a.lb = lb;
+    a.xy = b.xy;
+    a.co = b.co;
+    a.sw = b.sw;
+    a.zd = b.zd;
+    a.rect = b.rect;
+    a.touched = b.touched;
+    a.offsets = b.offsets;
+    a.keys = b.keys[buf];
+    a.vals = b.vals[buf];
+    a.capacity = b.capacity;
+    a.status = status;
+    hipLaunchKernelGGL(k_duplicate, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
+                         hipStream_t s) {
+    hipError_t e = launch_fill_u32(ranges, (size_t)tiles * 2, 0u, s);
+    if (e != hipSuccess) return e;
+    if (cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, 256)), dim3(256), 0, s, keys, n_ptr, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_math(const float* a, const float* b, int n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_math, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

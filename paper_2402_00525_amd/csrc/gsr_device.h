@@ -1,0 +1,181 @@
+// Device arithmetic of the gfx950 rasterizer: exp/ln, ordered depth keys,
+// camera rays, t_opt, the 2D Gaussian exponent, Algorithm 1 and the culling
+// test.  Every floating-point expression is written in a fixed evaluation
+// order and the library is built with -ffp-contract=off, so results are plain
+// IEEE binary32 operations (division and square root correctly rounded).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+constexpr float kEpsO = 1.0f / 255.0f;   // opacity threshold eps_O (Sec. 3.4)
+constexpr float kTMin = 0.0001f;         // transmittance stop
+constexpr float kAlphaMax = 0.99f;       // alpha clamp
+constexpr uint64_t kInvalidKey = ~0ull;
+
+// Camera as handed to kernels.
+struct DevCam {
+    float R[9];
+    float t[3];
+    float o[3];
+    float fx, fy, cx, cy, znear, limx, limy;
+    int W, H, tiles_x, tiles_y;
+};
+
+__device__ __forceinline__ float sel_min(float a, float b) { return a < b ? a : b; }
+__device__ __forceinline__ float sel_max(float a, float b) { return a > b ? a : b; }
+__device__ __forceinline__ float sel_clamp(float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// e^x: x = k ln2 + r with k = rint(x log2 e) (Cody & Waite reduction, ln 2 in
+// a 16-bit head and a tail), e^r by its Taylor series to degree 7 in Horner
+// form with fused multiply-adds, result scaled by 2^k.  Below -80 (or NaN): 0.
+__device__ __forceinline__ float exp_cw(float x) {
+    if (!(x >= -80.0f)) return 0.0f;
+    const float k = rintf(x * 1.44269504088896341f);
+    float r = fmaf(-k, 0.693145751953125f, x);
+    r = fmaf(-k, 1.42860676533018e-06f, r);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    return ldexpf(p, (int)k);
+}
+
+// ln x for x >= 1: x = m 2^e, m in [1/sqrt 2, sqrt 2), ln m = 2 atanh((m-1)/(m+1))
+// by its odd series through the 11th power.
+__device__ __forceinline__ float ln_atanh(float x) {
+    int e;
+    float m = frexpf(x, &e);
+    if (m < 0.70710678f) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float z = s * s;
+    float p = 1.0f / 11.0f;
+    p = fmaf(p, z, 1.0f / 9.0f);
+    p = fmaf(p, z, 1.0f / 7.0f);
+    p = fmaf(p, z, 1.0f / 5.0f);
+    p = fmaf(p, z, 1.0f / 3.0f);
+    p = fmaf(p, z, 1.0f);
+    const float lnm = (2.0f * s) * p;
+    return fmaf((float)e, 0.693147180559945309f, lnm);
+}
+
+// Unsigned image of a float that orders like the float ('-0' before '+0').
+__device__ __forceinline__ uint32_t depth_bits(float t) {
+    const uint32_t u = __float_as_uint(t);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float depth_from_bits(uint32_t b) {
+    return __uint_as_float((b & 0x80000000u) ? (b & 0x7fffffffu) : ~b);
+}
+
+// Unit world-space direction of the ray through image point (u, v).
+__device__ __forceinline__ float3 cam_ray(const DevCam& c, float u, float v) {
+    const float a = (u - c.cx) / c.fx;
+    const float b = (v - c.cy) / c.fy;
+    const float w0 = (c.R[0] * a + c.R[3] * b) + c.R[6];
+    const float w1 = (c.R[1] * a + c.R[4] * b) + c.R[7];
+    const float w2 = (c.R[2] * a + c.R[5] * b) + c.R[8];
+    const float len = sqrtf((w0 * w0 + w1 * w1) + w2 * w2);
+    return make_float3(w0 / len, w1 / len, w2 / len);
+}
+
+// The per-Gaussian data the render levels use: 2D mean, conic, opacity,
+// Sigma^-1 (6 unique entries) and w = Sigma^-1 (mu - o).
+struct Splat {
+    float x, y, ca, cb, cc, op;
+    float s00, s01, s02, s11, s12, s22, w0, w1, w2;
+};
+
+__device__ __forceinline__ Splat load_splat(const float2* __restrict__ xy, const float4* __restrict__ co,
+                                            const float4* __restrict__ sw, uint32_t id) {
+    Splat g;
+    const float2 m = xy[id];
+    const float4 c = co[id];
+    const float4 a = sw[3 * id];
+    const float4 b = sw[3 * id + 1];
+    const float4 e = sw[3 * id + 2];
+    g.x = m.x; g.y = m.y;
+    g.ca = c.x; g.cb = c.y; g.cc = c.z; g.op = c.w;
+    g.s00 = a.x; g.s01 = a.y; g.s02 = a.z; g.s11 = a.w;
+    g.s12 = b.x; g.s22 = b.y; g.w0 = b.z; g.w1 = b.w;
+    g.w2 = e.x;
+    return g;
+}
+
+// Depth of maximum contribution along unit direction d (Eq. dopt):
+// d^T Sigma^-1 (mu - o) / d^T Sigma^-1 d; a NaN quotient reads as +inf.
+__device__ __forceinline__ float t_opt(const Splat& g, float3 d) {
+    const float sd0 = (g.s00 * d.x + g.s01 * d.y) + g.s02 * d.z;
+    const float sd1 = (g.s01 * d.x + g.s11 * d.y) + g.s12 * d.z;
+    const float sd2 = (g.s02 * d.x + g.s12 * d.y) + g.s22 * d.z;
+    const float num = (d.x * g.w0 + d.y * g.w1) + d.z * g.w2;
+    const float den = (d.x * sd0 + d.y * sd1) + d.z * sd2;
+    const float t = num / den;
+    return (t != t) ? __int_as_float(0x7f800000) : t;
+}
+
+// Exponent of G_2 at (px, py): -1/2 (a dx^2 + c dy^2) - b dx dy with d = mu_2 - p.
+__device__ __forceinline__ float splat_power(const Splat& g, float px, float py) {
+    const float dx = g.x - px, dy = g.y - py;
+    return -0.5f * ((g.ca * dx) * dx + (g.cc * dy) * dy) - (g.cb * dx) * dy;
+}
+
+// Algorithm 1 (App. B.1): the point of box [x0,x1] x [y0,y1] where the 2D
+// Gaussian is largest, found on the two edges at the corner nearest the mean.
+__device__ __forceinline__ float2 box_max_point(const Splat& g, float x0, float x1, float y0, float y1) {
+    const float mx = g.x, my = g.y;
+    const bool in_x = (x0 <= mx && mx <= x1);
+    const bool in_y = (y0 <= my && my <= y1);
+    if (in_x && in_y) return make_float2(mx, my);
+    const float px = (mx < x0) ? x0 : ((mx > x1) ? x1 : ((mx - x0 <= x1 - mx) ? x0 : x1));
+    const float py = (my < y0) ? y0 : ((my > y1) ? y1 : ((my - y0 <= y1 - my) ? y0 : y1));
+    const float lx = ((px == x0) ? x1 : x0) - px;
+    const float ly = ((py == y0) ? y1 : y0) - py;
+    const float dx = mx - px, dy = my - py;
+    float tx = 0.0f, ty = 0.0f;
+    if (!in_x && ly != 0.0f) ty = sel_clamp((g.cb * dx + g.cc * dy) / (g.cc * ly), 0.0f, 1.0f);
+    if (!in_y && lx != 0.0f) tx = sel_clamp((g.ca * dx + g.cb * dy) / (g.ca * lx), 0.0f, 1.0f);
+    return make_float2(px + tx * lx, py + ty * ly);
+}
+
+// Exact culling: keep iff the maximum over the block clears eps_O.
+__device__ __forceinline__ bool keeps_block(const Splat& g, float x0, float x1, float y0, float y1, float2& xh) {
+    xh = box_max_point(g, x0, x1, y0, y1);
+    const float p = splat_power(g, xh.x, xh.y);
+    return p <= 0.0f && g.op * exp_cw(p) >= kEpsO;
+}
+
+// alpha at a pixel centre; false when the Gaussian is skipped there.
+__device__ __forceinline__ bool pixel_alpha(const Splat& g, float px, float py, float& alpha) {
+    const float p = splat_power(g, px, py);
+    if (p > 0.0f) return false;
+    const float a = g.op * exp_cw(p);
+    alpha = a < kAlphaMax ? a : kAlphaMax;
+    return !(alpha < kEpsO);
+}
+
+// ----- wavefront helpers (wave64) -----
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Orders this lane's LDS accesses against those of the other lanes of the
+// same wavefront (compiler barrier plus wait for outstanding LDS operations).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS traffic has landed
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace gsr

@@ -1,0 +1,96 @@
+// Internal launch interface shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsr_device.h"
+
+namespace gsr {
+
+enum { kModeGlobal = 0, kModeHier = 1 };
+
+// Device regions of one frame inside the caller's workspace.
+struct FrameBufs {
+    float2* xy;
+    float4* co;       // conic (a, b, c) + opacity
+    float4* sw;       // 3 float4 per Gaussian: Sigma^-1 (6), w (3), rgb (3)
+    float2* zd;       // view depth, |mu - o|
+    int4* rect;       // tile rectangle, inclusive
+    uint32_t* touched;
+    uint32_t* offsets;
+    uint32_t* scan_partial;   // scan scratch, >= scan_partial_len(max(n, hist)) + 2
+    uint64_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* hist;           // radix histograms, 256 x sort blocks
+    uint32_t* ranges;         // [tiles][2]
+    uint32_t* counters;       // [0] entries, [1] consumed by render, [2..3] spare
+    uint32_t capacity;
+};
+
+struct SceneArgs {
+    int n, deg;
+    const float* means;
+    const float* scales;
+    const float* rots;
+    const float* opac;
+    const float* sh;
+};
+
+// Scan tiles
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Radix sort tiles
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+
+inline size_t div_up(size_t a, size_t b) { return (a + b - 1) / b; }
+inline size_t scan_partial_len(size_t n) { return div_up(n, kScanTile); }
+inline size_t sort_blocks(size_t cap) { return div_up(cap, kSortTile); }
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
+                             hipStream_t s);
+// Exclusive scan of n uint32 values; the total (clamped to `clamp`) goes to
+// *total, and `status` gets the overflow bit if the total exceeds `clamp`.
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* partial, uint32_t* total,
+                       uint32_t clamp, int32_t* status, hipStream_t s);
+// Writes the unsorted entries into key/value buffer `buf`.
+hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
+                            hipStream_t s);
+// Stable LSD radix sort of the first counters[0] (key, value) pairs on the
+// low `bits` key bits; returns the buffer index (0/1) holding the result.
+hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s);
+hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
+                         hipStream_t s);
+
+struct RenderArgs {
+    DevCam cam;
+    uint32_t n;   // number of Gaussians (ids are checked against it)
+    const float2* xy;
+    const float4* co;
+    const float4* sw;
+    const float2* zd;
+    const uint32_t* vals;
+    const uint32_t* ranges;
+    uint32_t* counters;
+    float* rgb;
+    float* depth;
+    int32_t* count;
+    float* T;
+    int32_t* blend_ids;
+    int max_k;
+    float bg0, bg1, bg2;
+};
+
+hipError_t launch_render_global(const RenderArgs& a, hipStream_t s);
+bool hier_head_supported(int head);
+// Hierarchical render with head capacity `head` (1..24).
+hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s);
+
+hipError_t launch_probe_math(const float* a, const float* b, int n, float* out, hipStream_t s);
+
+}  // namespace gsr

@@ -1,0 +1,511 @@
+// Render kernels.
+//
+// k_render_hier: the hierarchical per-pixel resorting of Sec. 3.4 on wave64.
+// One workgroup of 256 lanes renders one 16x16 tile; every wavefront owns a
+// 16x4 strip of four 4x4 sub-tiles and never synchronises with the other
+// wavefronts.  Inside a wavefront:
+//   * a 16-lane row owns one 4x4 sub-tile and its tail queue (LDS, 64
+//     entries); every batch of 32 list entries is culled against the
+//     sub-tile (Algorithm 1), keyed by t_opt along the sub-tile's centre ray,
+//     ranked, and merged into the tail; while the tail holds more than 32,
+//     its front 16 go to the mid level;
+//   * a 4-lane quad owns one 2x2 block and its mid queue (LDS, 8 entries);
+//     sub-batches of 4 are culled against the block, keyed along the block's
+//     centre ray, ranked with quad shuffles and merged; while the mid queue
+//     holds more than 4, its front 4 go to the heads;
+//   * every lane owns one pixel and its head queue (registers, K entries);
+//     an entry is inserted by (t_opt along the pixel ray, list rank) and the
+//     front is blended front to back whenever the head holds more than K.
+// Queue keys are (depth bits << 32 | rank in the tile list), a total order,
+// so every sort and merge has one result.
+//
+// k_render_global: the 3DGS order -- each pixel blends its tile's list in
+// key order.
+#include "gsr_internal.h"
+
+namespace gsr {
+
+namespace {
+
+constexpr int kBatch = 32;
+constexpr int kTailCap = 64;
+constexpr int kPop = 16;
+constexpr int kMidCap = 8;
+constexpr int kMidBatch = 4;
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Number of entries of sorted arr[0..n) below key.
+__device__ __forceinline__ int count_below(const uint64_t* arr, int n, uint64_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (arr[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+struct WaveQueues {
+    uint64_t tkey[2][4][kTailCap];
+    uint32_t tid[2][4][kTailCap];
+    uint64_t nkey[4][kBatch];
+    uint32_t nid[4][kBatch];
+    uint64_t skey[4][kBatch];
+    uint32_t sid[4][kBatch];
+    uint64_t mkey[2][16][kMidCap];
+    uint32_t mid[2][16][kMidCap];
+};
+
+template <int K, bool DEBUG>
+struct PixelState {
+    float T, C0, C1, C2, D;
+    int n;
+    bool done;
+    uint64_t hk[K + 1];
+    uint32_t hid[K + 1];
+    float ha[K + 1];
+    int hn;
+};
+
+template <int K, bool DEBUG>
+__device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, DEBUG>& s, int pix, uint32_t id,
+                                          float alpha, float t) {
+    if (s.done) return;
+    const float Tn = s.T * (1.0f - alpha);
+    if (Tn < kTMin) {
+        s.done = true;
+        return;
+    }
+    const float4 e = a.sw[3 * id + 2];
+    s.C0 = s.C0 + (e.y * alpha) * s.T;
+    s.C1 = s.C1 + (e.z * alpha) * s.T;
+    s.C2 = s.C2 + (e.w * alpha) * s.T;
+    s.D = s.D + (t * alpha) * s.T;
+    if (DEBUG) {
+        if (s.n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + s.n] = (int32_t)id;
+    }
+    s.n += 1;
+    s.T = Tn;
+}
+
+// Remove the front of the head and blend it.
+template <int K, bool DEBUG>
+__device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, DEBUG>& s, int pix) {
+    const uint64_t k0 = s.hk[0];
+    const uint32_t i0 = s.hid[0];
+    const float a0 = s.ha[0];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        s.hk[i] = s.hk[i + 1];
+        s.hid[i] = s.hid[i + 1];
+        s.ha[i] = s.ha[i + 1];
+    }
+    s.hn -= 1;
+    blend_one<K, DEBUG>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)));
+}
+
+// Insertion into the sorted head (s.hn < K + 1 on entry).
+template <int K, bool DEBUG>
+__device__ __forceinline__ void head_insert(PixelState<K, DEBUG>& s, uint64_t key, uint32_t id, float alpha) {
+    int pos = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) pos += (i < s.hn && s.hk[i] < key) ? 1 : 0;
+#pragma unroll
+    for (int i = K; i >= 1; --i) {
+        if (i > pos && i <= s.hn) {
+            s.hk[i] = s.hk[i - 1];
+            s.hid[i] = s.hid[i - 1];
+            s.ha[i] = s.ha[i - 1];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        if (i == pos) {
+            s.hk[i] = key;
+            s.hid[i] = id;
+            s.ha[i] = alpha;
+        }
+    }
+    s.hn += 1;
+}
+
+template <int K, bool DEBUG>
+struct HierCtx {
+    const RenderArgs& a;
+    WaveQueues& q;
+    int row, j, quad, pl, gq, lane;
+    int px, py, pix;
+    bool quad_ok, pix_ok;
+    float Q0, Q1, Q2, Q3;
+    float3 dQ, dP;
+    // mid queue state (uniform over the quad)
+    int mb, ms, mn;
+    PixelState<K, DEBUG> st;
+
+    __device__ HierCtx(const RenderArgs& a_, WaveQueues& q_) : a(a_), q(q_) {}
+
+    // Head level: the c entries of this quad's mid buffer from position ms0.
+    __device__ void push_head(int c, int ms0) {
+        for (int e = 0; e < c; ++e) {
+            const uint64_t mk = q.mkey[mb][gq][ms0 + e];
+            uint32_t id = q.mid[mb][gq][ms0 + e];
+            id = id < a.n ? id : 0u;
+            if (!st.done && pix_ok) {
+                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                float alpha;
+                if (pixel_alpha(g, (float)px, (float)py, alpha)) {
+                    const float t = t_opt(g, dP);
+                    head_insert<K, DEBUG>(st, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha);
+                    if (st.hn > K) head_pop_blend<K, DEBUG>(a, st, pix);
+                }
+            }
+        }
+    }
+
+    // Mid level: a chunk of cl tail entries of row `row` (buffer tb, from cs).
+    __device__ void push_mid(int tb, int cs, int cl) {
+        if (!quad_ok) return;
+        const int qbase = lane & ~3;
+        for (int r0 = 0; r0 < cl; r0 += kMidBatch) {
+            const int idx = r0 + pl;
+            uint64_t key = kInvalidKey;
+            uint32_t id = 0;
+            if (idx < cl) {
+                const uint64_t tk = q.tkey[tb][row][cs + idx];
+                id = q.tid[tb][row][cs + idx];
+                id = id < a.n ? id : 0u;
+                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                float2 xh;
+                if (keeps_block(g, Q0, Q1, Q2, Q3, xh))
+                    key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
+            }
+            uint64_t qk[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) qk[m] = shfl_u64(key, qbase + m);
+            int rnk = 0, nnew = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                rnk += qk[m] < key ? 1 : 0;
+                nnew += qk[m] != kInvalidKey ? 1 : 0;
+            }
+            const int ob = mb ^ 1;
+            if (pl < mn) {
+                const uint64_t ek = q.mkey[mb][gq][ms + pl];
+                const uint32_t eid = q.mid[mb][gq][ms + pl];
+                int c = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) c += qk[m] < ek ? 1 : 0;
+                q.mkey[ob][gq][pl + c] = ek;
+                q.mid[ob][gq][pl + c] = eid;
+            }
+            if (key != kInvalidKey) {
+                int c = 0;
+                for (int m = 0; m < mn; ++m) c += q.mkey[mb][gq][ms + m] < key ? 1 : 0;
+                q.mkey[ob][gq][rnk + c] = key;
+                q.mid[ob][gq][rnk + c] = id;
+            }
+            wave_lds_sync();
+            mb = ob;
+            ms = 0;
+            mn += nnew;
+            while (mn > kMidCap - kMidBatch) {
+                push_head(kMidBatch, ms);
+                ms += kMidBatch;
+                mn -= kMidBatch;
+            }
+        }
+    }
+};
+
+template <int K, bool DEBUG>
+__global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
+    __shared__ WaveQueues s_q[4];
+    __shared__ uint32_t s_consumed[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const DevCam& cam = a.cam;
+    const int tile = blockIdx.x;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    WaveQueues& q = s_q[wave];
+    HierCtx<K, DEBUG> h(a, q);
+    h.lane = lane;
+    h.row = lane >> 4;
+    h.j = lane & 15;
+    h.quad = h.j >> 2;
+    h.pl = h.j & 3;
+    h.gq = h.row * 4 + h.quad;
+    const int sx0 = tx * 16 + h.row * 4, sy0 = ty * 16 + wave * 4;
+    const int qx0 = sx0 + 2 * (h.quad & 1), qy0 = sy0 + 2 * (h.quad >> 1);
+    h.px = qx0 + (h.pl & 1);
+    h.py = qy0 + (h.pl >> 1);
+    const bool sub_ok = sx0 < cam.W && sy0 < cam.H;
+    h.quad_ok = qx0 < cam.W && qy0 < cam.H;
+    h.pix_ok = h.px < cam.W && h.py < cam.H;
+    h.pix = h.py * cam.W + h.px;
+    const float S0 = (float)sx0, S1 = (float)min(sx0 + 3, cam.W - 1);
+    const float S2 = (float)sy0, S3 = (float)min(sy0 + 3, cam.H - 1);
+    h.Q0 = (float)qx0;
+    h.Q1 = (float)min(qx0 + 1, cam.W - 1);
+    h.Q2 = (float)qy0;
+    h.Q3 = (float)min(qy0 + 1, cam.H - 1);
+    const float3 dS = cam_ray(cam, 0.5f * (S0 + S1), 0.5f * (S2 + S3));
+    h.dQ = cam_ray(cam, 0.5f * (h.Q0 + h.Q1), 0.5f * (h.Q2 + h.Q3));
+    h.dP = cam_ray(cam, (float)h.px, (float)h.py);
+    h.st.T = 1.0f;
+    h.st.C0 = h.st.C1 = h.st.C2 = h.st.D = 0.0f;
+    h.st.n = 0;
+    h.st.done = !h.pix_ok;
+    h.st.hn = 0;
+#pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        h.st.hk[i] = kInvalidKey;
+        h.st.hid[i] = 0;
+        h.st.ha[i] = 0.0f;
+    }
+    h.mb = 0;
+    h.ms = 0;
+    h.mn = 0;
+    int tb = 0, ts = 0, tn = 0;  // tail state, uniform over the row
+    const int row = h.row, j = h.j;
+
+    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    uint32_t b0 = begin;
+    for (; b0 < end; b0 += kBatch) {
+        const uint64_t live = __ballot(!h.st.done);
+        if (live == 0) break;
+        const bool row_live = sub_ok && ((live >> (row * 16)) & 0xffffull) != 0;
+        if (!row_live) continue;
+        // Cull against the sub-tile and key along its centre ray.
+        uint64_t k2[2] = {kInvalidKey, kInvalidKey};
+        uint32_t i2[2] = {0, 0};
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const uint32_t e = b0 + (uint32_t)(j + 16 * hh);
+            if (e < end) {
+                uint32_t id = a.vals[e];
+                id = id < a.n ? id : 0u;
+                i2[hh] = id;
+                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                float2 xh;
+                if (keeps_block(g, S0, S1, S2, S3, xh))
+                    k2[hh] = ((uint64_t)depth_bits(t_opt(g, dS)) << 32) | (uint64_t)(e - begin);
+            }
+            q.nkey[row][j + 16 * hh] = k2[hh];
+            q.nid[row][j + 16 * hh] = i2[hh];
+        }
+        const uint64_t v0 = __ballot(k2[0] != kInvalidKey), v1 = __ballot(k2[1] != kInvalidKey);
+        const int nv = __popcll((v0 >> (row * 16)) & 0xffffull) + __popcll((v1 >> (row * 16)) & 0xffffull);
+        wave_lds_sync();
+        // Rank within the batch, then scatter into sorted order.
+        int r2[2] = {0, 0};
+        for (int m = 0; m < kBatch; ++m) {
+            const uint64_t km = q.nkey[row][m];
+            r2[0] += km < k2[0] ? 1 : 0;
+            r2[1] += km < k2[1] ? 1 : 0;
+        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+            if (k2[hh] != kInvalidKey) {
+                q.skey[row][r2[hh]] = k2[hh];
+                q.sid[row][r2[hh]] = i2[hh];
+            }
+        wave_lds_sync();
+        // Merge with the tail (both sorted, keys distinct) into the other buffer.
+        const int ob = tb ^ 1;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int idx = j + 16 * hh;
+            if (idx < tn) {
+                const uint64_t ek = q.tkey[tb][row][ts + idx];
+                const uint32_t eid = q.tid[tb][row][ts + idx];
+                const int pos = idx + count_below(q.skey[row], nv, ek);
+                q.tkey[ob][row][pos] = ek;
+                q.tid[ob][row][pos] = eid;
+            }
+            if (k2[hh] != kInvalidKey) {
+                const int pos = r2[hh] + count_below(&q.tkey[tb][row][ts], tn, k2[hh]);
+                q.tkey[ob][row][pos] = k2[hh];
+                q.tid[ob][row][pos] = i2[hh];
+            }
+        }
+        wave_lds_sync();
+        tb = ob;
+        ts = 0;
+        tn += nv;
+        while (tn > kTailCap - kBatch) {
+            h.push_mid(tb, ts, kPop);
+            ts += kPop;
+            tn -= kPop;
+        }
+    }
+    // Drain: the tail in chunks, then the mid queues, then the heads.
+    {
+        const uint64_t live = __ballot(!h.st.done);
+        const bool row_live = sub_ok && ((live >> (row * 16)) & 0xffffull) != 0;
+        if (row_live) {
+            while (tn > 0) {
+                const int c = tn < kPop ? tn : kPop;
+                h.push_mid(tb, ts, c);
+                ts += c;
+                tn -= c;
+            }
+            if (h.quad_ok) {
+                while (h.mn > 0) {
+                    const int c = h.mn < kMidBatch ? h.mn : kMidBatch;
+                    h.push_head(c, h.ms);
+                    h.ms += c;
+                    h.mn -= c;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i <= K; ++i)
+                if (h.st.hn > 0) head_pop_blend<K, DEBUG>(a, h.st, h.pix);
+        }
+    }
+    if (h.pix_ok) {
+        const size_t P = (size_t)cam.W * cam.H;
+        const size_t p = (size_t)h.pix;
+        a.rgb[p] = h.st.C0 + h.st.T * a.bg0;
+        a.rgb[P + p] = h.st.C1 + h.st.T * a.bg1;
+        a.rgb[2 * P + p] = h.st.C2 + h.st.T * a.bg2;
+        a.depth[p] = h.st.D;
+        a.count[p] = h.st.n;
+        a.T[p] = h.st.T;
+        if (DEBUG)
+            for (int k = h.st.n; k < a.max_k; ++k) a.blend_ids[p * a.max_k + k] = -1;
+    }
+    if (lane == 0) s_consumed[wave] = (b0 < end ? b0 : end) - begin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = s_consumed[0];
+        for (int w = 1; w < 4; ++w) c = s_consumed[w] > c ? s_consumed[w] : c;
+        if (c) atomicAdd(a.counters + 1, c);
+    }
+}
+
+template <bool DEBUG>
+__global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
+    __shared__ float2 s_xy[256];
+    __shared__ float4 s_co[256];
+    __shared__ float4 s_cd[256];
+    __shared__ uint32_t s_id[256];
+    const DevCam& cam = a.cam;
+    const int tile = blockIdx.x;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const int pix = py * cam.W + px;
+    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
+    int n = 0;
+    bool done = !inside;
+    uint32_t consumed = 0;
+    for (uint32_t start = begin; start < end; start += 256) {
+        if (__syncthreads_count(done ? 1 : 0) == 256) break;
+        const uint32_t idx = start + threadIdx.x;
+        if (idx < end) {
+            uint32_t id = a.vals[idx];
+            id = id < a.n ? id : 0u;
+            s_id[threadIdx.x] = id;
+            s_xy[threadIdx.x] = a.xy[id];
+            s_co[threadIdx.x] = a.co[id];
+            const float4 e = a.sw[3 * id + 2];
+            s_cd[threadIdx.x] = make_float4(e.y, e.z, e.w, a.zd[id].y);
+        }
+        __syncthreads();
+        const uint32_t cnt = (end - start) < 256u ? (end - start) : 256u;
+        consumed += cnt;
+        for (uint32_t k = 0; k < cnt && !done; ++k) {
+            Splat g;
+            g.x = s_xy[k].x;
+            g.y = s_xy[k].y;
+            const float4 c = s_co[k];
+            g.ca = c.x;
+            g.cb = c.y;
+            g.cc = c.z;
+            g.op = c.w;
+            float alpha;
+            if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
+            const float Tn = T * (1.0f - alpha);
+            if (Tn < kTMin) {
+                done = true;
+                break;
+            }
+            const float4 cd = s_cd[k];
+            C0 = C0 + (cd.x * alpha) * T;
+            C1 = C1 + (cd.y * alpha) * T;
+            C2 = C2 + (cd.z * alpha) * T;
+            D = D + (cd.w * alpha) * T;
+            if (DEBUG && n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + n] = (int32_t)s_id[k];
+            n += 1;
+            T = Tn;
+        }
+        __syncthreads();
+    }
+    if (inside) {
+        const size_t P = (size_t)cam.W * cam.H;
+        a.rgb[pix] = C0 + T * a.bg0;
+        a.rgb[P + pix] = C1 + T * a.bg1;
+        a.rgb[2 * P + pix] = C2 + T * a.bg2;
+        a.depth[pix] = D;
+        a.count[pix] = n;
+        a.T[pix] = T;
+        if (DEBUG)
+            for (int k = n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+    }
+    if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
+}
+
+template <int K>
+hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
+    const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
+    if (a.blend_ids)
+        hipLaunchKernelGGL((k_render_hier<K, true>), dim3(tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_render_hier<K, false>), dim3(tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool hier_head_supported(int head) {
+    switch (head) {
+        case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 20: case 24:
+            return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s) {
+    switch (head) {
+        case 1: return launch_hier_k<1>(a, s);
+        case 2: return launch_hier_k<2>(a, s);
+        case 3: return launch_hier_k<3>(a, s);
+        case 4: return launch_hier_k<4>(a, s);
+        case 6: return launch_hier_k<6>(a, s);
+        case 8: return launch_hier_k<8>(a, s);
+        case 12: return launch_hier_k<12>(a, s);
+        case 16: return launch_hier_k<16>(a, s);
+        case 20: return launch_hier_k<20>(a, s);
+        case 24: return launch_hier_k<24>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_render_global(const RenderArgs& a, hipStream_t s) {
+    const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
+    if (a.blend_ids)
+        hipLaunchKernelGGL(k_render_global<true>, dim3(tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_render_global<false>, dim3(tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -1,0 +1,281 @@
+"""Python binding of ``libgsr.so`` (the C ABI declared in ``include/gsr.h``).
+
+Argument marshalling only: every step of a frame runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  If the
+library is missing the binding raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsr.so")
+
+GSR_OK, GSR_EINVAL, GSR_ECAPACITY, GSR_EDEVICE, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4
+MODE_GLOBAL, MODE_HIER = 0, 1
+STATUS_OVERFLOW = 1
+
+
+class GsrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gsr error %d: %s" % (code, msg))
+        self.code = code
+
+
+class CScene(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("means", C.c_void_p), ("scales", C.c_void_p),
+                ("rots", C.c_void_p), ("opacities", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class CCamera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("center", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float), ("znear", C.c_float),
+                ("W", C.c_int32), ("H", C.c_int32)]
+
+
+class CConfig(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("batch", C.c_int32), ("tail", C.c_int32), ("pop", C.c_int32),
+                ("mid", C.c_int32), ("mid_batch", C.c_int32), ("head", C.c_int32), ("lb_threshold", C.c_int32),
+                ("bg", C.c_float * 3), ("flags", C.c_uint32)]
+
+
+class CLayout(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in
+                ("xy", "conic_o", "sw", "zd", "rect", "touched", "offsets", "keys", "values", "ranges",
+                 "counters", "entry_capacity", "total_bytes")]
+
+
+_lib = None
+
+EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
+           "gsr_render", "gsr_render_debug", "gsr_render_staged", "gsr_probe_math", "gsr_last_error",
+           "gsr_version")
+
+
+def lib():
+    """Load ``libgsr.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgsr.so is not built; run python -m paper_2402_00525_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.gsr_workspace_bytes.restype = C.c_size_t
+        L.gsr_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int64]
+        L.gsr_workspace_layout.restype = C.c_int
+        L.gsr_workspace_layout.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_size_t, C.POINTER(CLayout)]
+        L.gsr_default_config.argtypes = [C.POINTER(CConfig)]
+        L.gsr_check_config.argtypes = [C.POINTER(CConfig)]
+        L.gsr_check_config.restype = C.c_int
+        L.gsr_render.restype = C.c_int
+        L.gsr_render.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p, C.c_size_t,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gsr_render_debug.restype = C.c_int
+        L.gsr_render_debug.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
+                                       C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int32, C.c_void_p, C.c_void_p]
+        L.gsr_render_staged.restype = C.c_int
+        L.gsr_render_staged.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
+                                        C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
+        L.gsr_probe_math.restype = C.c_int
+        L.gsr_probe_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.gsr_last_error.restype = C.c_char_p
+        L.gsr_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != GSR_OK:
+        raise GsrError(rc, lib().gsr_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0)) -> CConfig:
+    c = CConfig()
+    lib().gsr_default_config(C.byref(c))
+    c.mode, c.head, c.lb_threshold = mode, head, lb_threshold
+    for i in range(3):
+        c.bg[i] = bg[i]
+    return c
+
+
+def camera(cam) -> CCamera:
+    """Convert any object with R, t, center, fx, fy, cx, cy, W, H, znear."""
+    c = CCamera()
+    R = [float(v) for v in cam.R.reshape(-1)]
+    for i in range(9):
+        c.R[i] = R[i]
+    for i in range(3):
+        c.t[i] = float(cam.t[i])
+        c.center[i] = float(cam.center[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.znear = float(getattr(cam, "znear", 0.2))
+    c.W, c.H = int(cam.W), int(cam.H)
+    return c
+
+
+@dataclass
+class DeviceScene:
+    """Gaussian parameters resident on the GPU (float32, contiguous)."""
+    means: torch.Tensor
+    scales: torch.Tensor
+    rots: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_host(scene, device="cuda") -> "DeviceScene":
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        return DeviceScene(f(scene.means), f(scene.scales), f(scene.rots), f(scene.opacities), f(scene.sh),
+                           int(scene.sh_degree))
+
+    def c_struct(self) -> CScene:
+        s = CScene()
+        s.n, s.sh_degree = self.n, self.sh_degree
+        s.means, s.scales, s.rots = self.means.data_ptr(), self.scales.data_ptr(), self.rots.data_ptr()
+        s.opacities, s.sh = self.opacities.data_ptr(), self.sh.data_ptr()
+        return s
+
+
+def workspace_bytes(n, W, H, entries_max) -> int:
+    b = lib().gsr_workspace_bytes(n, W, H, entries_max)
+    if b == 0:
+        raise GsrError(GSR_EINVAL, "bad workspace request")
+    return int(b)
+
+
+def layout(n, W, H, ws_bytes) -> CLayout:
+    L = CLayout()
+    _check(lib().gsr_workspace_layout(n, W, H, ws_bytes, C.byref(L)))
+    return L
+
+
+class Frame:
+    """Outputs of one render plus a view of the workspace it used."""
+
+    def __init__(self, H, W, device, max_k=0):
+        self.rgb = torch.empty((3, H, W), dtype=torch.float32, device=device)
+        self.depth = torch.empty((H, W), dtype=torch.float32, device=device)
+        self.count = torch.empty((H, W), dtype=torch.int32, device=device)
+        self.T = torch.empty((H, W), dtype=torch.float32, device=device)
+        self.blend_ids = torch.empty((H, W, max_k), dtype=torch.int32, device=device) if max_k > 0 else None
+
+
+class Renderer:
+    """Holds a workspace and renders frames into it.
+
+    ``render`` checks the device status word after the frame (one host
+    synchronisation) and grows the workspace when the tile entries overflowed;
+    ``render_async`` enqueues without any host synchronisation.
+    """
+
+    def __init__(self, device="cuda", entries_hint: int = 1 << 20):
+        self.device = torch.device(device)
+        self.entries_hint = int(entries_hint)
+        self.ws = None
+        self.ws_key = None
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    def plan(self, n, W, H, entries):
+        nbytes = workspace_bytes(n, W, H, max(1, int(entries)))
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ws_key = (n, W, H)
+        return self.ws
+
+    def render_async(self, scene: DeviceScene, cam, cfg: CConfig, out: Frame, max_k: int = 0, events=None):
+        """Enqueue one frame.  ``events``: optional ctypes array of five
+        hipEvent_t handles recorded at the stage boundaries."""
+        if self.ws is None:
+            self.plan(scene.n, cam.W, cam.H, self.entries_hint)
+        sc, cc = scene.c_struct(), camera(cam)
+        if events is not None:
+            rc = lib().gsr_render_staged(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
+                                         _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T),
+                                         _ptr(self.status), _stream(), events)
+        elif max_k > 0:
+            rc = lib().gsr_render_debug(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
+                                        _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T),
+                                        _ptr(out.blend_ids), max_k, _ptr(self.status), _stream())
+        else:
+            rc = lib().gsr_render(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
+                                  _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T), _ptr(self.status),
+                                  _stream())
+        _check(rc)
+        return out
+
+    def render(self, scene: DeviceScene, cam, cfg: CConfig | None = None, max_k: int = 0) -> Frame:
+        cfg = cfg or config()
+        out = Frame(cam.H, cam.W, self.device, max_k)
+        if self.ws is None:
+            self.plan(scene.n, cam.W, cam.H, self.entries_hint)
+        for _ in range(4):
+            self.status.zero_()
+            self.render_async(scene, cam, cfg, out, max_k)
+            st = int(self.status.item())
+            if not (st & STATUS_OVERFLOW):
+                return out
+            need = int(self.counter(scene.n, cam, 0, raw_total=True))
+            self.plan(scene.n, cam.W, cam.H, max(2 * need, 2 * self.capacity(scene.n, cam)))
+        raise GsrError(GSR_ECAPACITY, "tile entries keep overflowing the workspace")
+
+    # ----- workspace inspection (debugging / tests) -----
+    def capacity(self, n, cam) -> int:
+        return int(layout(n, cam.W, cam.H, self.ws.numel()).entry_capacity)
+
+    def region(self, n, cam, name, dtype, count):
+        L = layout(n, cam.W, cam.H, self.ws.numel())
+        off = getattr(L, name)
+        nbytes = count * torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype)
+
+    def counter(self, n, cam, k, raw_total=False):
+        c = self.region(n, cam, "counters", torch.int32, 4)
+        if raw_total:
+            # entries needed = sum of per-Gaussian counts (the clamped total may be smaller)
+            t = self.region(n, cam, "touched", torch.int32, n)
+            return int(t.to(torch.int64).sum().item())
+        return int(c[k].item())
+
+    def records(self, n, cam):
+        """Per-Gaussian records of the last frame (device tensors)."""
+        return dict(
+            xy=self.region(n, cam, "xy", torch.float32, 2 * n).view(n, 2),
+            conic_o=self.region(n, cam, "conic_o", torch.float32, 4 * n).view(n, 4),
+            sw=self.region(n, cam, "sw", torch.float32, 12 * n).view(n, 12),
+            zd=self.region(n, cam, "zd", torch.float32, 2 * n).view(n, 2),
+            rect=self.region(n, cam, "rect", torch.int32, 4 * n).view(n, 4),
+            touched=self.region(n, cam, "touched", torch.int32, n),
+        )
+
+    def sorted_entries(self, n, cam):
+        E = self.counter(n, cam, 0)
+        keys = self.region(n, cam, "keys", torch.int64, E)
+        vals = self.region(n, cam, "values", torch.int32, E)
+        tiles = ((cam.W + 15) // 16) * ((cam.H + 15) // 16)
+        ranges = self.region(n, cam, "ranges", torch.int32, 2 * tiles).view(tiles, 2)
+        return keys, vals, ranges
+
+
+def probe_math(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    n = a.numel()
+    out = torch.empty(6 * n, dtype=torch.float32, device=a.device)
+    _check(lib().gsr_probe_math(_ptr(a), _ptr(b), n, _ptr(out), _stream()))
+    return out.view(6, n)

@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every function the header declares, and
+its host-only entry points (workspace planning, configuration checks) behave
+as documented.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsr.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2402_00525_amd import gsr
+    if not os.path.exists(gsr.LIB_PATH):
+        from paper_2402_00525_amd import build
+        build.build()
+    return gsr
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(L):
+    names = declared_functions()
+    assert "gsr_render" in names and len(names) >= 8
+    lib = C.CDLL(L.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) <= set(names)
+
+
+def test_version_and_default_config(L):
+    assert b"gfx950" in L.lib().gsr_version()
+    c = L.config()
+    assert (c.mode, c.batch, c.tail, c.pop, c.mid, c.mid_batch, c.head, c.lb_threshold) == (1, 32, 64, 16, 8, 4, 4, 32)
+    assert L.lib().gsr_check_config(C.byref(c)) == 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tail", 48, -1), ("tail", 96, -4), ("mid", 6, -1), ("mid", 12, -4), ("head", 0, -1), ("head", 25, -4),
+    ("mode", 7, -1), ("flags", 1, -1), ("lb_threshold", -1, -1)])
+def test_config_validation(L, field, value, code):
+    # Sec. 3.4: tail = 32n+32, mid = 4m+4, head >= 1; only the built sizes run.
+    c = L.config()
+    setattr(c, field, value)
+    assert L.lib().gsr_check_config(C.byref(c)) == code
+    assert len(L.lib().gsr_last_error()) > 0
+
+
+def test_workspace_planning_roundtrip(L):
+    for n, W, H, E in [(2000, 128, 128, 10000), (1_000_000, 1920, 1080, 30_000_000), (0, 16, 16, 1), (5, 1, 1, 7)]:
+        nbytes = L.workspace_bytes(n, W, H, E)
+        lay = L.layout(n, W, H, nbytes)
+        assert lay.entry_capacity >= E
+        assert lay.total_bytes <= nbytes
+        offs = sorted([lay.xy, lay.conic_o, lay.sw, lay.zd, lay.rect, lay.touched, lay.offsets, lay.keys,
+                       lay.values, lay.ranges, lay.counters])
+        assert all(o % 256 == 0 for o in offs)
+        assert len(set(offs)) == len(offs) or n == 0
+
+
+def test_workspace_errors(L):
+    assert L.lib().gsr_workspace_bytes(-1, 16, 16, 10) == 0
+    assert L.lib().gsr_workspace_bytes(10, 0, 16, 10) == 0
+    with pytest.raises(L.GsrError) as e:
+        L.layout(1000, 64, 64, 1024)
+    assert e.value.code == L.GSR_ECAPACITY

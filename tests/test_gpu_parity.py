@@ -1,0 +1,150 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact: per-Gaussian records, tile counts, sorted (tile, depth) keys and
+Gaussian ids, tile ranges, per-pixel blend counts and blend order.  Images:
+within 1e-4 absolute per float32 channel (the arithmetic is specified to be
+identical, so they are expected to match exactly; the bound is the contract).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2402_00525_amd import synth
+
+from gpu_util import (assert_images_close, assert_records_equal, assert_sorted_equal, gpu_frame, say)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup(oracle_lib):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_00525_amd import gsr
+    gsr.lib()
+    return oracle_lib
+
+
+def test_device_arithmetic_matches_host():
+    from paper_2402_00525_amd import gsr
+    rng = np.random.default_rng(0)
+    a = np.concatenate([rng.uniform(-90, 10, 20000), rng.uniform(1, 1e6, 5000), rng.standard_normal(5000) * 1e-3,
+                        np.array([0.0, -0.0, 1.0, -80.0, -80.5, 0.5, 1.5, 2.5, -2.5])]).astype(np.float32)
+    b = rng.uniform(-5, 5, a.size).astype(np.float32)
+    b[b == 0] = 1.0
+    out = gsr.probe_math(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    with np.errstate(all="ignore"):
+        np.testing.assert_array_equal(out[0].view(np.uint32), (a / b).view(np.uint32))
+        sq = np.sqrt(a)
+        ok = a >= 0
+        np.testing.assert_array_equal(out[1][ok].view(np.uint32), sq[ok].view(np.uint32))
+        np.testing.assert_array_equal(out[4], np.rint(a))
+        np.testing.assert_array_equal(out[5].view(np.uint32), (a * b + a).view(np.uint32))
+    e = np.array([oracle.exp32(x) for x in a], np.float32)
+    np.testing.assert_array_equal(out[2].view(np.uint32), e.view(np.uint32))
+    big = a >= 1
+    l = np.array([oracle.ln32(x) for x in a[big]], np.float32)
+    np.testing.assert_array_equal(out[3][big].view(np.uint32), l.view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_HIER, oracle.MODE_GLOBAL])
+def test_small_scene_bit_exact(mode):
+    sc, cam = synth.workload_small()
+    say("case: small scene mode", mode)
+    o = oracle.frame(sc, cam, mode=mode, max_k=64)
+    g = gpu_frame(sc, cam, mode=mode, max_k=64)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    # the arithmetic is the same, so the images agree bit for bit
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+
+
+@pytest.mark.parametrize("head", [1, 2, 3, 8, 16, 24])
+def test_head_sizes_bit_exact(head):
+    sc, cam = synth.workload_small()
+    cam = synth.orbit_camera(128, 96, view=5)
+    say("case: head", head)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, head=head, max_k=48)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, head=head, max_k=48)
+    assert_sorted_equal(g, o)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+
+
+@pytest.mark.parametrize("W,H", [(200, 120), (33, 17), (16, 16), (1, 1), (250, 9)])
+def test_ragged_images(W, H):
+    sc = synth.uniform_scene(1500, seed=21, sh_degree=2)
+    cam = synth.orbit_camera(W, H, view=11)
+    say("case: ragged", W, H)
+    for mode in (oracle.MODE_HIER, oracle.MODE_GLOBAL):
+        o = oracle.frame(sc, cam, mode=mode, max_k=32)
+        g = gpu_frame(sc, cam, mode=mode, max_k=32)
+        assert_records_equal(g, o)
+        assert_sorted_equal(g, o)
+        assert_images_close(g, o, TOL)
+        np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+
+
+def test_mixture_scene_1080p_subsample_bit_exact():
+    full = synth.mixture_scene(200_000, seed=1)
+    sc = synth.subsample(full, 20_000)
+    cam = synth.orbit_camera(1920, 1080, view=3)
+    say("case: 20k mixture at 1080p")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=16)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=16)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+
+
+def test_edge_cases_empty_culled_nan():
+    from paper_2402_00525_amd import gsr
+    cam = synth.front_camera(64, 48)
+    say("case: empty scene")
+    empty = synth.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros((0, 4), np.float32),
+                        np.zeros((0,), np.float32), np.zeros((0, 1, 3), np.float32), 0)
+    ds = gsr.DeviceScene.from_host(empty)
+    r = gsr.Renderer(entries_hint=16)
+    out = r.render(ds, cam, gsr.config(bg=(0.25, 0.5, 0.75)))
+    rgb = out.rgb.cpu().numpy()
+    assert np.all(rgb[0] == 0.25) and np.all(rgb[2] == 0.75)
+    assert np.all(out.count.cpu().numpy() == 0) and np.all(out.T.cpu().numpy() == 1.0)
+    say("case: culled / NaN / zero quaternion")
+    sc = synth.uniform_scene(300, seed=9)
+    sc.means[0] = [0, 0, -10]          # behind the camera
+    sc.means[1, 0] = np.nan            # NaN parameter
+    sc.scales[2, 1] = 0.0              # zero scale
+    sc.rots[3] = 0.0                   # zero quaternion -> identity
+    sc.opacities[4] = 0.001            # below 1/255
+    sc.opacities[5] = np.inf
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=16)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=16)
+    assert o.touched[[0, 1, 2, 4, 5]].sum() == 0
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+
+
+def test_deterministic_repeat():
+    sc, cam = synth.workload_small()
+    a = gpu_frame(sc, cam, max_k=16)
+    b = gpu_frame(sc, cam, max_k=16)
+    for k in ("rgb", "depth", "T", "count", "blend_ids", "keys", "values"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_overflow_grows_workspace():
+    from paper_2402_00525_amd import gsr
+    sc, cam = synth.workload_small()
+    say("case: overflow")
+    ds = gsr.DeviceScene.from_host(sc)
+    r = gsr.Renderer(entries_hint=100)           # far too small: status bit, then re-plan
+    out = r.render(ds, cam, gsr.config(), max_k=8)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=8)
+    np.testing.assert_array_equal(out.blend_ids.cpu().numpy(), o.blend_ids)
