@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the sorted Gaussian-splatting frame on one MI355X.
+
+A step is one whole frame of the hot path -- preprocess, prefix sum and
+duplication, radix sort and tile ranges, hierarchical render -- for one view
+of a 60-view orbit around a synthetic 3M-Gaussian scene (degree-3 SH) at
+1920x1080, with the scene resident in HBM.  Prints ONE JSON line.
+
+Timing: W untimed frames, then K frames bracketed by torch.cuda.synchronize();
+stage and kernel durations come from HIP events recorded on the render stream
+at the stage boundaries and around every radix-scatter launch.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ms/frame @1080p fwd & fwd+bwd; batched views/s; achieved HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "3m_1080p": dict(n=3_000_000, seed=2, W=1920, H=1080),
+    "1m_1080p": dict(n=1_000_000, seed=1, W=1920, H=1080),
+    "small": dict(n=2000, seed=0, W=128, H=128),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="3m_1080p", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-global", action="store_true", help="skip timing the 3DGS global order alongside")
+    ap.add_argument("--views", type=int, default=60, help="orbit views to cycle through (60 = full orbit)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def make_events(n):
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    for e in evs:
+        e.record()
+    torch.cuda.synchronize()
+    return evs, (C.c_void_p * n)(*[e.cuda_event for e in evs])
+
+
+def time_frames(r, ds, cams, cfg, steps, warmup, passes):
+    """Render warmup + steps frames; returns per-frame stage/kernel times (ms)."""
+    import torch
+    from paper_2402_00525_amd import gsr
+    W, H = cams[0].W, cams[0].H
+    out = gsr.Frame(H, W, "cuda")
+    for i in range(warmup):
+        r.render_async(ds, cams[i % len(cams)], cfg, out)
+    nev = 5 + 2 * passes
+    frames = [make_events(nev) for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r.status.zero_()
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(steps):
+        r.render_async(ds, cams[(warmup + i) % len(cams)], cfg, out, events=frames[i][1])
+    end.record()
+    torch.cuda.synchronize()
+    if int(r.status.item()) != 0:
+        raise RuntimeError("tile entries overflowed the planned workspace during timing")
+    total = start.elapsed_time(end)
+    stages, scatter = [], []
+    for evs, _ in frames:
+        stages.append([evs[k].elapsed_time(evs[k + 1]) for k in range(4)])
+        scatter.append([evs[5 + 2 * p].elapsed_time(evs[6 + 2 * p]) for p in range(passes)])
+    return total / steps, stages, scatter
+
+
+def plan(r, ds, cams, cfg):
+    """Render every view once (untimed, with the overflow check) and size the
+    workspace for the largest frame plus 5%."""
+    import torch
+    n = ds.n
+    emax, consumed = 0, []
+    for cam in cams:
+        r.render(ds, cam, cfg)
+        emax = max(emax, r.counter(n, cam, 0))
+        consumed.append(r.counter(n, cam, 1))
+    r.plan(n, cams[0].W, cams[0].H, int(emax * 1.05) + 1024)
+    torch.cuda.synchronize()
+    return emax, consumed
+
+
+def mean(x):
+    return sum(x) / max(1, len(x))
+
+
+def cpu_baseline(scene, cam, E):
+    """The oracle on a bounded sample of the same frame: every per-Gaussian
+    stage and the full sort, but the render on 1 tile in 256; the render time
+    is scaled to the whole image."""
+    import numpy as np
+    import oracle
+    tiles = ((cam.W + 15) // 16) * ((cam.H + 15) // 16)
+    mask = np.zeros(tiles, np.uint8)
+    mask[::256] = 1
+    t0 = time.time()
+    r = oracle.frame(scene, cam, mode=oracle.MODE_HIER, tile_mask=mask, want_entries=False, capacity=E + 1024)
+    wall = time.time() - t0
+    pre, dup, srt, ren = r.stats["ms"]
+    est = pre + dup + srt + ren * tiles / int(mask.sum())
+    return {"value": round(est, 1), "unit": "ms/frame", "cores": int(r.stats["threads"]), "kind": "oracle",
+            "sample": "one 1920x1080 frame of the same scene: all %d Gaussians preprocessed, duplicated and sorted "
+                      "(%d entries), hierarchical render on %d of %d tiles scaled to the full image; %.1f s wall"
+                      % (scene.n, r.stats["entries"], int(mask.sum()), tiles, wall),
+            "stages_ms": {"preprocess": round(pre, 1), "duplicate": round(dup, 1), "sort": round(srt, 1),
+                          "render_scaled": round(ren * tiles / int(mask.sum()), 1)}}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build renders on one GPU only (the multi-GPU sharding is a design note); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2402_00525_amd import gsr, synth
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.time()
+    if args.workload == "small":
+        scene, cam0 = synth.workload_small()
+        cams = [cam0]
+    else:
+        scene = synth.mixture_scene(wl["n"], seed=wl["seed"])
+        cams = [synth.orbit_camera(wl["W"], wl["H"], v) for v in range(0, 60, max(1, 60 // args.views))]
+    log("scene generated in %.1fs" % (time.time() - t0))
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
+        del src, dst
+    ds = gsr.DeviceScene.from_host(scene)
+    n, W, H = scene.n, cams[0].W, cams[0].H
+    P = W * H
+    passes = gsr.lib().gsr_sort_passes(W, H)
+    ksh = (scene.sh_degree + 1) ** 2
+
+    results = {}
+    for label, mode in (("hier", gsr.MODE_HIER), ("global", gsr.MODE_GLOBAL)):
+        if label == "global" and args.no_global:
+            continue
+        cfg = gsr.config(mode=mode)
+        r = gsr.Renderer(entries_hint=40 * n)
+        emax, consumed = plan(r, ds, cams, cfg)
+        ms, stages, scatter = time_frames(r, ds, cams, cfg, args.steps, args.warmup, passes)
+        # entries of the timed views (every view was rendered once while planning)
+        views = [(args.warmup + i) % len(cams) for i in range(args.steps)]
+        E_views, cons_views = [], []
+        for v in sorted(set(views)):
+            r.render(ds, cams[v], cfg)
+            E_views.append(r.counter(n, cams[v], 0))
+            cons_views.append(r.counter(n, cams[v], 1))
+        results[label] = dict(ms=ms, stages=[mean([s[k] for s in stages]) for k in range(4)],
+                              scatter=mean([mean(s) for s in scatter]), E=mean(E_views), consumed=mean(cons_views),
+                              emax=emax)
+        log("%s: %.3f ms/frame, stages %s, scatter %.3f ms/launch, E %.0f, consumed %.0f" %
+            (label, ms, ["%.3f" % x for x in results[label]["stages"]], results[label]["scatter"],
+             results[label]["E"], results[label]["consumed"]))
+        del r
+        torch.cuda.empty_cache()
+
+    h = results["hier"]
+    # Dominant kernel and its algorithmic bytes per launch.
+    cands = {
+        "k_preprocess": (h["stages"][0], h["stages"][0], n * (44 + 12 * ksh) + n * 104),
+        "k_radix_scatter": (h["scatter"] * passes, h["scatter"], 24.0 * h["E"]),
+        "k_render_hier": (h["stages"][3], h["stages"][3], 76.0 * h["consumed"] + 24.0 * P),
+    }
+    dom = max(cands, key=lambda k: cands[k][0])
+    per_frame, dur, nbytes = cands[dom]
+    achieved = nbytes / (dur * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(nbytes), "avg_launch_ms": round(dur, 4)}
+    frame_bytes = (n * (44 + 12 * ksh) + n * 104) + 8.0 * n + 12.0 * h["E"] + 24.0 * h["E"] + 8.0 * h["E"] \
+        + 76.0 * h["consumed"] + 24.0 * P
+    line = {
+        "metric": METRIC, "value": round(h["ms"], 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(h["ms"], 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d-Gaussian mixture scene (SH degree %d), %dx%d, 60-view orbit, hierarchical "
+                               "resort 64/8/4" % (n, scene.sh_degree, W, H),
+                   "gaussians": n, "width": W, "height": H, "views": len(cams), "head": 4},
+        "stages_ms": {k: round(v, 4) for k, v in zip(("preprocess", "duplicate", "sort", "render"), h["stages"])},
+        "entries": int(h["E"]), "entries_consumed": int(h["consumed"]),
+        "frame_hbm_GBs": round(frame_bytes / (h["ms"] * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+    }
+    if "global" in results:
+        g = results["global"]
+        line["global_order"] = {"ms_per_frame": round(g["ms"], 4), "entries": int(g["E"]),
+                                "stages_ms": {k: round(v, 4) for k, v in
+                                              zip(("preprocess", "duplicate", "sort", "render"), g["stages"])}}
+    if not args.no_cpu_baseline and args.workload != "small":
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(scene, cams[args.warmup % len(cams)], int(h["emax"]))
+    elif not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, cams[0], int(h["emax"]))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,14 +150,19 @@ int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_co
                      size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                      int32_t* blend_ids, int32_t max_k, int32_t* status_dev, gsr_stream_t stream);
 
-/* As gsr_render, and records five caller-created HIP events (hipEvent_t,
- * passed as void*) on the stream at the stage boundaries of Sec. 4.3's
- * breakdown: events[0] before Preprocess, [1] after Preprocess, [2] after
- * Duplicate (prefix sum + key emission), [3] after Sort (radix sort + tile
- * ranges), [4] after Render.  The caller owns and destroys the events. */
+/* As gsr_render, and records caller-created HIP events (hipEvent_t, passed
+ * as void*) on the stream at the stage boundaries of the paper's per-stage
+ * timing (Sec. 4.3): events[0] before Preprocess, [1] after Preprocess, [2]
+ * after Duplicate (prefix sum + key emission), [3] after Sort (radix sort +
+ * tile ranges), [4] after Render.  With n_events >= 5 + 2 * passes
+ * (passes = gsr_sort_passes(W, H)), events[5 + 2p] and [6 + 2p] also bracket
+ * the scatter launch of radix pass p.  The caller owns the events. */
 int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
-                      int32_t* status_dev, gsr_stream_t stream, void* const* events);
+                      int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);
+
+/* Number of 8-bit radix passes a W x H frame's keys need (tile bits + 32). */
+int gsr_sort_passes(int32_t W, int32_t H);
 
 /* Element-wise arithmetic probe of the device (diagnostic): for n inputs
  * a[i], b[i] writes out[k*n + i] for k = 0..5:

@@ -52,7 +52,8 @@ class OFrameOut(C.Structure):
                 ("values", C.c_void_p), ("capacity", C.c_int64), ("n_entries", C.c_int64),
                 ("ranges", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p),
                 ("count", C.c_void_p), ("T", C.c_void_p), ("blend_ids", C.c_void_p),
-                ("max_k", C.c_int32), ("delta", C.c_void_p), ("stats", C.c_int64 * 12), ("tile_mask", C.c_void_p)]
+                ("max_k", C.c_int32), ("delta", C.c_void_p), ("stats", C.c_int64 * 12), ("tile_mask", C.c_void_p),
+                ("ms", C.c_double * 4), ("threads", C.c_int32)]
 
 
 def lib():
@@ -127,7 +128,8 @@ def _scene_arrays(scene):
             (scene.means, scene.scales, scene.rots, scene.opacities, scene.sh)]
 
 
-def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mask=None, **cfgkw) -> FrameResult:
+def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mask=None, capacity=None,
+          want_entries=True, **cfgkw) -> FrameResult:
     """Run the whole frame on the CPU and return every intermediate.  With
     ``tile_mask`` (uint8 per tile) only those tiles are rendered; per-Gaussian
     records and the sorted entries are always complete."""
@@ -150,10 +152,10 @@ def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mas
     T = np.zeros((H, W), dt)
     delta = np.zeros((H, W), np.float32)
     bids = np.zeros((H, W, max_k), np.int32) if max_k > 0 else None
-    cap = 0
+    cap = int(capacity) if capacity is not None else 64 * n + 4096
     for attempt in range(2):
-        keys = np.zeros(max(cap, 1), np.uint64)
-        values = np.zeros(max(cap, 1), np.uint32)
+        keys = np.empty(max(cap, 1), np.uint64) if want_entries else None
+        values = np.empty(max(cap, 1), np.uint32) if want_entries else None
         o = OFrameOut()
         o.xy, o.conic_o, o.sw, o.zd, o.rect, o.touched = map(_p, (xy, conic_o, sw, zd, rect, touched))
         o.keys, o.values, o.capacity = _p(keys), _p(values), cap
@@ -177,8 +179,10 @@ def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mas
     E = int(o.n_entries)
     st = list(o.stats)
     stats = dict(tail_in=st[0], mid_in=st[1], head_in=st[2], blends=st[3], max_tail=st[4], max_mid=st[5],
-                 max_head=st[6], min_tail_after_pop=st[7], entries=st[8])
-    return FrameResult(xy, conic_o, sw, zd, rect, touched, keys[:E], values[:E], ranges, rgb, depth, count, T,
+                 max_head=st[6], min_tail_after_pop=st[7], entries=st[8], ms=list(o.ms), threads=int(o.threads))
+    if want_entries:
+        keys, values = keys[:E], values[:E]
+    return FrameResult(xy, conic_o, sw, zd, rect, touched, keys, values, ranges, rgb, depth, count, T,
                        bids, delta, stats)
 
 

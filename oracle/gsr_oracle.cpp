@@ -22,6 +22,7 @@
 // the special cases described in hier_subtile().
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -727,8 +728,13 @@ template <class F> struct Frame {
     std::vector<u32> range_lo, range_hi;
     std::vector<Pixel<F>> pix;
     HierStats stats;
+    double ms[4] = {0, 0, 0, 0};  // preprocess, duplicate, sort, render (wall clock)
     Frame(const OCam& c, const OCfg& f) : cam(c), cfg(f) {}
 };
+
+inline double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 template <class F>
 void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* scales, const float* rots,
@@ -738,12 +744,14 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
     const int K = (deg + 1) * (deg + 1);
     fr.recs.assign(n, Rec<F>());
     fr.touched.assign(n, 0);
+    double t0 = now_ms();
 #pragma omp parallel for schedule(dynamic, 256)
     for (int i = 0; i < n; ++i) {
         preprocess_one<F>(cam, mode, deg, means + 3 * i, scales + 3 * i, rots + 4 * i, opac[i], sh + 3 * K * i, fr.recs[i]);
         fr.touched[i] = (mode == MODE_FULL) ? 0 : count_tiles(cam, mode, fr.recs[i]);
     }
     const int ntiles = cam.tiles_x * cam.tiles_y;
+    fr.ms[0] = now_ms() - t0;
     fr.pix.assign((size_t)cam.W * cam.H, Pixel<F>());
     if (mode == MODE_FULL) {
         // Brute force (Sec. 3.2): every visible Gaussian, per pixel, sorted by
@@ -775,11 +783,17 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
         return;
     }
     // Duplicate in Gaussian order, then sort by (tile, depth key, id).
+    t0 = now_ms();
     std::vector<std::vector<Entry>> per(n);
 #pragma omp parallel for schedule(dynamic, 256)
     for (int i = 0; i < n; ++i) emit_entries(cam, mode, fr.recs[i], (u32)i, per[i]);
     fr.entries.clear();
-    for (int i = 0; i < n; ++i) fr.entries.insert(fr.entries.end(), per[i].begin(), per[i].end());
+    for (int i = 0; i < n; ++i) {
+        fr.entries.insert(fr.entries.end(), per[i].begin(), per[i].end());
+        std::vector<Entry>().swap(per[i]);
+    }
+    fr.ms[1] = now_ms() - t0;
+    t0 = now_ms();
     std::sort(fr.entries.begin(), fr.entries.end());
     fr.range_lo.assign(ntiles, 0);
     fr.range_hi.assign(ntiles, 0);
@@ -790,6 +804,8 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
     }
     std::vector<u32> ids(fr.entries.size());
     for (size_t e = 0; e < ids.size(); ++e) ids[e] = fr.entries[e].id;
+    fr.ms[2] = now_ms() - t0;
+    t0 = now_ms();
 
     if (mode == MODE_GLOBAL) {
         // Each pixel blends its tile's list in key order (3DGS).
@@ -811,6 +827,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
                     }
                 }
         }
+        fr.ms[3] = now_ms() - t0;
         return;
     }
     // Hierarchical: every 4x4 sub-tile runs its queues independently.
@@ -824,6 +841,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
         HierSubtile<F> H(cam, fr.cfg, fr.recs, sx * 4, sy * 4, fr.pix, sts[s]);
         H.run(ids.data(), fr.range_lo[tile], fr.range_hi[tile]);
     }
+    fr.ms[3] = now_ms() - t0;
     for (auto& s : sts) {
         fr.stats.tail_in += s.tail_in; fr.stats.mid_in += s.mid_in; fr.stats.head_in += s.head_in;
         fr.stats.blends += s.blends;
@@ -861,6 +879,8 @@ struct OFrameOut {
     float* delta;        // [H,W] per-pixel sort error
     int64_t stats[12];   // out: tail_in, mid_in, head_in, blends, max_tail, max_mid, max_head, min_tail_after_pop, entries
     const uint8_t* tile_mask;  // optional [tiles]: render only these tiles
+    double ms[4];              // out: preprocess, duplicate, sort, render wall-clock times
+    int32_t threads;           // out: OpenMP threads used
 };
 
 template <class F, class OUT>
@@ -918,6 +938,12 @@ static int frame_impl(int n, int deg, const float* means, const float* scales, c
     o->stats[0] = fr.stats.tail_in; o->stats[1] = fr.stats.mid_in; o->stats[2] = fr.stats.head_in;
     o->stats[3] = fr.stats.blends; o->stats[4] = fr.stats.max_tail; o->stats[5] = fr.stats.max_mid;
     o->stats[6] = fr.stats.max_head; o->stats[7] = fr.stats.min_tail_after_pop; o->stats[8] = (int64_t)fr.entries.size();
+    for (int k = 0; k < 4; ++k) o->ms[k] = fr.ms[k];
+#ifdef _OPENMP
+    o->threads = omp_get_max_threads();
+#else
+    o->threads = 1;
+#endif
     return 0;
 }
 

@@ -120,7 +120,7 @@ int check_camera(const gsr_camera* c) {
 
 int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                 float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
-                int32_t* status_dev, gsr_stream_t stream, void* const* events) {
+                int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events) {
     int rc = check_scene(scene);
     if (rc) return rc;
     if ((rc = check_camera(cam))) return rc;
@@ -177,7 +177,8 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
         return fail_hip(e, "duplicate");
     if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
     int res = 0;
-    if ((e = gsr::launch_sort(b, key_bits, &res, s)) != hipSuccess) return fail_hip(e, "sort");
+    void* const* scatter_ev = (events && n_events >= 5 + 2 * passes) ? events + 5 : nullptr;
+    if ((e = gsr::launch_sort(b, key_bits, &res, s, scatter_ev)) != hipSuccess) return fail_hip(e, "sort");
     if ((e = gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess)
         return fail_hip(e, "ranges");
     if ((e = mark(3)) != hipSuccess) return fail_hip(e, "event");
@@ -260,17 +261,22 @@ int gsr_check_config(const gsr_config* c) {
 int gsr_render(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                float* rgb, float* depth, int32_t* count, float* T_final, int32_t* status_dev, gsr_stream_t stream) {
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
-                       nullptr);
+                       nullptr, 0);
 }
 
 int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                       float* rgb, float* depth, int32_t* count, float* T_final, int32_t* status_dev,
-                      gsr_stream_t stream, void* const* events) {
-    if (!events) return fail(GSR_EINVAL, "events is NULL");
-    for (int k = 0; k < 5; ++k)
+                      gsr_stream_t stream, void* const* events, int32_t n_events) {
+    if (!events || n_events < 5) return fail(GSR_EINVAL, "need at least 5 events");
+    for (int k = 0; k < n_events; ++k)
         if (!events[k]) return fail(GSR_EINVAL, "event is NULL");
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
-                       events);
+                       events, n_events);
+}
+
+int gsr_sort_passes(int32_t W, int32_t H) {
+    if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
+    return (32 + bits_for_tiles(tiles_of(W, H)) + 7) / 8;
 }
 
 int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
@@ -278,7 +284,7 @@ int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_co
                      int32_t* status_dev, gsr_stream_t stream) {
     if (!blend_ids) return fail(GSR_EINVAL, "blend_ids is NULL");
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, blend_ids, max_k, status_dev, stream,
-                       nullptr);
+                       nullptr, 0);
 }
 
 int gsr_probe_math(const float* a, const float* b, int32_t n, float* out, gsr_stream_t stream) {

@@ -63,7 +63,10 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const Fr
                             hipStream_t s);
 // Stable LSD radix sort of the first counters[0] (key, value) pairs on the
 // low `bits` key bits; returns the buffer index (0/1) holding the result.
-hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s);
+// `scatter_events` (optional): 2 events per pass recorded right before and
+// after that pass's scatter launch.
+hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s,
+                       void* const* scatter_events = nullptr);
 hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
                          hipStream_t s);
 

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
 
 }  // namespace
 
-hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s) {
+hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s, void* const* scatter_events) {
     const size_t nb = sort_blocks(b.capacity);
     const int passes = (bits + 7) / 8;
     // Duplication writes into buffer (passes & 1) so that the result lands in buffer 0.
@@ -101,9 +101,11 @@ hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_
                            (const uint32_t*)b.counters, shift, b.hist, (uint32_t)nb);
         hipError_t e = launch_scan(b.hist, b.hist, nb * 256, b.scan_partial, nullptr, 0xffffffffu, nullptr, s);
         if (e != hipSuccess) return e;
+        if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p], s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)b.keys[cur],
                            (const uint32_t*)b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (const uint32_t*)b.counters,
                            shift, (const uint32_t*)b.hist, (uint32_t)nb);
+        if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p + 1], s)) != hipSuccess) return e;
         cur ^= 1;
     }
     *result_buf = cur;

@@ -52,8 +52,8 @@ class CLayout(C.Structure):
 _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
-           "gsr_render", "gsr_render_debug", "gsr_render_staged", "gsr_probe_math", "gsr_last_error",
-           "gsr_version")
+           "gsr_render", "gsr_render_debug", "gsr_render_staged", "gsr_sort_passes", "gsr_probe_math",
+           "gsr_last_error", "gsr_version")
 
 
 def lib():
@@ -80,7 +80,9 @@ def lib():
         L.gsr_render_staged.restype = C.c_int
         L.gsr_render_staged.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                         C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                        C.c_void_p, C.c_void_p]
+                                        C.c_void_p, C.c_void_p, C.c_int32]
+        L.gsr_sort_passes.restype = C.c_int
+        L.gsr_sort_passes.argtypes = [C.c_int32, C.c_int32]
         L.gsr_probe_math.restype = C.c_int
         L.gsr_probe_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.gsr_last_error.restype = C.c_char_p
@@ -201,15 +203,15 @@ class Renderer:
         return self.ws
 
     def render_async(self, scene: DeviceScene, cam, cfg: CConfig, out: Frame, max_k: int = 0, events=None):
-        """Enqueue one frame.  ``events``: optional ctypes array of five
-        hipEvent_t handles recorded at the stage boundaries."""
+        """Enqueue one frame.  ``events``: optional ctypes array of hipEvent_t
+        handles recorded at the stage boundaries (see gsr_render_staged)."""
         if self.ws is None:
             self.plan(scene.n, cam.W, cam.H, self.entries_hint)
         sc, cc = scene.c_struct(), camera(cam)
         if events is not None:
             rc = lib().gsr_render_staged(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
                                          _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T),
-                                         _ptr(self.status), _stream(), events)
+                                         _ptr(self.status), _stream(), events, len(events))
         elif max_k > 0:
             rc = lib().gsr_render_debug(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
                                         _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T),
