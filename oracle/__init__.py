@@ -53,7 +53,7 @@ class OFrameOut(C.Structure):
                 ("ranges", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p),
                 ("count", C.c_void_p), ("T", C.c_void_p), ("blend_ids", C.c_void_p),
                 ("max_k", C.c_int32), ("delta", C.c_void_p), ("stats", C.c_int64 * 12), ("tile_mask", C.c_void_p),
-                ("ms", C.c_double * 4), ("threads", C.c_int32)]
+                ("ms", C.c_double * 4), ("threads", C.c_int32), ("signature", C.c_uint64)]
 
 
 def lib():
@@ -75,6 +75,8 @@ def lib():
         L.oracle_topt_f64.restype = C.c_int
         L.oracle_ray_f64.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_void_p]
         L.oracle_ray_f32.argtypes = [C.c_void_p, C.c_float, C.c_float, C.c_void_p]
+        L.oracle_backward_f64.restype = C.c_int
+        L.oracle_backward_f32.restype = C.c_int
         _lib = L
     return _lib
 
@@ -179,7 +181,8 @@ def frame(scene, cam, mode=MODE_HIER, head=4, max_k=0, precision="f32", tile_mas
     E = int(o.n_entries)
     st = list(o.stats)
     stats = dict(tail_in=st[0], mid_in=st[1], head_in=st[2], blends=st[3], max_tail=st[4], max_mid=st[5],
-                 max_head=st[6], min_tail_after_pop=st[7], entries=st[8], ms=list(o.ms), threads=int(o.threads))
+                 max_head=st[6], min_tail_after_pop=st[7], entries=st[8], ms=list(o.ms), threads=int(o.threads),
+                 signature=int(o.signature))
     if want_entries:
         keys, values = keys[:E], values[:E]
     return FrameResult(xy, conic_o, sw, zd, rect, touched, keys, values, ranges, rgb, depth, count, T,
@@ -232,3 +235,24 @@ def ray(cam, u, v, precision="f64"):
         d = np.zeros(3, np.float32)
         lib().oracle_ray_f32(C.byref(oc), float(u), float(v), _p(d))
     return d
+
+
+def backward(scene, cam, dL_drgb, precision="f64", head=4, mode=MODE_HIER, bg=(0.0, 0.0, 0.0)):
+    """Forward + backward of one frame (Sec. 3.5): returns the image, the
+    gradients of sum(dL_drgb * rgb) with respect to every Gaussian parameter,
+    and the decision signature of the frame."""
+    L = lib()
+    n, K = scene.n, (scene.sh_degree + 1) ** 2
+    dt = np.float64 if precision == "f64" else np.float32
+    dL = np.ascontiguousarray(dL_drgb, dtype=dt)
+    g = dict(means=np.zeros((n, 3), dt), scales=np.zeros((n, 3), dt), rots=np.zeros((n, 4), dt),
+             opacities=np.zeros(n, dt), sh=np.zeros((n, K, 3), dt))
+    rgb = np.zeros((3, cam.H, cam.W), dt)
+    sig = np.zeros(1, np.uint64)
+    oc, of = ocam(cam), ocfg(mode=mode, head=head, bg=bg)
+    fn = L.oracle_backward_f64 if precision == "f64" else L.oracle_backward_f32
+    rc = fn(C.c_int(n), C.c_int(scene.sh_degree), *map(_p, _scene_arrays(scene)), C.byref(oc), C.byref(of), _p(dL),
+            _p(g["means"]), _p(g["scales"]), _p(g["rots"]), _p(g["opacities"]), _p(g["sh"]), _p(rgb), _p(sig))
+    if rc != 0:
+        raise RuntimeError("oracle backward failed: %d" % rc)
+    return rgb, g, int(sig[0])

@@ -248,6 +248,7 @@ template <class F> struct Rec {
     int rect[4];      // tile rectangle x0, y0, x1, y1 (inclusive)
     bool vis;
     bool clamp_rgb[3];
+    bool clamp_x, clamp_y;  // frustum clamp of the EWA Jacobian active
 };
 
 const float EPS_O_F = 1.0f / 255.0f;
@@ -461,6 +462,8 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
     // Visible: write the record.
     g.x = mx; g.y = my;
     g.ca = ca; g.cb = cb; g.cc = cc; g.op = op;
+    g.clamp_x = !(-cam.limx <= txtz && txtz <= cam.limx);
+    g.clamp_y = !(-cam.limy <= tytz && tytz <= cam.limy);
     g.rect[0] = (int)fx0; g.rect[1] = (int)fy0; g.rect[2] = (int)fx1; g.rect[3] = (int)fy1;
     for (int ch = 0; ch < 3; ++ch) { g.rgb[ch] = rgb[ch]; g.clamp_rgb[ch] = clamped[ch]; }
     g.s[0] = Si[0][0]; g.s[1] = Si[0][1]; g.s[2] = Si[0][2];
@@ -852,6 +855,227 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Backward pass (Sec. 3.5).  The image is C = sum_i c_i alpha_i T_i + T_N bg
+// over each pixel's blend sequence (Eq. volume_desc).  Front to back, the
+// colour of everything behind Gaussian i is C - C_i (C_i: accumulated colour
+// including i) and the transmittance behind it is T_N / T_{i+1}, so
+//   dC/dc_i     = alpha_i T_i
+//   dC/dalpha_i = c_i T_i - (C - C_i + T_N bg) / (1 - alpha_i).
+// The order (t_opt, culling, termination) is piecewise constant and carries
+// no gradient; clamped quantities (alpha at 0.99, colour at 0, the frustum
+// clamp of the Jacobian) pass none through the clamped variable.
+// ---------------------------------------------------------------------------
+template <class F> struct G2 {
+    F mx = 0, my = 0, ca = 0, cb = 0, cc = 0, op = 0, rgb[3] = {0, 0, 0};
+};
+
+template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const float bg[3], std::vector<G2<F>>& g2) {
+    const Cam<F>& cam = fr.cam;
+    const size_t P = (size_t)cam.W * cam.H;
+    for (int y = 0; y < cam.H; ++y)
+        for (int x = 0; x < cam.W; ++x) {
+            const size_t p = (size_t)y * cam.W + x;
+            const Pixel<F>& px = fr.pix[p];
+            const F TN = px.T;
+            F T = 1, Cacc[3] = {0, 0, 0};
+            for (size_t k = 0; k < px.ids.size(); ++k) {
+                const int id = px.ids[k];
+                const F a = px.alphas[k];
+                const Rec<F>& g = fr.recs[id];
+                for (int ch = 0; ch < 3; ++ch) Cacc[ch] = Cacc[ch] + (g.rgb[ch] * a) * T;
+                F ga = 0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    const F dl = dL[ch * P + p];
+                    g2[id].rgb[ch] += dl * a * T;
+                    ga += dl * (g.rgb[ch] * T - (px.C[ch] - Cacc[ch] + TN * (F)bg[ch]) / (F(1) - a));
+                }
+                const F pw = power_at(g, (F)x, (F)y);
+                const F G = expE(pw);
+                if (g.op * G < F(0.99)) {
+                    g2[id].op += ga * G;
+                    const F gp = ga * a;  // d alpha / d power = o G = alpha
+                    const F dx = g.x - (F)x, dy = g.y - (F)y;
+                    g2[id].mx += gp * (-g.ca * dx - g.cb * dy);
+                    g2[id].my += gp * (-g.cc * dy - g.cb * dx);
+                    g2[id].ca += gp * (F(-0.5) * dx * dx);
+                    g2[id].cb += gp * (-dx * dy);
+                    g2[id].cc += gp * (F(-0.5) * dy * dy);
+                }
+                T = T * (F(1) - a);
+            }
+        }
+}
+
+// Chain rule from the 2D quantities back to the Gaussian parameters through
+// the colour (SH), the conic (EWA, Sigma = R S S^T R^T) and the 2D mean.
+template <class F>
+void backward_gaussian(const Cam<F>& cam, int deg, const float* mu_in, const float* s_in, const float* q_in,
+                       const float* sh_in, const Rec<F>& rec, const G2<F>& g, F* dmu, F* ds, F* dq, F* dop, F* dsh) {
+    const int K = (deg + 1) * (deg + 1);
+    for (int j = 0; j < 3; ++j) dmu[j] = ds[j] = 0;
+    for (int j = 0; j < 4; ++j) dq[j] = 0;
+    *dop = 0;
+    for (int k = 0; k < 3 * K; ++k) dsh[k] = 0;
+    if (!rec.vis) return;
+    const F mu[3] = {(F)mu_in[0], (F)mu_in[1], (F)mu_in[2]};
+    const F s[3] = {(F)s_in[0], (F)s_in[1], (F)s_in[2]};
+    const F n2 = ((F)q_in[0] * q_in[0] + (F)q_in[1] * q_in[1]) + (F)q_in[2] * q_in[2] + (F)q_in[3] * q_in[3];
+    F qn[4] = {1, 0, 0, 0}, nrm = 0;
+    if (n2 != F(0)) {
+        nrm = std::sqrt(n2);
+        for (int j = 0; j < 4; ++j) qn[j] = (F)q_in[j] / nrm;
+    }
+    const F w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+    F Rq[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                  {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                  {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    F M[3][3], Sg[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) M[j][l] = Rq[j][l] * s[l];
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) Sg[j][k] = M[j][0] * M[k][0] + M[j][1] * M[k][1] + M[j][2] * M[k][2];
+    F p[3];
+    for (int j = 0; j < 3; ++j) p[j] = cam.R[3 * j] * mu[0] + cam.R[3 * j + 1] * mu[1] + cam.R[3 * j + 2] * mu[2] + cam.t[j];
+    const F pz = p[2], pz2 = pz * pz, pz3 = pz2 * pz;
+    const F txtz = p[0] / pz, tytz = p[1] / pz;
+    const F Lx = sclamp(txtz, -cam.limx, cam.limx), Ly = sclamp(tytz, -cam.limy, cam.limy);
+    const F J00 = cam.fx / pz, J02 = -(cam.fx * Lx * pz) / pz2;
+    const F J11 = cam.fy / pz, J12 = -(cam.fy * Ly * pz) / pz2;
+    F T[2][3];
+    for (int k = 0; k < 3; ++k) {
+        T[0][k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
+        T[1][k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+    }
+    F TS[2][3];
+    for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 3; ++k) TS[j][k] = T[j][0] * Sg[0][k] + T[j][1] * Sg[1][k] + T[j][2] * Sg[2][k];
+    const F a = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + F(0.3);
+    const F b = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+    const F c = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + F(0.3);
+    const F D = a * c - b * b, D2 = D * D;
+
+    // Colour: rgb = max(0, sum_k b_k(dir) sh_k + 1/2), dir = (mu - o) / |mu - o|.
+    F dm[3] = {mu[0] - cam.o[0], mu[1] - cam.o[1], mu[2] - cam.o[2]};
+    const F len = std::sqrt(dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2]);
+    const F dir[3] = {dm[0] / len, dm[1] / len, dm[2] / len};
+    F bas[16], db[16][3];
+    sh_basis<F>(deg, dir[0], dir[1], dir[2], bas);
+    sh_basis_grad<F>(deg, dir[0], dir[1], dir[2], db);
+    F gacc[3];
+    for (int ch = 0; ch < 3; ++ch) gacc[ch] = rec.clamp_rgb[ch] ? F(0) : g.rgb[ch];
+    F gdir[3] = {0, 0, 0};
+    for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) {
+            dsh[3 * k + ch] = bas[k] * gacc[ch];
+            for (int j = 0; j < 3; ++j) gdir[j] += gacc[ch] * (F)sh_in[3 * k + ch] * db[k][j];
+        }
+    const F dd = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+    for (int j = 0; j < 3; ++j) dmu[j] += (gdir[j] - dir[j] * dd) / len;
+
+    // Conic (c, -b, a) / D of the 2D covariance (a, b, c).
+    const F ga = g.ca * (-c * c / D2) + g.cb * (b * c / D2) + g.cc * (-b * b / D2);
+    const F gb = g.ca * (2 * b * c / D2) + g.cb * (-F(1) / D - 2 * b * b / D2) + g.cc * (2 * a * b / D2);
+    const F gc = g.ca * (-b * b / D2) + g.cb * (a * b / D2) + g.cc * (-a * a / D2);
+    const F G2m[2][2] = {{ga, gb / 2}, {gb / 2, gc}};
+    // Sigma_2 = T Sigma T^T: dSigma = T^T G T, dT = 2 G T Sigma.
+    F dSg[3][3], dT[2][3];
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+            F acc = 0;
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v) acc += T[u][j] * G2m[u][v] * T[v][k];
+            dSg[j][k] = acc;
+        }
+    for (int u = 0; u < 2; ++u)
+        for (int k = 0; k < 3; ++k) {
+            F acc = 0;
+            for (int v = 0; v < 2; ++v) acc += G2m[u][v] * TS[v][k];
+            dT[u][k] = 2 * acc;
+        }
+    // T = J W with W the camera rotation.
+    F dJ00 = 0, dJ02 = 0, dJ11 = 0, dJ12 = 0;
+    for (int k = 0; k < 3; ++k) {
+        dJ00 += dT[0][k] * cam.R[k];
+        dJ02 += dT[0][k] * cam.R[6 + k];
+        dJ11 += dT[1][k] * cam.R[3 + k];
+        dJ12 += dT[1][k] * cam.R[6 + k];
+    }
+    F gp[3] = {0, 0, 0};
+    gp[0] += g.mx * cam.fx / pz;
+    gp[1] += g.my * cam.fy / pz;
+    gp[2] += -g.mx * cam.fx * p[0] / pz2 - g.my * cam.fy * p[1] / pz2;
+    gp[2] += dJ00 * (-cam.fx / pz2) + dJ11 * (-cam.fy / pz2);
+    if (!rec.clamp_x) {
+        gp[0] += dJ02 * (-cam.fx / pz2);
+        gp[2] += dJ02 * (2 * cam.fx * p[0] / pz3);
+    } else {
+        gp[2] += dJ02 * (cam.fx * Lx / pz2);
+    }
+    if (!rec.clamp_y) {
+        gp[1] += dJ12 * (-cam.fy / pz2);
+        gp[2] += dJ12 * (2 * cam.fy * p[1] / pz3);
+    } else {
+        gp[2] += dJ12 * (cam.fy * Ly / pz2);
+    }
+    for (int j = 0; j < 3; ++j) dmu[j] += cam.R[j] * gp[0] + cam.R[3 + j] * gp[1] + cam.R[6 + j] * gp[2];
+
+    // Sigma = M M^T with M = R_q diag(s).
+    F dM[3][3];
+    for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) dM[j][l] = 2 * (dSg[j][0] * M[0][l] + dSg[j][1] * M[1][l] + dSg[j][2] * M[2][l]);
+    F dR[3][3];
+    for (int l = 0; l < 3; ++l) {
+        ds[l] = dM[0][l] * Rq[0][l] + dM[1][l] * Rq[1][l] + dM[2][l] * Rq[2][l];
+        for (int j = 0; j < 3; ++j) dR[j][l] = dM[j][l] * s[l];
+    }
+    // Rotation from the unit quaternion, then the normalisation.
+    F dqn[4];
+    dqn[0] = 2 * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+    dqn[1] = 2 * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2 * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                  w * dR[2][1] - 2 * x * dR[2][2]);
+    dqn[2] = 2 * (-2 * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                  z * dR[2][1] - 2 * y * dR[2][2]);
+    dqn[3] = 2 * (-2 * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2 * z * dR[1][1] + y * dR[1][2] +
+                  x * dR[2][0] + y * dR[2][1]);
+    if (n2 != F(0)) {
+        const F qd = qn[0] * dqn[0] + qn[1] * dqn[1] + qn[2] * dqn[2] + qn[3] * dqn[3];
+        for (int j = 0; j < 4; ++j) dq[j] = (dqn[j] - qn[j] * qd) / nrm;
+    }
+    *dop = g.op;
+}
+
+// FNV-1a hash of every discrete decision of a frame: visibility, rectangles,
+// kept-tile counts, clamps, and each pixel's blend sequence.  Two parameter
+// vectors with equal signatures lie on the same smooth piece of the image.
+template <class F> u64 decision_signature(const Frame<F>& fr) {
+    u64 h = 1469598103934665603ull;
+    auto mix = [&](u64 v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (size_t i = 0; i < fr.recs.size(); ++i) {
+        const Rec<F>& g = fr.recs[i];
+        mix(g.vis);
+        if (!g.vis) continue;
+        for (int k = 0; k < 4; ++k) mix((u64)(int64_t)g.rect[k]);
+        mix(fr.touched[i]);
+        mix(g.clamp_rgb[0] | (g.clamp_rgb[1] << 1) | (g.clamp_rgb[2] << 2) | (g.clamp_x << 3) | (g.clamp_y << 4));
+    }
+    for (size_t p = 0; p < fr.pix.size(); ++p) {
+        const Pixel<F>& px = fr.pix[p];
+        mix(px.ids.size());
+        for (size_t k = 0; k < px.ids.size(); ++k) {
+            mix((u64)px.ids[k]);
+            mix(px.alphas[k] >= F(0.99));
+        }
+    }
+    return h;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -881,6 +1105,7 @@ struct OFrameOut {
     const uint8_t* tile_mask;  // optional [tiles]: render only these tiles
     double ms[4];              // out: preprocess, duplicate, sort, render wall-clock times
     int32_t threads;           // out: OpenMP threads used
+    uint64_t signature;        // out: hash of every discrete decision of the frame
 };
 
 template <class F, class OUT>
@@ -939,11 +1164,37 @@ static int frame_impl(int n, int deg, const float* means, const float* scales, c
     o->stats[3] = fr.stats.blends; o->stats[4] = fr.stats.max_tail; o->stats[5] = fr.stats.max_mid;
     o->stats[6] = fr.stats.max_head; o->stats[7] = fr.stats.min_tail_after_pop; o->stats[8] = (int64_t)fr.entries.size();
     for (int k = 0; k < 4; ++k) o->ms[k] = fr.ms[k];
+    o->signature = decision_signature(fr);
 #ifdef _OPENMP
     o->threads = omp_get_max_threads();
 #else
     o->threads = 1;
 #endif
+    return 0;
+}
+
+
+// Forward and backward of one frame: dL_drgb [3,H,W]; gradients per Gaussian
+// (means [N,3], scales [N,3], rots [N,4], opacities [N], sh [N,(d+1)^2,3]);
+// also writes the forward image and the decision signature.
+template <class F>
+static int backward_impl(int n, int deg, const float* means, const float* scales, const float* rots,
+                         const float* opac, const float* sh, const OCam* cam, const OCfg* cfg, const F* dL, F* dmeans,
+                         F* dscales, F* drots, F* dopac, F* dsh, F* rgb_out, uint64_t* signature) {
+    if (n < 0 || deg < 0 || deg > 3) return -1;
+    Frame<F> fr(*cam, *cfg);
+    run_frame<F>(fr, n, deg, means, scales, rots, opac, sh, nullptr);
+    std::vector<G2<F>> g2(n);
+    backward_blends(fr, dL, cfg->bg, g2);
+    const int K = (deg + 1) * (deg + 1);
+    for (int i = 0; i < n; ++i)
+        backward_gaussian<F>(fr.cam, deg, means + 3 * i, scales + 3 * i, rots + 4 * i, sh + 3 * K * i, fr.recs[i], g2[i],
+                             dmeans + 3 * i, dscales + 3 * i, drots + 4 * i, dopac + i, dsh + 3 * K * i);
+    const size_t P = (size_t)cam->W * cam->H;
+    if (rgb_out)
+        for (size_t p = 0; p < P; ++p)
+            for (int ch = 0; ch < 3; ++ch) rgb_out[ch * P + p] = fr.pix[p].C[ch] + fr.pix[p].T * (F)cfg->bg[ch];
+    if (signature) *signature = decision_signature(fr);
     return 0;
 }
 
@@ -959,6 +1210,20 @@ int oracle_frame_f64(int n, int deg, const float* means, const float* scales, co
                      const float* sh, const OCam* cam, const OCfg* cfg, OFrameOut* out, double* rgb, double* depth,
                      double* T) {
     return frame_impl<double, double>(n, deg, means, scales, rots, opac, sh, cam, cfg, out, rgb, depth, T);
+}
+
+int oracle_backward_f64(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                        const float* sh, const OCam* cam, const OCfg* cfg, const double* dL, double* dmeans,
+                        double* dscales, double* drots, double* dopac, double* dsh, double* rgb, uint64_t* sig) {
+    return backward_impl<double>(n, deg, means, scales, rots, opac, sh, cam, cfg, dL, dmeans, dscales, drots, dopac, dsh,
+                                 rgb, sig);
+}
+
+int oracle_backward_f32(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                        const float* sh, const OCam* cam, const OCfg* cfg, const float* dL, float* dmeans,
+                        float* dscales, float* drots, float* dopac, float* dsh, float* rgb, uint64_t* sig) {
+    return backward_impl<float>(n, deg, means, scales, rots, opac, sh, cam, cfg, dL, dmeans, dscales, drots, dopac, dsh,
+                                rgb, sig);
 }
 
 // ----- element functions exposed for the pins -----

@@ -1,0 +1,105 @@
+"""Pins of the oracle's backward pass (Sec. 3.5) against float64 central
+finite differences of the oracle's own float64 forward.
+
+Coordinates whose perturbation changes a discrete decision (culling, the
+blend sequence of any pixel, a clamp, the sign of the L1 residual) are
+skipped: the image is only piecewise smooth in the parameters.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_00525_amd import synth
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built(oracle_lib):
+    return oracle_lib
+
+
+def fd_scene():
+    # 64 Gaussians drawn like the small scene but with degree-3 SH, 32x32 camera
+    return synth.uniform_scene(64, seed=5, sh_degree=3), synth.front_camera(32, 32)
+
+
+def l1_loss(rgb, target):
+    return float(np.abs(rgb - target).mean())
+
+
+PARAMS = ("means", "scales", "rots", "opacities", "sh")
+
+
+def _perturbed(scene, name, idx, value):
+    arrs = {k: getattr(scene, k).copy() for k in PARAMS}
+    arrs[name].reshape(-1)[idx] = value
+    return synth.Scene(arrs["means"], arrs["scales"], arrs["rots"], arrs["opacities"], arrs["sh"], scene.sh_degree)
+
+
+def test_backward_matches_finite_differences_f64():
+    scene, cam = fd_scene()
+    target = synth.random_target(cam.H, cam.W, seed=4).astype(np.float64)
+    rgb0, _, _ = oracle.backward(scene, cam, np.zeros((3, cam.H, cam.W)), "f64")
+    sgn = np.sign(rgb0 - target)
+    dL = sgn / rgb0.size
+    rgb, grads, sig0 = oracle.backward(scene, cam, dL, "f64")
+    np.testing.assert_array_equal(rgb, rgb0)
+    rng = np.random.default_rng(0)
+    checked, skipped = 0, 0
+    # step sizes: relative to the value for the (small, positive) scales, absolute otherwise
+    rel_h = {"means": 1e-4, "scales": 1e-3, "rots": 1e-4, "opacities": 1e-4, "sh": 1e-3}
+    worst = 0.0
+    for name in PARAMS:
+        flat = getattr(scene, name).reshape(-1)
+        g = grads[name].reshape(-1)
+        # coordinates of Gaussians that contribute to some pixel
+        picks = rng.choice(flat.size, size=min(flat.size, 160), replace=False)
+        for idx in picks:
+            v = float(flat[idx])
+            h = rel_h[name] * (abs(v) if name == "scales" else max(1.0, abs(v)))
+            vp, vm = np.float32(v + h), np.float32(v - h)
+            step = float(vp) - float(vm)
+            rp = oracle.frame(_perturbed(scene, name, idx, vp), cam, precision="f64", want_entries=False)
+            rm = oracle.frame(_perturbed(scene, name, idx, vm), cam, precision="f64", want_entries=False)
+            if (rp.stats["signature"] != sig0 or rm.stats["signature"] != sig0
+                    or np.any(np.sign(rp.rgb - target) != sgn) or np.any(np.sign(rm.rgb - target) != sgn)):
+                skipped += 1
+                continue
+            fd = (l1_loss(rp.rgb, target) - l1_loss(rm.rgb, target)) / step
+            err = abs(fd - g[idx])
+            tol = 2e-7 + 2e-4 * abs(fd)
+            worst = max(worst, err / tol)
+            assert err <= tol, (name, idx, fd, g[idx])
+            checked += 1
+    print("checked", checked, "skipped", skipped, "worst err/tol", worst)
+    assert checked > 500, (checked, skipped)
+    assert skipped < checked
+
+
+def test_backward_f32_close_to_f64():
+    scene, cam = fd_scene()
+    target = synth.random_target(cam.H, cam.W, seed=4)
+    rgb0, _, _ = oracle.backward(scene, cam, np.zeros((3, cam.H, cam.W)), "f64")
+    dL = np.sign(rgb0 - target) / rgb0.size
+    _, g64, s64 = oracle.backward(scene, cam, dL, "f64")
+    _, g32, s32 = oracle.backward(scene, cam, dL.astype(np.float32), "f32")
+    for name in PARAMS:
+        a, b = g32[name].astype(np.float64), g64[name]
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 1e-3 * scale + 1e-9, name
+
+
+def test_backward_single_gaussian_closed_form():
+    # One Gaussian, dL/drgb = 1 on one channel at one pixel: d rgb / d opacity
+    # equals G (the unclamped Gaussian value) times the colour (Eq. volume_desc).
+    cam = synth.front_camera(32, 32)
+    sc = synth.Scene(np.array([[0.05, -0.03, 0.0]], np.float32), np.array([[0.2, 0.15, 0.1]], np.float32),
+                     np.array([[0.9, 0.1, 0.2, 0.3]], np.float32), np.array([0.5], np.float32),
+                     np.array([[[0.3, -0.2, 0.1]]], np.float32), 0)
+    r = oracle.frame(sc, cam, precision="f64", want_entries=False)
+    dL = np.zeros((3, 32, 32))
+    dL[1, 15, 16] = 1.0
+    _, g, _ = oracle.backward(sc, cam, dL, "f64")
+    col = 0.5 / np.sqrt(np.pi) * float(sc.sh[0, 0, 1]) + 0.5
+    alpha = r.rgb[1, 15, 16] / col
+    np.testing.assert_allclose(g["opacities"][0], alpha / 0.5 * col, rtol=1e-10)
+    np.testing.assert_allclose(g["sh"][0, 0, 1], alpha * 0.5 / np.sqrt(np.pi), rtol=1e-10)
