@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-global", action="store_true", help="skip timing the 3DGS global order alongside")
     ap.add_argument("--views", type=int, default=60, help="orbit views to cycle through (60 = full orbit)")
+    ap.add_argument("--no-fwd-bwd", action="store_true",
+                    help="skip the forward+backward measurement (500k Gaussians, 1280x720, L1 loss)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -126,6 +128,55 @@ def cpu_baseline(scene, cam, E):
                       % (scene.n, r.stats["entries"], int(mask.sum()), tiles, wall),
             "stages_ms": {"preprocess": round(pre, 1), "duplicate": round(dup, 1), "sort": round(srt, 1),
                           "render_scaled": round(ren * tiles / int(mask.sum()), 1)}}
+
+
+def fwd_bwd(steps, warmup):
+    """Forward + L1-loss gradient + backward on 500k mixture Gaussians at
+    1280x720 (target: a seeded random image); returns ms per training step."""
+    import torch
+    from paper_2402_00525_amd import gsr, synth
+    scene = synth.mixture_scene(500_000, seed=3)
+    cams = [synth.orbit_camera(1280, 720, v) for v in range(0, 60, 6)]
+    target = torch.from_numpy(synth.random_target(720, 1280, seed=4)).cuda()
+    ds = gsr.DeviceScene.from_host(scene)
+    cfg = gsr.config()
+    r = gsr.Renderer(entries_hint=40 * scene.n)
+    plan(r, ds, cams, cfg)
+    out = gsr.Frame(720, 1280, "cuda")
+    grads = {k: torch.empty_like(getattr(ds, k)) for k in ("means", "scales", "rots", "opacities", "sh")}
+
+    def step(cam, evs=None):
+        if evs is not None:
+            evs[0].record()
+        r.render_async(ds, cam, cfg, out)
+        if evs is not None:
+            evs[1].record()
+        dL = torch.sign(out.rgb - target) / out.rgb.numel()
+        g = gsr.render_backward(r, ds, cam, cfg, out, dL)
+        if evs is not None:
+            evs[2].record()
+        return g
+
+    for i in range(warmup):
+        step(cams[i % len(cams)])
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    r.status.zero_()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        step(cams[(warmup + i) % len(cams)], evs[i])
+    t1.record()
+    torch.cuda.synchronize()
+    if int(r.status.item()) != 0:
+        raise RuntimeError("overflow during fwd+bwd timing")
+    fwd = mean([e[0].elapsed_time(e[1]) for e in evs])
+    bwd = mean([e[1].elapsed_time(e[2]) for e in evs])
+    return {"ms_per_step": round(t0.elapsed_time(t1) / steps, 4), "forward_ms": round(fwd, 4),
+            "loss_and_backward_ms": round(bwd, 4),
+            "workload": "500000-Gaussian mixture scene (SH degree 3), 1280x720, 10 orbit views, L1 loss to a "
+                        "seeded random target, gradients for means/scales/rotations/opacities/SH"}
 
 
 def main():
@@ -216,6 +267,10 @@ def main():
         line["global_order"] = {"ms_per_frame": round(g["ms"], 4), "entries": int(g["E"]),
                                 "stages_ms": {k: round(v, 4) for k, v in
                                               zip(("preprocess", "duplicate", "sort", "render"), g["stages"])}}
+    if not args.no_fwd_bwd and args.workload != "small":
+        log("forward+backward ...")
+        line["fwd_bwd"] = fwd_bwd(max(5, args.steps // 2), 3)
+        log("fwd+bwd: %s" % line["fwd_bwd"])
     if not args.no_cpu_baseline and args.workload != "small":
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(scene, cams[args.warmup % len(cams)], int(h["emax"]))

@@ -105,9 +105,10 @@ typedef struct gsr_config {
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
  * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
  * (Gaussian id), ranges uint32[tiles][2] = [start, end) per tile; counters
- * uint32[4] = (entries, entries consumed by the renderer, unused, unused). */
+ * uint32[4] = (entries, entries consumed by the renderer, unused, unused);
+ * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb). */
 typedef struct gsr_layout {
-    int64_t xy, conic_o, sw, zd, rect, touched, offsets;
+    int64_t xy, conic_o, sw, zd, rect, touched, offsets, grad2d;
     int64_t keys, values, ranges, counters;
     int64_t entry_capacity;
     int64_t total_bytes;
@@ -149,6 +150,23 @@ int gsr_render(const gsr_scene* scene /* host struct, device arrays */, const gs
 int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                      size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                      int32_t* blend_ids, int32_t max_k, int32_t* status_dev, gsr_stream_t stream);
+
+/* Backward of gsr_render (Sec. 3.5), for the hierarchical order.  Given
+ * dL_drgb [3,H,W] and the forward call's rgb and T_final, re-runs the same
+ * per-pixel resorting front to back (nothing per pixel is stored by the
+ * forward pass) and writes the gradients of L with respect to
+ *   dmeans [N,3], dscales [N,3], drots [N,4] (unnormalised quaternion),
+ *   dopacities [N], dsh [N,(d+1)^2,3]   (device, float32, overwritten).
+ * scene, cam, cfg and ws must be exactly those of the forward call, and ws
+ * unmodified since.  The order of floating-point atomic additions makes the
+ * gradients reproducible only to rounding.  No gradient flows through the
+ * blend order, culling or early termination (they are piecewise constant),
+ * nor through the depth output.  Returns GSR_EUNSUPPORTED for the global
+ * order. */
+int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                        size_t ws_bytes, const float* dL_drgb, const float* rgb, const float* T_final,
+                        float* dmeans, float* dscales, float* drots, float* dopacities, float* dsh,
+                        gsr_stream_t stream);
 
 /* As gsr_render, and records caller-created HIP events (hipEvent_t, passed
  * as void*) on the stream at the stage boundaries of the paper's per-stage

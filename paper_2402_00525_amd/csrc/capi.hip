@@ -39,6 +39,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->rect = take(16 * n);
     L->touched = take(4 * n);
     L->offsets = take(4 * n);
+    L->grad2d = take(36 * n);
     L->ranges = take(8 * (int64_t)tiles);
     L->counters = take(64);
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
@@ -118,6 +119,27 @@ int check_camera(const gsr_camera* c) {
     return GSR_OK;
 }
 
+gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t hist, int64_t k1, int64_t v1) {
+    gsr::FrameBufs b;
+    b.xy = (float2*)(base + L.xy);
+    b.co = (float4*)(base + L.conic_o);
+    b.sw = (float4*)(base + L.sw);
+    b.zd = (float2*)(base + L.zd);
+    b.rect = (int4*)(base + L.rect);
+    b.touched = (uint32_t*)(base + L.touched);
+    b.offsets = (uint32_t*)(base + L.offsets);
+    b.scan_partial = (uint32_t*)(base + sp);
+    b.hist = (uint32_t*)(base + hist);
+    b.keys[0] = (uint64_t*)(base + L.keys);
+    b.keys[1] = (uint64_t*)(base + k1);
+    b.vals[0] = (uint32_t*)(base + L.values);
+    b.vals[1] = (uint32_t*)(base + v1);
+    b.ranges = (uint32_t*)(base + L.ranges);
+    b.counters = (uint32_t*)(base + L.counters);
+    b.capacity = (uint32_t)L.entry_capacity;
+    return b;
+}
+
 int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                 float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
                 int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events) {
@@ -136,23 +158,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if (rc) return fail(rc, "workspace too small");
     char* base = (char*)ws;
     if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
-    gsr::FrameBufs b;
-    b.xy = (float2*)(base + L.xy);
-    b.co = (float4*)(base + L.conic_o);
-    b.sw = (float4*)(base + L.sw);
-    b.zd = (float2*)(base + L.zd);
-    b.rect = (int4*)(base + L.rect);
-    b.touched = (uint32_t*)(base + L.touched);
-    b.offsets = (uint32_t*)(base + L.offsets);
-    b.scan_partial = (uint32_t*)(base + sp);
-    b.hist = (uint32_t*)(base + hist);
-    b.keys[0] = (uint64_t*)(base + L.keys);
-    b.keys[1] = (uint64_t*)(base + k1);
-    b.vals[0] = (uint32_t*)(base + L.values);
-    b.vals[1] = (uint32_t*)(base + v1);
-    b.ranges = (uint32_t*)(base + L.ranges);
-    b.counters = (uint32_t*)(base + L.counters);
-    b.capacity = (uint32_t)L.entry_capacity;
+    const gsr::FrameBufs b = frame_bufs(base, L, sp, hist, k1, v1);
 
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
@@ -201,12 +207,66 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.bg0 = cfg->bg[0];
     ra.bg1 = cfg->bg[1];
     ra.bg2 = cfg->bg[2];
+    ra.dL = nullptr;
+    ra.rgb_in = nullptr;
+    ra.T_in = nullptr;
+    ra.grad2d = nullptr;
     if (mode == GSR_MODE_HIER)
         e = gsr::launch_render_hier(ra, cfg->head, s);
     else
         e = gsr::launch_render_global(ra, s);
     if (e != hipSuccess) return fail_hip(e, "render");
     if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
+    return GSR_OK;
+}
+
+
+int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+                  const float* dL, const float* rgb, const float* T_final, float* dmeans, float* dscales, float* drots,
+                  float* dopac, float* dsh, gsr_stream_t stream) {
+    int rc = check_scene(scene);
+    if (rc) return rc;
+    if ((rc = check_camera(cam))) return rc;
+    if (!cfg) return fail(GSR_EINVAL, "config is NULL");
+    if ((rc = gsr_check_config(cfg))) return rc;
+    if (cfg->mode != GSR_MODE_HIER) return fail(GSR_EUNSUPPORTED, "backward is built for the hierarchical order");
+    if (!gsr::hier_head_supported(cfg->head)) return fail(GSR_EUNSUPPORTED, "head size not built");
+    if (!ws || !dL || !rgb || !T_final) return fail(GSR_EINVAL, "input is NULL");
+    if (scene->n > 0 && (!dmeans || !dscales || !drots || !dopac || !dsh)) return fail(GSR_EINVAL, "gradient is NULL");
+    gsr_layout L;
+    int64_t sp, hist, k1, v1;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &sp, &hist, &k1, &v1);
+    if (rc) return fail(rc, "workspace too small");
+    char* base = (char*)ws;
+    if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
+    const gsr::FrameBufs b = frame_bufs(base, L, sp, hist, k1, v1);
+    float* g2 = (float*)(base + L.grad2d);
+    hipStream_t s = (hipStream_t)stream;
+    const gsr::DevCam dc = make_cam(cam);
+    gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
+    hipError_t e;
+    if ((e = gsr::launch_fill_u32((uint32_t*)g2, (size_t)9 * scene->n, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
+    gsr::RenderArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.cam = dc;
+    ra.n = (uint32_t)scene->n;
+    ra.xy = b.xy;
+    ra.co = b.co;
+    ra.sw = b.sw;
+    ra.zd = b.zd;
+    ra.vals = b.vals[0];
+    ra.ranges = b.ranges;
+    ra.counters = b.counters;
+    ra.bg0 = cfg->bg[0];
+    ra.bg1 = cfg->bg[1];
+    ra.bg2 = cfg->bg[2];
+    ra.dL = dL;
+    ra.rgb_in = rgb;
+    ra.T_in = T_final;
+    ra.grad2d = g2;
+    if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render backward");
+    if ((e = gsr::launch_preprocess_backward(sc, dc, b.co, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
+        return fail_hip(e, "preprocess backward");
     return GSR_OK;
 }
 
@@ -272,6 +332,13 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
         if (!events[k]) return fail(GSR_EINVAL, "event is NULL");
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
                        events, n_events);
+}
+
+int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                        size_t ws_bytes, const float* dL_drgb, const float* rgb, const float* T_final, float* dmeans,
+                        float* dscales, float* drots, float* dopacities, float* dsh, gsr_stream_t stream) {
+    return backward_impl(scene, cam, cfg, ws, ws_bytes, dL_drgb, rgb, T_final, dmeans, dscales, drots, dopacities, dsh,
+                         stream);
 }
 
 int gsr_sort_passes(int32_t W, int32_t H) {

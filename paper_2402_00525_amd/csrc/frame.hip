@@ -20,6 +20,79 @@ constexpr float kC3c = 0.4570457994644658f;
 constexpr float kC3d = 0.37317633259011546f;
 constexpr float kC3e = 1.4453057213202771f;
 
+// Real SH basis b[0..(deg+1)^2) at the unit direction (x, y, z).
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* bas) {
+    bas[0] = kC0;
+    if (deg >= 1) {
+        bas[1] = (-kC1) * y;
+        bas[2] = kC1 * z;
+        bas[3] = (-kC1) * x;
+    }
+    if (deg >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+        bas[4] = kC2a * xy;
+        bas[5] = (-kC2a) * yz;
+        bas[6] = kC2b * ((2.0f * zz - xx) - yy);
+        bas[7] = (-kC2a) * xz;
+        bas[8] = kC2c * (xx - yy);
+        if (deg >= 3) {
+            bas[9] = (-kC3a) * (y * (3.0f * xx - yy));
+            bas[10] = kC3b * (xy * z);
+            bas[11] = (-kC3c) * (y * ((4.0f * zz - xx) - yy));
+            bas[12] = kC3d * (z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
+            bas[13] = (-kC3c) * (x * ((4.0f * zz - xx) - yy));
+            bas[14] = kC3e * (z * (xx - yy));
+            bas[15] = (-kC3a) * (x * (xx - 3.0f * yy));
+        }
+    }
+}
+
+// Gradient of sum_k w_k b_k(dir) with respect to dir, for weights w_k.
+__device__ __forceinline__ float3 sh_basis_vjp(int deg, float x, float y, float z, const float* w) {
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    if (deg >= 1) {
+        gy += -kC1 * w[1];
+        gz += kC1 * w[2];
+        gx += -kC1 * w[3];
+    }
+    if (deg >= 2) {
+        gx += kC2a * y * w[4];
+        gy += kC2a * x * w[4];
+        gy += -kC2a * z * w[5];
+        gz += -kC2a * y * w[5];
+        gx += kC2b * (-2.0f * x) * w[6];
+        gy += kC2b * (-2.0f * y) * w[6];
+        gz += kC2b * (4.0f * z) * w[6];
+        gx += -kC2a * z * w[7];
+        gz += -kC2a * x * w[7];
+        gx += kC2c * (2.0f * x) * w[8];
+        gy += kC2c * (-2.0f * y) * w[8];
+    }
+    if (deg >= 3) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        gx += -kC3a * (6.0f * x * y) * w[9];
+        gy += -kC3a * (3.0f * xx - 3.0f * yy) * w[9];
+        gx += kC3b * (y * z) * w[10];
+        gy += kC3b * (x * z) * w[10];
+        gz += kC3b * (x * y) * w[10];
+        gx += -kC3c * (-2.0f * x * y) * w[11];
+        gy += -kC3c * (4.0f * zz - xx - 3.0f * yy) * w[11];
+        gz += -kC3c * (8.0f * y * z) * w[11];
+        gx += kC3d * (-6.0f * x * z) * w[12];
+        gy += kC3d * (-6.0f * y * z) * w[12];
+        gz += kC3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+        gx += -kC3c * (4.0f * zz - 3.0f * xx - yy) * w[13];
+        gy += -kC3c * (-2.0f * x * y) * w[13];
+        gz += -kC3c * (8.0f * x * z) * w[13];
+        gx += kC3e * (2.0f * x * z) * w[14];
+        gy += kC3e * (-2.0f * y * z) * w[14];
+        gz += kC3e * (xx - yy) * w[14];
+        gx += -kC3a * (3.0f * xx - 3.0f * yy) * w[15];
+        gy += -kC3a * (-6.0f * x * y) * w[15];
+    }
+    return make_float3(gx, gy, gz);
+}
+
 __device__ __forceinline__ uint32_t wave_reduce_add(uint32_t v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -164,30 +237,8 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
                 dist = len;
                 pz = p[2];
                 float bas[16];
-                bas[0] = kC0;
                 const int deg = sc.deg;
-                if (deg >= 1) {
-                    bas[1] = (-kC1) * y;
-                    bas[2] = kC1 * z;
-                    bas[3] = (-kC1) * x;
-                }
-                if (deg >= 2) {
-                    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
-                    bas[4] = kC2a * xy;
-                    bas[5] = (-kC2a) * yz;
-                    bas[6] = kC2b * ((2.0f * zz - xx) - yy);
-                    bas[7] = (-kC2a) * xz;
-                    bas[8] = kC2c * (xx - yy);
-                    if (deg >= 3) {
-                        bas[9] = (-kC3a) * (y * (3.0f * xx - yy));
-                        bas[10] = kC3b * (xy * z);
-                        bas[11] = (-kC3c) * (y * ((4.0f * zz - xx) - yy));
-                        bas[12] = kC3d * (z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
-                        bas[13] = (-kC3c) * (x * ((4.0f * zz - xx) - yy));
-                        bas[14] = kC3e * (z * (xx - yy));
-                        bas[15] = (-kC3a) * (x * (xx - 3.0f * yy));
-                    }
-                }
+                sh_basis(deg, x, y, z, bas);
                 const int K = (deg + 1) * (deg + 1);
                 const float* shp = sc.sh + (size_t)i * 3 * K;
 #pragma unroll
@@ -487,6 +538,191 @@ __global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __re
     if (i + 1 == n || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(i + 1);
 }
 
+struct BwdArgs {
+    SceneArgs sc;
+    DevCam cam;
+    const float4* co;
+    const float* g2;
+    float* dmeans;
+    float* dscales;
+    float* drots;
+    float* dopac;
+    float* dsh;
+};
+
+// Backward of preprocessing (Sec. 3.5 chain rule): from the accumulated
+// gradients of the 2D mean, conic, opacity and colour to the mean, scales,
+// quaternion, opacity and SH coefficients.  The forward quantities are
+// recomputed; clamped colour channels and a clamped frustum coordinate pass
+// no gradient through the clamped variable.
+__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.sc.n) return;
+    const int deg = a.sc.deg, K = (deg + 1) * (deg + 1);
+    float* dsh = a.dsh + (size_t)i * 3 * K;
+    const bool vis = a.co[i].w > 0.0f;
+    if (!vis) {
+        for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.0f;
+        for (int j = 0; j < 3; ++j) a.dmeans[3 * i + j] = a.dscales[3 * i + j] = 0.0f;
+        for (int j = 0; j < 4; ++j) a.drots[4 * i + j] = 0.0f;
+        a.dopac[i] = 0.0f;
+        return;
+    }
+    const DevCam& cam = a.cam;
+    const float* gg = a.g2 + 9 * (size_t)i;
+    const float gmx = gg[0], gmy = gg[1], gca = gg[2], gcb = gg[3], gcc = gg[4], gop = gg[5];
+    const float grgb[3] = {gg[6], gg[7], gg[8]};
+    const float mu[3] = {a.sc.means[3 * i], a.sc.means[3 * i + 1], a.sc.means[3 * i + 2]};
+    const float s[3] = {a.sc.scales[3 * i], a.sc.scales[3 * i + 1], a.sc.scales[3 * i + 2]};
+    const float4 qv = reinterpret_cast<const float4*>(a.sc.rots)[i];
+    const float n2 = ((qv.x * qv.x + qv.y * qv.y) + qv.z * qv.z) + qv.w * qv.w;
+    float nrm = 0.0f, w = 1.0f, x = 0.0f, y = 0.0f, z = 0.0f;
+    if (n2 != 0.0f) {
+        nrm = sqrtf(n2);
+        w = qv.x / nrm; x = qv.y / nrm; y = qv.z / nrm; z = qv.w / nrm;
+    }
+    const float Rq[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
+                            {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
+                            {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
+    float M[3][3], Sg[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) M[j][l] = Rq[j][l] * s[l];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Sg[j][k] = M[j][0] * M[k][0] + M[j][1] * M[k][1] + M[j][2] * M[k][2];
+    float p[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        p[j] = ((cam.R[3 * j] * mu[0] + cam.R[3 * j + 1] * mu[1]) + cam.R[3 * j + 2] * mu[2]) + cam.t[j];
+    const float pz = p[2], pz2 = pz * pz, pz3 = pz2 * pz;
+    const float txtz = p[0] / pz, tytz = p[1] / pz;
+    const bool cx_ = !(-cam.limx <= txtz && txtz <= cam.limx);
+    const bool cy_ = !(-cam.limy <= tytz && tytz <= cam.limy);
+    const float Lx = sel_clamp(txtz, -cam.limx, cam.limx), Ly = sel_clamp(tytz, -cam.limy, cam.limy);
+    const float J00 = cam.fx / pz, J02 = -(cam.fx * Lx) / pz;
+    const float J11 = cam.fy / pz, J12 = -(cam.fy * Ly) / pz;
+    float T[2][3], TS[2][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T[0][k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
+        T[1][k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) TS[j][k] = T[j][0] * Sg[0][k] + T[j][1] * Sg[1][k] + T[j][2] * Sg[2][k];
+    const float ea = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + 0.3f;
+    const float eb = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+    const float ec = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + 0.3f;
+    const float D = ea * ec - eb * eb, D2 = D * D;
+
+    // Colour.  The clamp decision repeats the forward arithmetic exactly.
+    const float dm[3] = {mu[0] - cam.o[0], mu[1] - cam.o[1], mu[2] - cam.o[2]};
+    const float len = sqrtf((dm[0] * dm[0] + dm[1] * dm[1]) + dm[2] * dm[2]);
+    const float dx_ = dm[0] / len, dy_ = dm[1] / len, dz_ = dm[2] / len;
+    float bas[16];
+    sh_basis(deg, dx_, dy_, dz_, bas);
+    const float* shp = a.sc.sh + (size_t)i * 3 * K;
+    float gacc[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = bas[0] * shp[ch];
+        for (int k = 1; k < K; ++k) acc = acc + bas[k] * shp[3 * k + ch];
+        acc = acc + 0.5f;
+        gacc[ch] = acc < 0.0f ? 0.0f : grgb[ch];
+    }
+    float wk[16];
+    for (int k = 0; k < K; ++k) {
+        dsh[3 * k] = bas[k] * gacc[0];
+        dsh[3 * k + 1] = bas[k] * gacc[1];
+        dsh[3 * k + 2] = bas[k] * gacc[2];
+        wk[k] = gacc[0] * shp[3 * k] + gacc[1] * shp[3 * k + 1] + gacc[2] * shp[3 * k + 2];
+    }
+    const float3 gd = sh_basis_vjp(deg, dx_, dy_, dz_, wk);
+    const float dd = dx_ * gd.x + dy_ * gd.y + dz_ * gd.z;
+    float dmu[3] = {(gd.x - dx_ * dd) / len, (gd.y - dy_ * dd) / len, (gd.z - dz_ * dd) / len};
+
+    // Conic (c, -b, a) / D of the 2D covariance (a, b, c).
+    const float ga = gca * (-ec * ec / D2) + gcb * (eb * ec / D2) + gcc * (-eb * eb / D2);
+    const float gb = gca * (2.0f * eb * ec / D2) + gcb * (-1.0f / D - 2.0f * eb * eb / D2) + gcc * (2.0f * ea * eb / D2);
+    const float gc = gca * (-eb * eb / D2) + gcb * (ea * eb / D2) + gcc * (-ea * ea / D2);
+    const float G00 = ga, G01 = 0.5f * gb, G11 = gc;
+    // Sigma_2 = T Sigma T^T: dSigma = T^T G T, dT = 2 G T Sigma.
+    float dSg[3][3], dT[2][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            dSg[j][k] = T[0][j] * (G00 * T[0][k] + G01 * T[1][k]) + T[1][j] * (G01 * T[0][k] + G11 * T[1][k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dT[0][k] = 2.0f * (G00 * TS[0][k] + G01 * TS[1][k]);
+        dT[1][k] = 2.0f * (G01 * TS[0][k] + G11 * TS[1][k]);
+    }
+    float dJ00 = 0.0f, dJ02 = 0.0f, dJ11 = 0.0f, dJ12 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dJ00 += dT[0][k] * cam.R[k];
+        dJ02 += dT[0][k] * cam.R[6 + k];
+        dJ11 += dT[1][k] * cam.R[3 + k];
+        dJ12 += dT[1][k] * cam.R[6 + k];
+    }
+    float gp0 = gmx * cam.fx / pz, gp1 = gmy * cam.fy / pz;
+    float gp2 = -gmx * cam.fx * p[0] / pz2 - gmy * cam.fy * p[1] / pz2;
+    gp2 += dJ00 * (-cam.fx / pz2) + dJ11 * (-cam.fy / pz2);
+    if (!cx_) {
+        gp0 += dJ02 * (-cam.fx / pz2);
+        gp2 += dJ02 * (2.0f * cam.fx * p[0] / pz3);
+    } else {
+        gp2 += dJ02 * (cam.fx * Lx / pz2);
+    }
+    if (!cy_) {
+        gp1 += dJ12 * (-cam.fy / pz2);
+        gp2 += dJ12 * (2.0f * cam.fy * p[1] / pz3);
+    } else {
+        gp2 += dJ12 * (cam.fy * Ly / pz2);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dmu[j] += cam.R[j] * gp0 + cam.R[3 + j] * gp1 + cam.R[6 + j] * gp2;
+
+    // Sigma = M M^T with M = R_q diag(s); then the unit quaternion.
+    float dR[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        float dsl = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float dM = 2.0f * (dSg[j][0] * M[0][l] + dSg[j][1] * M[1][l] + dSg[j][2] * M[2][l]);
+            dsl += dM * Rq[j][l];
+            dR[j][l] = dM * s[l];
+        }
+        a.dscales[3 * i + l] = dsl;
+    }
+    float dq[4];
+    dq[0] = 2.0f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+    dq[1] = 2.0f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0f * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                    w * dR[2][1] - 2.0f * x * dR[2][2]);
+    dq[2] = 2.0f * (-2.0f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                    z * dR[2][1] - 2.0f * y * dR[2][2]);
+    dq[3] = 2.0f * (-2.0f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.0f * z * dR[1][1] +
+                    y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+    if (n2 != 0.0f) {
+        const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+        a.drots[4 * i] = (dq[0] - w * qd) / nrm;
+        a.drots[4 * i + 1] = (dq[1] - x * qd) / nrm;
+        a.drots[4 * i + 2] = (dq[2] - y * qd) / nrm;
+        a.drots[4 * i + 3] = (dq[3] - z * qd) / nrm;
+    } else {
+        for (int j = 0; j < 4; ++j) a.drots[4 * i + j] = 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a.dmeans[3 * i + j] = dmu[j];
+    a.dopac[i] = gop;
+}
+
 __global__ void k_probe_math(const float* a, const float* b, int n, float* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -563,6 +799,15 @@ hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* 
     if (e != hipSuccess) return e;
     if (cap == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, 256)), dim3(256), 0, s, keys, n_ptr, ranges);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* co, const float* grad2d,
+                                      float* dmeans, float* dscales, float* drots, float* dopac, float* dsh,
+                                      hipStream_t s) {
+    if (sc.n == 0) return hipSuccess;
+    BwdArgs a{sc, cam, co, grad2d, dmeans, dscales, drots, dopac, dsh};
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -87,12 +87,24 @@ struct RenderArgs {
     int32_t* blend_ids;
     int max_k;
     float bg0, bg1, bg2;
+    // backward only (grad2d != nullptr): dL/d rgb [3,H,W], the forward image and
+    // transmittance, and the per-Gaussian 2D gradients [N][9] =
+    // (mean x, mean y, conic a, b, c, opacity, r, g, b) accumulated atomically.
+    const float* dL;
+    const float* rgb_in;
+    const float* T_in;
+    float* grad2d;
 };
 
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s);
 bool hier_head_supported(int head);
 // Hierarchical render with head capacity `head` (1..24).
 hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s);
+
+// Per-Gaussian chain from the 2D gradients to the parameters.
+hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* co, const float* grad2d,
+                                      float* dmeans, float* dscales, float* drots, float* dopac, float* dsh,
+                                      hipStream_t s);
 
 hipError_t launch_probe_math(const float* a, const float* b, int n, float* out, hipStream_t s);
 

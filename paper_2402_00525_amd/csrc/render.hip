@@ -27,6 +27,9 @@ namespace gsr {
 
 namespace {
 
+// Kernel modes: forward, forward writing blend-id lists, backward.
+enum { kFwd = 0, kFwdDebug = 1, kBwd = 2 };
+
 constexpr int kBatch = 32;
 constexpr int kTailCap = 64;
 constexpr int kPop = 16;
@@ -63,7 +66,7 @@ struct WaveQueues {
     uint32_t mid[2][16][kMidCap];
 };
 
-template <int K, bool DEBUG>
+template <int K, int MODE>
 struct PixelState {
     float T, C0, C1, C2, D;
     int n;
@@ -72,10 +75,13 @@ struct PixelState {
     uint32_t hid[K + 1];
     float ha[K + 1];
     int hn;
+    // backward only: dL/dC, final colour without background, final transmittance
+    float g0, g1, g2, F0, F1, F2, TN;
+    float px, py;
 };
 
-template <int K, bool DEBUG>
-__device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, DEBUG>& s, int pix, uint32_t id,
+template <int K, int MODE>
+__device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MODE>& s, int pix, uint32_t id,
                                           float alpha, float t) {
     if (s.done) return;
     const float Tn = s.T * (1.0f - alpha);
@@ -88,16 +94,43 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, DEB
     s.C1 = s.C1 + (e.z * alpha) * s.T;
     s.C2 = s.C2 + (e.w * alpha) * s.T;
     s.D = s.D + (t * alpha) * s.T;
-    if (DEBUG) {
+    if (MODE == kFwdDebug) {
         if (s.n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + s.n] = (int32_t)id;
+    }
+    if (MODE == kBwd) {
+        // Sec. 3.5, front to back: everything behind this Gaussian contributes
+        // C - C_i (C_i includes it), and dC/dalpha = c T - (C - C_i + T_N bg) / (1 - alpha).
+        const float w = alpha * s.T;
+        const float inv = 1.0f / (1.0f - alpha);
+        const float ga = s.g0 * (e.y * s.T - ((s.F0 - s.C0) + s.TN * a.bg0) * inv) +
+                         s.g1 * (e.z * s.T - ((s.F1 - s.C1) + s.TN * a.bg1) * inv) +
+                         s.g2 * (e.w * s.T - ((s.F2 - s.C2) + s.TN * a.bg2) * inv);
+        float* g = a.grad2d + 9 * (size_t)id;
+        atomicAdd(g + 6, s.g0 * w);
+        atomicAdd(g + 7, s.g1 * w);
+        atomicAdd(g + 8, s.g2 * w);
+        const float2 m = a.xy[id];
+        const float4 c = a.co[id];
+        const float dx = m.x - s.px, dy = m.y - s.py;
+        const float pw = -0.5f * ((c.x * dx) * dx + (c.z * dy) * dy) - (c.y * dx) * dy;
+        const float G = exp_cw(pw);
+        if (c.w * G < kAlphaMax) {
+            const float gp = ga * alpha;  // d alpha / d power = o G
+            atomicAdd(g + 0, gp * (-c.x * dx - c.y * dy));
+            atomicAdd(g + 1, gp * (-c.z * dy - c.y * dx));
+            atomicAdd(g + 2, gp * (-0.5f * dx * dx));
+            atomicAdd(g + 3, gp * (-dx * dy));
+            atomicAdd(g + 4, gp * (-0.5f * dy * dy));
+            atomicAdd(g + 5, ga * G);
+        }
     }
     s.n += 1;
     s.T = Tn;
 }
 
 // Remove the front of the head and blend it.
-template <int K, bool DEBUG>
-__device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, DEBUG>& s, int pix) {
+template <int K, int MODE>
+__device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, MODE>& s, int pix) {
     const uint64_t k0 = s.hk[0];
     const uint32_t i0 = s.hid[0];
     const float a0 = s.ha[0];
@@ -108,12 +141,12 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
         s.ha[i] = s.ha[i + 1];
     }
     s.hn -= 1;
-    blend_one<K, DEBUG>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)));
+    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)));
 }
 
 // Insertion into the sorted head (s.hn < K + 1 on entry).
-template <int K, bool DEBUG>
-__device__ __forceinline__ void head_insert(PixelState<K, DEBUG>& s, uint64_t key, uint32_t id, float alpha) {
+template <int K, int MODE>
+__device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key, uint32_t id, float alpha) {
     int pos = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) pos += (i < s.hn && s.hk[i] < key) ? 1 : 0;
@@ -136,7 +169,7 @@ __device__ __forceinline__ void head_insert(PixelState<K, DEBUG>& s, uint64_t ke
     s.hn += 1;
 }
 
-template <int K, bool DEBUG>
+template <int K, int MODE>
 struct HierCtx {
     const RenderArgs& a;
     WaveQueues& q;
@@ -147,7 +180,7 @@ struct HierCtx {
     float3 dQ, dP;
     // mid queue state (uniform over the quad)
     int mb, ms, mn;
-    PixelState<K, DEBUG> st;
+    PixelState<K, MODE> st;
 
     __device__ HierCtx(const RenderArgs& a_, WaveQueues& q_) : a(a_), q(q_) {}
 
@@ -162,8 +195,8 @@ struct HierCtx {
                 float alpha;
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
                     const float t = t_opt(g, dP);
-                    head_insert<K, DEBUG>(st, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha);
-                    if (st.hn > K) head_pop_blend<K, DEBUG>(a, st, pix);
+                    head_insert<K, MODE>(st, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha);
+                    if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix);
                 }
             }
         }
@@ -224,7 +257,7 @@ struct HierCtx {
     }
 };
 
-template <int K, bool DEBUG>
+template <int K, int MODE>
 __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     __shared__ WaveQueues s_q[4];
     __shared__ uint32_t s_consumed[4];
@@ -233,7 +266,7 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     WaveQueues& q = s_q[wave];
-    HierCtx<K, DEBUG> h(a, q);
+    HierCtx<K, MODE> h(a, q);
     h.lane = lane;
     h.row = lane >> 4;
     h.j = lane & 15;
@@ -262,6 +295,18 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     h.st.n = 0;
     h.st.done = !h.pix_ok;
     h.st.hn = 0;
+    h.st.px = (float)h.px;
+    h.st.py = (float)h.py;
+    if (MODE == kBwd && h.pix_ok) {
+        const size_t P = (size_t)cam.W * cam.H, p = (size_t)h.pix;
+        h.st.g0 = a.dL[p];
+        h.st.g1 = a.dL[P + p];
+        h.st.g2 = a.dL[2 * P + p];
+        h.st.TN = a.T_in[p];
+        h.st.F0 = a.rgb_in[p] - h.st.TN * a.bg0;
+        h.st.F1 = a.rgb_in[P + p] - h.st.TN * a.bg1;
+        h.st.F2 = a.rgb_in[2 * P + p] - h.st.TN * a.bg2;
+    }
 #pragma unroll
     for (int i = 0; i <= K; ++i) {
         h.st.hk[i] = kInvalidKey;
@@ -365,10 +410,10 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
             }
 #pragma unroll
             for (int i = 0; i <= K; ++i)
-                if (h.st.hn > 0) head_pop_blend<K, DEBUG>(a, h.st, h.pix);
+                if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix);
         }
     }
-    if (h.pix_ok) {
+    if (MODE != kBwd && h.pix_ok) {
         const size_t P = (size_t)cam.W * cam.H;
         const size_t p = (size_t)h.pix;
         a.rgb[p] = h.st.C0 + h.st.T * a.bg0;
@@ -377,12 +422,12 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
         a.depth[p] = h.st.D;
         a.count[p] = h.st.n;
         a.T[p] = h.st.T;
-        if (DEBUG)
+        if (MODE == kFwdDebug)
             for (int k = h.st.n; k < a.max_k; ++k) a.blend_ids[p * a.max_k + k] = -1;
     }
     if (lane == 0) s_consumed[wave] = (b0 < end ? b0 : end) - begin;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (MODE != kBwd && threadIdx.x == 0) {
         uint32_t c = s_consumed[0];
         for (int w = 1; w < 4; ++w) c = s_consumed[w] > c ? s_consumed[w] : c;
         if (c) atomicAdd(a.counters + 1, c);
@@ -465,10 +510,12 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
 template <int K>
 hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
-    if (a.blend_ids)
-        hipLaunchKernelGGL((k_render_hier<K, true>), dim3(tiles), dim3(256), 0, s, a);
+    if (a.grad2d)
+        hipLaunchKernelGGL((k_render_hier<K, kBwd>), dim3(tiles), dim3(256), 0, s, a);
+    else if (a.blend_ids)
+        hipLaunchKernelGGL((k_render_hier<K, kFwdDebug>), dim3(tiles), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_render_hier<K, false>), dim3(tiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_render_hier<K, kFwd>), dim3(tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -45,14 +45,14 @@ class CConfig(C.Structure):
 
 class CLayout(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
-                ("xy", "conic_o", "sw", "zd", "rect", "touched", "offsets", "keys", "values", "ranges",
+                ("xy", "conic_o", "sw", "zd", "rect", "touched", "offsets", "grad2d", "keys", "values", "ranges",
                  "counters", "entry_capacity", "total_bytes")]
 
 
 _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
-           "gsr_render", "gsr_render_debug", "gsr_render_staged", "gsr_sort_passes", "gsr_probe_math",
+           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_sort_passes", "gsr_probe_math",
            "gsr_last_error", "gsr_version")
 
 
@@ -77,6 +77,9 @@ def lib():
         L.gsr_render_debug.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                        C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int32, C.c_void_p, C.c_void_p]
+        L.gsr_render_backward.restype = C.c_int
+        L.gsr_render_backward.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
+                                          C.c_size_t] + [C.c_void_p] * 9
         L.gsr_render_staged.restype = C.c_int
         L.gsr_render_staged.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                         C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -281,3 +284,69 @@ def probe_math(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     out = torch.empty(6 * n, dtype=torch.float32, device=a.device)
     _check(lib().gsr_probe_math(_ptr(a), _ptr(b), n, _ptr(out), _stream()))
     return out.view(6, n)
+
+
+# ---------------------------------------------------------------------------
+# Differentiable rendering (torch.autograd.Function over gsr_render /
+# gsr_render_backward).
+# ---------------------------------------------------------------------------
+_ENTRY_HINTS = {}
+
+
+def _sh_degree(sh: torch.Tensor) -> int:
+    k = int(sh.shape[1])
+    d = {1: 0, 4: 1, 9: 2, 16: 3}.get(k)
+    if d is None:
+        raise GsrError(GSR_EINVAL, "sh must be [N,(d+1)^2,3] with d in 0..3")
+    return d
+
+
+class RenderFunction(torch.autograd.Function):
+    """rgb = render(means, scales, rots, opacities, sh) for one camera, with
+    the hierarchical per-pixel order; the backward re-runs the same order front
+    to back inside the library.  depth, count and T are returned without
+    gradients."""
+
+    @staticmethod
+    def forward(ctx, means, scales, rots, opacities, sh, cam, cfg):
+        ds = DeviceScene(means.detach().contiguous(), scales.detach().contiguous(), rots.detach().contiguous(),
+                         opacities.detach().contiguous(), sh.detach().contiguous(), _sh_degree(sh))
+        key = (ds.n, int(cam.W), int(cam.H))
+        # every call gets its own workspace: the backward needs it untouched
+        r = Renderer(device=means.device, entries_hint=_ENTRY_HINTS.get(key, max(1 << 16, 32 * ds.n)))
+        out = r.render(ds, cam, cfg)
+        _ENTRY_HINTS[key] = int(1.2 * r.counter(ds.n, cam, 0)) + 1024
+        ctx.state = (r, ds, cam, cfg, out)
+        ctx.mark_non_differentiable(out.depth, out.count, out.T)
+        return out.rgb, out.depth, out.count, out.T
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_count, g_T):
+        r, ds, cam, cfg, out = ctx.state
+        g_rgb = g_rgb.contiguous() if g_rgb is not None else torch.zeros_like(out.rgb)
+        dm, dsc, drt = torch.empty_like(ds.means), torch.empty_like(ds.scales), torch.empty_like(ds.rots)
+        dop, dsh = torch.empty_like(ds.opacities), torch.empty_like(ds.sh)
+        sc, cc = ds.c_struct(), camera(cam)
+        _check(lib().gsr_render_backward(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(r.ws), r.ws.numel(),
+                                         _ptr(g_rgb), _ptr(out.rgb), _ptr(out.T), _ptr(dm), _ptr(dsc), _ptr(drt),
+                                         _ptr(dop), _ptr(dsh), _stream()))
+        ctx.state = None
+        return dm, dsc, drt, dop, dsh, None, None
+
+
+def render(means, scales, rots, opacities, sh, cam, cfg: CConfig | None = None):
+    """Differentiable render of one view: returns (rgb [3,H,W], depth, count, T)."""
+    return RenderFunction.apply(means, scales, rots, opacities, sh, cam, cfg or config())
+
+
+def render_backward(renderer: Renderer, scene: DeviceScene, cam, cfg: CConfig, frame: Frame, dL_drgb):
+    """Gradients of a frame rendered with ``renderer.render`` (direct C-ABI call)."""
+    grads = dict(means=torch.empty_like(scene.means), scales=torch.empty_like(scene.scales),
+                 rots=torch.empty_like(scene.rots), opacities=torch.empty_like(scene.opacities),
+                 sh=torch.empty_like(scene.sh))
+    sc, cc = scene.c_struct(), camera(cam)
+    _check(lib().gsr_render_backward(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(renderer.ws), renderer.ws.numel(),
+                                     _ptr(dL_drgb.contiguous()), _ptr(frame.rgb), _ptr(frame.T), _ptr(grads["means"]),
+                                     _ptr(grads["scales"]), _ptr(grads["rots"]), _ptr(grads["opacities"]),
+                                     _ptr(grads["sh"]), _stream()))
+    return grads
