@@ -105,7 +105,8 @@ typedef struct gsr_config {
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
  * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
  * (Gaussian id), ranges uint32[tiles][2] = [start, end) per tile; counters
- * uint32[4] = (entries, entries consumed by the renderer, unused, unused);
+ * uint32[4] = (entries, entries consumed by the renderer, unused, entries needed before clamping
+ * to the capacity, saturated at 2^32 - 1);
  * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb). */
 typedef struct gsr_layout {
     int64_t xy, conic_o, sw, zd, rect, touched, offsets, grad2d;
@@ -181,6 +182,69 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
 
 /* Number of 8-bit radix passes a W x H frame's keys need (tile bits + 32). */
 int gsr_sort_passes(int32_t W, int32_t H);
+
+/* ---------------------------------------------------------------------------
+ * Batched rendering: many views (cameras of any resolution) of several scenes
+ * rendered by one launch sequence.  All views' Gaussians are preprocessed into
+ * one record array, all (view, tile, depth) keys are sorted once, and one
+ * persistent render kernel pulls (tile, 16x4 strip) work items of all views
+ * from an atomic queue, largest tile lists first.  Each view's pixels equal
+ * those of gsr_render for that view (hierarchical order).
+ * ------------------------------------------------------------------------- */
+typedef struct gsr_view {
+    int32_t scene;        /* index into the scenes array */
+    gsr_camera cam;
+    float* rgb;           /* [3,H,W] device outputs of this view */
+    float* depth;         /* [H,W] */
+    int32_t* count;       /* [H,W] */
+    float* T;             /* [H,W] */
+} gsr_view;
+
+/* Launch parameters that change speed only, never results. */
+typedef struct gsr_schedule {
+    int32_t wgs_per_cu;   /* persistent render grid = compute units x this (1..8) */
+    int32_t cost_order;   /* 1: tiles with the longest lists first; 0: view order */
+    int32_t lb_threshold; /* see gsr_config */
+} gsr_schedule;
+
+typedef struct gsr_batch gsr_batch; /* opaque host-side plan */
+
+/* Workspace for a batch with room for entries_max (view, tile, Gaussian)
+ * entries in total; 0 for an invalid batch. */
+size_t gsr_batch_workspace_bytes(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
+                                 int64_t entries_max);
+
+void gsr_default_schedule(gsr_schedule* sched /* host */);
+
+/* Plan a batch (host arrays; the scenes' device arrays and the views' outputs
+ * must stay valid while the plan is used).  Copies a per-view table into ws
+ * with a blocking copy, so call it outside stream capture.  sched may be NULL
+ * (default).  Only the hierarchical order is supported. */
+int gsr_batch_create(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
+                     const gsr_config* cfg, const gsr_schedule* sched, void* ws, size_t ws_bytes, gsr_batch** out);
+
+/* Enqueue the whole batch on `stream`: kernel launches only (no allocation,
+ * no host synchronisation, no memset nodes), so the call can be captured
+ * into a HIP graph and replayed.  Overflow sets bit 0 of *status_dev. */
+int gsr_batch_render(gsr_batch* batch, int32_t* status_dev, gsr_stream_t stream);
+
+int gsr_batch_set_schedule(gsr_batch* batch, const gsr_schedule* sched);
+int gsr_batch_get_schedule(const gsr_batch* batch, gsr_schedule* sched);
+
+/* Autotuner: times every candidate schedule (persistent grid 1-3 workgroups
+ * per compute unit, cost order on/off, load-balancing threshold 16/32/64) with
+ * `repeats` renders each, keeps the fastest in the plan and returns it.  With
+ * cache_path, a schedule stored for the same device and batch shape is reused
+ * without timing, and a new result is appended.  Synchronises the stream. */
+int gsr_batch_tune(gsr_batch* batch, int32_t* status_dev, gsr_stream_t stream, const char* cache_path,
+                   int32_t repeats, gsr_schedule* best, float* best_ms);
+
+int64_t gsr_batch_records(const gsr_batch* batch);        /* total Gaussian records */
+int64_t gsr_batch_tiles(const gsr_batch* batch);          /* total 16x16 tiles */
+int64_t gsr_batch_entry_capacity(const gsr_batch* batch); /* entries the workspace holds */
+int64_t gsr_batch_counters_offset(const gsr_batch* batch);/* byte offset of uint32 counters[4] in ws:
+                                                             (entries, queue head, tiles, entries needed) */
+void gsr_batch_destroy(gsr_batch* batch);
 
 /* Element-wise arithmetic probe of the device (diagnostic): for n inputs
  * a[i], b[i] writes out[k*n + i] for k = 0..5:

@@ -1,8 +1,12 @@
 // Host side of the C ABI: argument validation, workspace layout and the
 // stream-ordered launch sequence of a frame.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
+#include <vector>
 
 #include "../../include/gsr.h"
 #include "gsr_internal.h"
@@ -177,7 +181,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, b, s)) != hipSuccess) return fail_hip(e, "preprocess");
     if ((e = mark(1)) != hipSuccess) return fail_hip(e, "event");
     if ((e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
-                              s)) != hipSuccess)
+                              s, b.counters + 3)) != hipSuccess)
         return fail_hip(e, "scan");
     if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, b, passes & 1, status_dev, s)) != hipSuccess)
         return fail_hip(e, "duplicate");
@@ -270,9 +274,367 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     return GSR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched rendering: many views of several scenes in one launch sequence.
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+    int64_t views, xy, co, sw, zd, rect, touched, offsets, ranges, counters;
+    int64_t keys[2], vals[2], hist, partial;
+    int64_t tkeys[2], tvals[2], thist, tpartial;
+    int64_t cap, total;
+};
+
+void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, BatchLayout* L) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L->views = take((int64_t)sizeof(gsr::ViewDev) * n_views);
+    L->xy = take(8 * R);
+    L->co = take(16 * R);
+    L->sw = take(48 * R);
+    L->zd = take(8 * R);
+    L->rect = take(16 * R);
+    L->touched = take(4 * R);
+    L->offsets = take(4 * R);
+    L->ranges = take(8 * tiles);
+    L->counters = take(64);
+    const int64_t nbt = (int64_t)gsr::sort_blocks((size_t)tiles);
+    L->tkeys[0] = take(8 * tiles);
+    L->tkeys[1] = take(8 * tiles);
+    L->tvals[0] = take(4 * tiles);
+    L->tvals[1] = take(4 * tiles);
+    L->thist = take(4 * 256 * nbt);
+    L->tpartial = take(4 * ((int64_t)gsr::scan_partial_len((size_t)nbt * 256) + 2));
+    const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
+    L->partial = take(4 * ((int64_t)std::max(gsr::scan_partial_len((size_t)R), gsr::scan_partial_len((size_t)nb * 256)) + 2));
+    L->hist = take(4 * 256 * nb);
+    L->keys[0] = take(8 * cap);
+    L->keys[1] = take(8 * cap);
+    L->vals[0] = take(4 * cap);
+    L->vals[1] = take(4 * cap);
+    L->cap = cap;
+    L->total = off;
+}
+
+}  // namespace
+
+struct gsr_batch {
+    std::vector<gsr_scene> scenes;
+    std::vector<gsr_view> views;
+    gsr_config cfg;
+    gsr_schedule sched;
+    char* ws;
+    size_t ws_bytes;
+    BatchLayout L;
+    int64_t R, tiles;
+    std::vector<int64_t> rec_base, tile_base;
+    int cu_count;
+};
+
+namespace {
+
+int validate_batch(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
+                   int64_t* R, int64_t* tiles) {
+    if (!scenes || n_scenes <= 0 || !views || n_views <= 0) return fail(GSR_EINVAL, "empty batch");
+    for (int i = 0; i < n_scenes; ++i)
+        if (int rc = check_scene(&scenes[i])) return rc;
+    *R = 0;
+    *tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (views[v].scene < 0 || views[v].scene >= n_scenes) return fail(GSR_EINVAL, "view scene index out of range");
+        if (int rc = check_camera(&views[v].cam)) return rc;
+        if (!views[v].rgb || !views[v].depth || !views[v].count || !views[v].T)
+            return fail(GSR_EINVAL, "view output is NULL");
+        *R += scenes[views[v].scene].n;
+        *tiles += tiles_of(views[v].cam.W, views[v].cam.H);
+    }
+    if (*R >= ((int64_t)1 << 32) - 1 || *tiles >= ((int64_t)1 << 31)) return fail(GSR_EINVAL, "batch too large");
+    return GSR_OK;
+}
+
+int batch_capacity(int64_t R, int64_t tiles, int64_t n_views, size_t ws_bytes, BatchLayout* L) {
+    int64_t lo = 0, hi = ((int64_t)1 << 31) - 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        batch_layout_for(R, tiles, n_views, mid, L);
+        if (L->total <= (int64_t)ws_bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    if (lo <= 0) return GSR_ECAPACITY;
+    batch_layout_for(R, tiles, n_views, lo, L);
+    return GSR_OK;
+}
+
+int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
+    char* base = b->ws;
+    const BatchLayout& L = b->L;
+    gsr::FrameBufs fb;
+    fb.xy = (float2*)(base + L.xy);
+    fb.co = (float4*)(base + L.co);
+    fb.sw = (float4*)(base + L.sw);
+    fb.zd = (float2*)(base + L.zd);
+    fb.rect = (int4*)(base + L.rect);
+    fb.touched = (uint32_t*)(base + L.touched);
+    fb.offsets = (uint32_t*)(base + L.offsets);
+    fb.scan_partial = (uint32_t*)(base + L.partial);
+    fb.hist = (uint32_t*)(base + L.hist);
+    fb.keys[0] = (uint64_t*)(base + L.keys[0]);
+    fb.keys[1] = (uint64_t*)(base + L.keys[1]);
+    fb.vals[0] = (uint32_t*)(base + L.vals[0]);
+    fb.vals[1] = (uint32_t*)(base + L.vals[1]);
+    fb.ranges = (uint32_t*)(base + L.ranges);
+    fb.counters = (uint32_t*)(base + L.counters);
+    fb.capacity = (uint32_t)L.cap;
+    const int key_bits = 32 + bits_for_tiles((int)b->tiles);
+    const int passes = (key_bits + 7) / 8;
+    const int lb = b->sched.lb_threshold;
+    hipError_t e;
+    if ((e = gsr::launch_fill_u32(fb.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
+    if ((e = gsr::launch_fill_u32(fb.counters + 2, 1, (uint32_t)b->tiles, s)) != hipSuccess) return fail_hip(e, "clear");
+    auto shifted = [&](int64_t r0) {
+        gsr::FrameBufs v = fb;
+        v.xy += r0;
+        v.co += r0;
+        v.sw += 3 * r0;
+        v.zd += r0;
+        v.rect += r0;
+        v.touched += r0;
+        v.offsets += r0;
+        return v;
+    };
+    for (size_t v = 0; v < b->views.size(); ++v) {
+        const gsr_scene& sc = b->scenes[b->views[v].scene];
+        const gsr::SceneArgs sa{sc.n, sc.sh_degree, sc.means, sc.scales, sc.rots, sc.opacities, sc.sh};
+        if ((e = gsr::launch_preprocess(sa, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, shifted(b->rec_base[v]), s)) !=
+            hipSuccess)
+            return fail_hip(e, "preprocess");
+    }
+    if ((e = gsr::launch_scan(fb.touched, fb.offsets, (size_t)b->R, fb.scan_partial, fb.counters, fb.capacity,
+                              status_dev, s, fb.counters + 3)) != hipSuccess)
+        return fail_hip(e, "scan");
+    for (size_t v = 0; v < b->views.size(); ++v) {
+        const gsr_scene& sc = b->scenes[b->views[v].scene];
+        if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, shifted(b->rec_base[v]),
+                                       passes & 1, status_dev, s, (uint32_t)b->tile_base[v], (uint32_t)b->rec_base[v])) !=
+            hipSuccess)
+            return fail_hip(e, "duplicate");
+    }
+    int res = 0;
+    if ((e = gsr::launch_sort(fb, key_bits, &res, s)) != hipSuccess) return fail_hip(e, "sort");
+    if ((e = gsr::launch_ranges(fb.keys[res], fb.counters, fb.ranges, fb.capacity, (int)b->tiles, s)) != hipSuccess)
+        return fail_hip(e, "ranges");
+    const uint32_t* order = nullptr;
+    if (b->sched.cost_order) {
+        uint64_t* tk[2] = {(uint64_t*)(base + L.tkeys[0]), (uint64_t*)(base + L.tkeys[1])};
+        uint32_t* tv[2] = {(uint32_t*)(base + L.tvals[0]), (uint32_t*)(base + L.tvals[1])};
+        if ((e = gsr::launch_tile_cost_keys(fb.ranges, (uint32_t)b->tiles, tk[0], tv[0], s)) != hipSuccess)
+            return fail_hip(e, "tile costs");
+        int tres = 0;
+        if ((e = gsr::launch_sort_pairs(tk, tv, fb.counters + 2, (size_t)b->tiles, (uint32_t*)(base + L.thist),
+                                        (uint32_t*)(base + L.tpartial), 32, 0, &tres, s)) != hipSuccess)
+            return fail_hip(e, "tile order");
+        order = tv[tres];
+    }
+    gsr::BatchArgs ba;
+    ba.views = (const gsr::ViewDev*)(base + L.views);
+    ba.n_views = (int)b->views.size();
+    ba.n_records = (uint32_t)b->R;
+    ba.xy = fb.xy;
+    ba.co = fb.co;
+    ba.sw = fb.sw;
+    ba.zd = fb.zd;
+    ba.vals = fb.vals[res];
+    ba.ranges = fb.ranges;
+    ba.order = order;
+    ba.queue = fb.counters + 1;
+    ba.n_items = (uint32_t)(4 * b->tiles);
+    ba.bg0 = b->cfg.bg[0];
+    ba.bg1 = b->cfg.bg[1];
+    ba.bg2 = b->cfg.bg[2];
+    const unsigned grid = (unsigned)(b->cu_count * std::max(1, b->sched.wgs_per_cu));
+    if ((e = gsr::launch_render_hier_batch(ba, b->cfg.head, grid, s)) != hipSuccess) return fail_hip(e, "render");
+    return GSR_OK;
+}
+
+std::string batch_key(const gsr_batch* b) {
+    std::ostringstream k;
+    k << "gfx950-" << b->cu_count << "cu-views" << b->views.size() << "-records" << b->R << "-tiles" << b->tiles
+      << "-head" << b->cfg.head;
+    return k.str();
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t gsr_batch_workspace_bytes(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
+                                 int64_t entries_max) {
+    int64_t R, tiles;
+    if (validate_batch(scenes, n_scenes, views, n_views, &R, &tiles) || entries_max < 1 ||
+        entries_max > ((int64_t)1 << 31) - 1)
+        return 0;
+    BatchLayout L;
+    batch_layout_for(R, tiles, n_views, entries_max, &L);
+    return (size_t)L.total;
+}
+
+void gsr_default_schedule(gsr_schedule* s) {
+    if (!s) return;
+    s->wgs_per_cu = 2;
+    s->cost_order = 1;
+    s->lb_threshold = 32;
+}
+
+int gsr_batch_create(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
+                     const gsr_config* cfg, const gsr_schedule* sched, void* ws, size_t ws_bytes, gsr_batch** out) {
+    if (!out) return fail(GSR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int64_t R, tiles;
+    if (int rc = validate_batch(scenes, n_scenes, views, n_views, &R, &tiles)) return rc;
+    if (!cfg) return fail(GSR_EINVAL, "config is NULL");
+    if (int rc = gsr_check_config(cfg)) return rc;
+    if (cfg->mode != GSR_MODE_HIER) return fail(GSR_EUNSUPPORTED, "batches render the hierarchical order");
+    if (!gsr::hier_head_supported(cfg->head)) return fail(GSR_EUNSUPPORTED, "head size not built");
+    if (!ws || ((uintptr_t)ws & 255) != 0) return fail(GSR_EINVAL, "workspace NULL or not 256-byte aligned");
+    gsr_batch* b = new gsr_batch();
+    b->scenes.assign(scenes, scenes + n_scenes);
+    b->views.assign(views, views + n_views);
+    b->cfg = *cfg;
+    if (sched)
+        b->sched = *sched;
+    else
+        gsr_default_schedule(&b->sched);
+    if (b->sched.wgs_per_cu < 1 || b->sched.wgs_per_cu > 8 || b->sched.lb_threshold < 0) {
+        delete b;
+        return fail(GSR_EINVAL, "bad schedule");
+    }
+    b->ws = (char*)ws;
+    b->ws_bytes = ws_bytes;
+    b->R = R;
+    b->tiles = tiles;
+    if (batch_capacity(R, tiles, n_views, ws_bytes, &b->L)) {
+        delete b;
+        return fail(GSR_ECAPACITY, "workspace too small for the batch");
+    }
+    std::vector<gsr::ViewDev> vd(n_views);
+    int64_t r = 0, t = 0;
+    for (int v = 0; v < n_views; ++v) {
+        b->rec_base.push_back(r);
+        b->tile_base.push_back(t);
+        vd[v].cam = make_cam(&views[v].cam);
+        vd[v].rgb = views[v].rgb;
+        vd[v].depth = views[v].depth;
+        vd[v].count = views[v].count;
+        vd[v].T = views[v].T;
+        vd[v].tile_base = (uint32_t)t;
+        vd[v].rec_base = (uint32_t)r;
+        r += scenes[views[v].scene].n;
+        t += tiles_of(views[v].cam.W, views[v].cam.H);
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipMemcpy(b->ws + b->L.views, vd.data(), sizeof(gsr::ViewDev) * n_views, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete b;
+        return fail_hip(e, "batch create");
+    }
+    *out = b;
+    return GSR_OK;
+}
+
+int gsr_batch_render(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream) {
+    if (!b || !status_dev) return fail(GSR_EINVAL, "batch or status is NULL");
+    return batch_render_impl(b, status_dev, (hipStream_t)stream);
+}
+
+int gsr_batch_set_schedule(gsr_batch* b, const gsr_schedule* sched) {
+    if (!b || !sched || sched->wgs_per_cu < 1 || sched->wgs_per_cu > 8 || sched->lb_threshold < 0)
+        return fail(GSR_EINVAL, "bad schedule");
+    b->sched = *sched;
+    return GSR_OK;
+}
+
+int gsr_batch_get_schedule(const gsr_batch* b, gsr_schedule* sched) {
+    if (!b || !sched) return fail(GSR_EINVAL, "NULL argument");
+    *sched = b->sched;
+    return GSR_OK;
+}
+
+int64_t gsr_batch_records(const gsr_batch* b) { return b ? b->R : -1; }
+int64_t gsr_batch_tiles(const gsr_batch* b) { return b ? b->tiles : -1; }
+int64_t gsr_batch_entry_capacity(const gsr_batch* b) { return b ? b->L.cap : -1; }
+int64_t gsr_batch_counters_offset(const gsr_batch* b) { return b ? b->L.counters : -1; }
+
+int gsr_batch_tune(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream, const char* cache_path, int32_t repeats,
+                   gsr_schedule* best_out, float* best_ms) {
+    if (!b || !status_dev) return fail(GSR_EINVAL, "batch or status is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = batch_key(b);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string k;
+        gsr_schedule c;
+        float ms;
+        while (in >> k >> c.wgs_per_cu >> c.cost_order >> c.lb_threshold >> ms) {
+            if (k == key) {
+                b->sched = c;
+                if (best_out) *best_out = c;
+                if (best_ms) *best_ms = ms;
+                return GSR_OK;
+            }
+        }
+    }
+    // Every candidate renders the same pixels: only speed differs.
+    std::vector<gsr_schedule> cands;
+    for (int w : {1, 2, 3})
+        for (int c : {0, 1})
+            for (int lb : {16, 32, 64}) cands.push_back(gsr_schedule{w, c, lb});
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(GSR_EDEVICE, "event");
+    float best = 1e30f;
+    gsr_schedule bs = b->sched;
+    const int reps = repeats > 0 ? repeats : 3;
+    int rc = GSR_OK;
+    for (const gsr_schedule& c : cands) {
+        b->sched = c;
+        if ((rc = batch_render_impl(b, status_dev, s))) break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !rc; ++r) rc = batch_render_impl(b, status_dev, s);
+        hipEventRecord(e1, s);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(GSR_EDEVICE, "tune sync");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms < best) {
+            best = ms;
+            bs = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->sched = bs;
+    if (rc) return rc;
+    if (best_out) *best_out = bs;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        std::ofstream o(cache_path, std::ios::app);
+        o << key << " " << bs.wgs_per_cu << " " << bs.cost_order << " " << bs.lb_threshold << " " << best << "\n";
+    }
+    return GSR_OK;
+}
+
+void gsr_batch_destroy(gsr_batch* b) { delete b; }
+
 
 size_t gsr_workspace_bytes(int64_t n, int32_t W, int32_t H, int64_t entries_max) {
     if (n < 0 || W <= 0 || H <= 0 || entries_max < 1 || entries_max > ((int64_t)1 << 31) - 1) return 0;

@@ -358,12 +358,13 @@ struct DupArgs {
     uint32_t* vals;
     uint32_t capacity;
     int32_t* status;
+    uint32_t tile_base, id_base;
 };
 
 __device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32_t tile, uint32_t dbits, uint32_t id) {
     if (pos < a.capacity) {
-        a.keys[pos] = ((uint64_t)tile << 32) | (uint64_t)dbits;
-        a.vals[pos] = id;
+        a.keys[pos] = ((uint64_t)(tile + a.tile_base) << 32) | (uint64_t)dbits;
+        a.vals[pos] = id + a.id_base;
     } else {
         atomicOr(a.status, 1);
     }
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 
 // One block: exclusive scan of the partial sums (64-bit running total).
 __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, size_t np, uint32_t* total_out,
-                                                        uint32_t clamp, int32_t* status) {
+                                                        uint32_t clamp, int32_t* status, uint32_t* raw_total) {
     __shared__ uint32_t lw[16];
     unsigned long long carry = 0;
     for (size_t b0 = 0; b0 < np; b0 += blockDim.x) {
@@ -494,6 +495,7 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, size_
         if (j < np) partial[j] = (uint32_t)(carry + ex);
         carry += tot;
     }
+    if (threadIdx.x == 0 && raw_total) *raw_total = carry > 0xffffffffull ? 0xffffffffu : (uint32_t)carry;
     if (threadIdx.x == 0 && total_out) {
         if (carry > (unsigned long long)clamp) {
             if (status) atomicOr(status, 1);
@@ -758,20 +760,21 @@ hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, i
 }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* partial, uint32_t* total,
-                       uint32_t clamp, int32_t* status, hipStream_t s) {
+                       uint32_t clamp, int32_t* status, hipStream_t s, uint32_t* raw_total) {
     const size_t nb = scan_partial_len(n);
     if (n == 0) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, total, (size_t)1, 0u);
+        if (total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, total, (size_t)1, 0u);
+        if (raw_total) hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, raw_total, (size_t)1, 0u);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, total, clamp, status);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partial, nb, total, clamp, status, raw_total);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)partial);
     return hipGetLastError();
 }
 
 hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
-                            hipStream_t s) {
+                            hipStream_t s, uint32_t tile_base, uint32_t id_base) {
     if (n == 0) return hipSuccess;
     DupArgs a;
     a.cam = cam;
@@ -789,6 +792,8 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const Fr
     a.vals = b.vals[buf];
     a.capacity = b.capacity;
     a.status = status;
+    a.tile_base = tile_base;
+    a.id_base = id_base;
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

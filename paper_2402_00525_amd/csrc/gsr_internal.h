@@ -55,18 +55,30 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
                              hipStream_t s);
 // Exclusive scan of n uint32 values; the total (clamped to `clamp`) goes to
-// *total, and `status` gets the overflow bit if the total exceeds `clamp`.
+// *total, and `status` gets the overflow bit if the total exceeds `clamp`;
+// raw_total (optional) receives the unclamped total, saturated at 2^32 - 1.
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* partial, uint32_t* total,
-                       uint32_t clamp, int32_t* status, hipStream_t s);
-// Writes the unsorted entries into key/value buffer `buf`.
+                       uint32_t clamp, int32_t* status, hipStream_t s, uint32_t* raw_total = nullptr);
+// Writes the unsorted entries into key/value buffer `buf`; tile ids are
+// offset by tile_base and Gaussian ids by id_base (zero for one view).
 hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
-                            hipStream_t s);
+                            hipStream_t s, uint32_t tile_base = 0, uint32_t id_base = 0);
 // Stable LSD radix sort of the first counters[0] (key, value) pairs on the
 // low `bits` key bits; returns the buffer index (0/1) holding the result.
 // `scatter_events` (optional): 2 events per pass recorded right before and
 // after that pass's scatter launch.
 hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s,
                        void* const* scatter_events = nullptr);
+// Stable LSD sort of the first *n_ptr pairs of (keys[start], vals[start]) on
+// the low `bits` key bits, for at most `cap` pairs; the result lands in
+// buffer start ^ (passes & 1), returned in *result_buf.  hist holds
+// 256 * sort_blocks(cap) words, partial scan_partial_len(256 * sort_blocks(cap)) + 2.
+hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], const uint32_t* n_ptr, size_t cap,
+                             uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
+                             void* const* scatter_events = nullptr);
+// Cost keys for ordering tiles: key[t] = ~(list length of tile t), val[t] = t.
+hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals,
+                                 hipStream_t s);
 hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
                          hipStream_t s);
 
@@ -96,7 +108,35 @@ struct RenderArgs {
     float* grad2d;
 };
 
+// Per-view descriptor of a batch, in device memory.
+struct ViewDev {
+    DevCam cam;
+    float* rgb;
+    float* depth;
+    int32_t* count;
+    float* T;
+    uint32_t tile_base;  // first global tile id of this view
+    uint32_t rec_base;   // first record of this view
+};
+
+struct BatchArgs {
+    const ViewDev* views;
+    int n_views;
+    uint32_t n_records;
+    const float2* xy;
+    const float4* co;
+    const float4* sw;
+    const float2* zd;
+    const uint32_t* vals;
+    const uint32_t* ranges;   // per global tile
+    const uint32_t* order;    // global tiles in work order (nullptr: natural order)
+    uint32_t* queue;          // work-queue head, zero before the launch
+    uint32_t n_items;         // 4 strips per global tile
+    float bg0, bg1, bg2;
+};
+
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s);
+hipError_t launch_render_hier_batch(const BatchArgs& b, int head, unsigned grid, hipStream_t s);
 bool hier_head_supported(int head);
 // Hierarchical render with head capacity `head` (1..24).
 hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s);

@@ -257,15 +257,15 @@ struct HierCtx {
     }
 };
 
+// One wavefront renders one 16x4 strip (`strip` = 0..3) of four 4x4 sub-tiles
+// of tile `tile` (image tile index); its list is ranges[range_tile].  Returns
+// the number of list entries the wavefront read before its pixels finished.
 template <int K, int MODE>
-__global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
-    __shared__ WaveQueues s_q[4];
-    __shared__ uint32_t s_consumed[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, int range_tile, int strip,
+                                                 WaveQueues& q) {
+    const int lane = threadIdx.x & 63, wave = strip;
     const DevCam& cam = a.cam;
-    const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    WaveQueues& q = s_q[wave];
     HierCtx<K, MODE> h(a, q);
     h.lane = lane;
     h.row = lane >> 4;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     int tb = 0, ts = 0, tn = 0;  // tail state, uniform over the row
     const int row = h.row, j = h.j;
 
-    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const uint32_t begin = a.ranges[2 * range_tile], end = a.ranges[2 * range_tile + 1];
     uint32_t b0 = begin;
     for (; b0 < end; b0 += kBatch) {
         const uint64_t live = __ballot(!h.st.done);
@@ -425,12 +425,76 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
         if (MODE == kFwdDebug)
             for (int k = h.st.n; k < a.max_k; ++k) a.blend_ids[p * a.max_k + k] = -1;
     }
-    if (lane == 0) s_consumed[wave] = (b0 < end ? b0 : end) - begin;
+    return (b0 < end ? b0 : end) - begin;
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
+    __shared__ WaveQueues s_q[4];
+    __shared__ uint32_t s_consumed[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t c = render_strip<K, MODE>(a, blockIdx.x, blockIdx.x, wave, s_q[wave]);
+    if (lane == 0) s_consumed[wave] = c;
     __syncthreads();
     if (MODE != kBwd && threadIdx.x == 0) {
-        uint32_t c = s_consumed[0];
-        for (int w = 1; w < 4; ++w) c = s_consumed[w] > c ? s_consumed[w] : c;
-        if (c) atomicAdd(a.counters + 1, c);
+        uint32_t m = s_consumed[0];
+        for (int w = 1; w < 4; ++w) m = s_consumed[w] > m ? s_consumed[w] : m;
+        if (m) atomicAdd(a.counters + 1, m);
+    }
+}
+
+// Persistent form over many views: every wavefront pulls (tile, strip) work
+// items from one atomic queue until the queue is empty; tiles are taken in
+// the order given by `order` (largest lists first when cost-ordered), so
+// views of very different sizes share the machine.  Every wavefront leaves
+// the loop once the queue is exhausted.
+template <int K>
+__global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
+    __shared__ WaveQueues s_q[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(b.queue, 1u);
+        item = (uint32_t)__shfl((int)item, 0);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= b.n_items) break;
+        const uint32_t slot = item >> 2;
+        const uint32_t gt = b.order ? b.order[slot] : slot;
+        // view of global tile gt: the last view whose first tile is <= gt
+        int lo = 0, hi = b.n_views - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.views[mid].tile_base <= gt)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int v = __builtin_amdgcn_readfirstlane(lo);
+        const ViewDev& vd = b.views[v];
+        RenderArgs a;
+        a.cam = vd.cam;
+        a.n = b.n_records;
+        a.xy = b.xy;
+        a.co = b.co;
+        a.sw = b.sw;
+        a.zd = b.zd;
+        a.vals = b.vals;
+        a.ranges = b.ranges;
+        a.counters = nullptr;
+        a.rgb = vd.rgb;
+        a.depth = vd.depth;
+        a.count = vd.count;
+        a.T = vd.T;
+        a.blend_ids = nullptr;
+        a.max_k = 0;
+        a.bg0 = b.bg0;
+        a.bg1 = b.bg1;
+        a.bg2 = b.bg2;
+        a.dL = nullptr;
+        a.rgb_in = nullptr;
+        a.T_in = nullptr;
+        a.grad2d = nullptr;
+        render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave]);
     }
 }
 
@@ -542,6 +606,28 @@ hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s) {
         case 16: return launch_hier_k<16>(a, s);
         case 20: return launch_hier_k<20>(a, s);
         case 24: return launch_hier_k<24>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int K>
+hipError_t launch_hier_batch_k(const BatchArgs& b, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_hier_batch<K>, dim3(grid), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_hier_batch(const BatchArgs& b, int head, unsigned grid, hipStream_t s) {
+    switch (head) {
+        case 1: return launch_hier_batch_k<1>(b, grid, s);
+        case 2: return launch_hier_batch_k<2>(b, grid, s);
+        case 3: return launch_hier_batch_k<3>(b, grid, s);
+        case 4: return launch_hier_batch_k<4>(b, grid, s);
+        case 6: return launch_hier_batch_k<6>(b, grid, s);
+        case 8: return launch_hier_batch_k<8>(b, grid, s);
+        case 12: return launch_hier_batch_k<12>(b, grid, s);
+        case 16: return launch_hier_batch_k<16>(b, grid, s);
+        case 20: return launch_hier_batch_k<20>(b, grid, s);
+        case 24: return launch_hier_batch_k<24>(b, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -90,25 +90,52 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
 
 }  // namespace
 
-hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s, void* const* scatter_events) {
-    const size_t nb = sort_blocks(b.capacity);
+hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], const uint32_t* n_ptr, size_t cap,
+                             uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
+                             void* const* scatter_events) {
+    const size_t nb = sort_blocks(cap);
     const int passes = (bits + 7) / 8;
-    // Duplication writes into buffer (passes & 1) so that the result lands in buffer 0.
-    int cur = passes & 1;
+    int cur = start;
+    hipError_t e = hipSuccess;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)b.keys[cur],
-                           (const uint32_t*)b.counters, shift, b.hist, (uint32_t)nb);
-        hipError_t e = launch_scan(b.hist, b.hist, nb * 256, b.scan_partial, nullptr, 0xffffffffu, nullptr, s);
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)keys[cur], n_ptr,
+                           shift, hist, (uint32_t)nb);
+        e = launch_scan(hist, hist, nb * 256, partial, nullptr, 0xffffffffu, nullptr, s);
         if (e != hipSuccess) return e;
         if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p], s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)b.keys[cur],
-                           (const uint32_t*)b.vals[cur], b.keys[cur ^ 1], b.vals[cur ^ 1], (const uint32_t*)b.counters,
-                           shift, (const uint32_t*)b.hist, (uint32_t)nb);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)keys[cur],
+                           (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, (const uint32_t*)hist,
+                           (uint32_t)nb);
         if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p + 1], s)) != hipSuccess) return e;
         cur ^= 1;
     }
     *result_buf = cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s, void* const* scatter_events) {
+    // Duplication writes into buffer (passes & 1) so that the result lands in buffer 0.
+    const int passes = (bits + 7) / 8;
+    return launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, bits, passes & 1,
+                             result_buf, s, scatter_events);
+}
+
+namespace {
+__global__ void k_tile_cost_keys(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint64_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t len = ranges[2 * (size_t)t + 1] - ranges[2 * (size_t)t];
+    keys[t] = (uint64_t)(~len);
+    vals[t] = t;
+}
+}  // namespace
+
+hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals,
+                                 hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_cost_keys, dim3((n_tiles + 255) / 256), dim3(256), 0, s, ranges, n_tiles, keys, vals);
     return hipGetLastError();
 }
 

@@ -237,8 +237,8 @@ class Renderer:
             st = int(self.status.item())
             if not (st & STATUS_OVERFLOW):
                 return out
-            need = int(self.counter(scene.n, cam, 0, raw_total=True))
-            self.plan(scene.n, cam.W, cam.H, max(2 * need, 2 * self.capacity(scene.n, cam)))
+            need = self.counter(scene.n, cam, 3) & 0xffffffff
+            self.plan(scene.n, cam.W, cam.H, max(int(need * 1.05) + 1024, 2 * self.capacity(scene.n, cam)))
         raise GsrError(GSR_ECAPACITY, "tile entries keep overflowing the workspace")
 
     # ----- workspace inspection (debugging / tests) -----
@@ -251,12 +251,9 @@ class Renderer:
         nbytes = count * torch.tensor([], dtype=dtype).element_size()
         return self.ws[off:off + nbytes].view(dtype)
 
-    def counter(self, n, cam, k, raw_total=False):
+    def counter(self, n, cam, k):
+        """counters[k]: 0 entries, 1 entries consumed by the renderer, 3 entries needed."""
         c = self.region(n, cam, "counters", torch.int32, 4)
-        if raw_total:
-            # entries needed = sum of per-Gaussian counts (the clamped total may be smaller)
-            t = self.region(n, cam, "touched", torch.int32, n)
-            return int(t.to(torch.int64).sum().item())
         return int(c[k].item())
 
     def records(self, n, cam):
@@ -350,3 +347,177 @@ def render_backward(renderer: Renderer, scene: DeviceScene, cam, cfg: CConfig, f
                                      _ptr(grads["scales"]), _ptr(grads["rots"]), _ptr(grads["opacities"]),
                                      _ptr(grads["sh"]), _stream()))
     return grads
+
+
+# ---------------------------------------------------------------------------
+# Batched rendering (gsr_batch_*)
+# ---------------------------------------------------------------------------
+class CView(C.Structure):
+    _fields_ = [("scene", C.c_int32), ("cam", CCamera), ("rgb", C.c_void_p), ("depth", C.c_void_p),
+                ("count", C.c_void_p), ("T", C.c_void_p)]
+
+
+class CSchedule(C.Structure):
+    _fields_ = [("wgs_per_cu", C.c_int32), ("cost_order", C.c_int32), ("lb_threshold", C.c_int32)]
+
+
+_BATCH_FNS = {
+    "gsr_batch_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int64]),
+    "gsr_default_schedule": (None, [C.c_void_p]),
+    "gsr_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]),
+    "gsr_batch_render": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsr_batch_set_schedule": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_batch_get_schedule": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsr_batch_tune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_char_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gsr_batch_records": (C.c_int64, [C.c_void_p]),
+    "gsr_batch_tiles": (C.c_int64, [C.c_void_p]),
+    "gsr_batch_entry_capacity": (C.c_int64, [C.c_void_p]),
+    "gsr_batch_counters_offset": (C.c_int64, [C.c_void_p]),
+    "gsr_batch_destroy": (None, [C.c_void_p]),
+}
+EXPORTS = EXPORTS + tuple(_BATCH_FNS)
+
+
+def _blib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        for name, (res, args) in _BATCH_FNS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        L._batch_ready = True
+    return L
+
+
+def schedule(wgs_per_cu=None, cost_order=None, lb_threshold=None) -> CSchedule:
+    s = CSchedule()
+    _blib().gsr_default_schedule(C.byref(s))
+    if wgs_per_cu is not None:
+        s.wgs_per_cu = wgs_per_cu
+    if cost_order is not None:
+        s.cost_order = cost_order
+    if lb_threshold is not None:
+        s.lb_threshold = lb_threshold
+    return s
+
+
+class BatchRenderer:
+    """Many views of several scenes rendered by one launch sequence
+    (gsr_batch_render), optionally captured once into a HIP graph and replayed.
+
+    scenes: list of DeviceScene; views: list of (scene index, camera)."""
+
+    def __init__(self, scenes, views, cfg: CConfig | None = None, sched: CSchedule | None = None,
+                 entries_hint: int | None = None, device="cuda"):
+        self.device = torch.device(device)
+        self.scenes = scenes
+        self.cfg = cfg or config()
+        self.sched = sched
+        self.frames = [Frame(cam.H, cam.W, self.device) for _, cam in views]
+        self.cscenes = (CScene * len(scenes))(*[s.c_struct() for s in scenes])
+        self.cviews = (CView * len(views))()
+        for k, (si, cam) in enumerate(views):
+            f = self.frames[k]
+            self.cviews[k].scene = si
+            self.cviews[k].cam = camera(cam)
+            self.cviews[k].rgb, self.cviews[k].depth = f.rgb.data_ptr(), f.depth.data_ptr()
+            self.cviews[k].count, self.cviews[k].T = f.count.data_ptr(), f.T.data_ptr()
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.handle = None
+        self.ws = None
+        self.graph = None
+        records = sum(scenes[si].n for si, _ in views)
+        self._plan(entries_hint or min((1 << 31) - 1, 16 * records + (1 << 20)))
+
+    def _plan(self, entries):
+        L = _blib()
+        self.close_plan()
+        nbytes = L.gsr_batch_workspace_bytes(self.cscenes, len(self.cscenes), self.cviews, len(self.cviews),
+                                             int(entries))
+        if nbytes == 0:
+            raise GsrError(GSR_EINVAL, L.gsr_last_error().decode())
+        self.ws = None
+        torch.cuda.empty_cache()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(L.gsr_batch_create(self.cscenes, len(self.cscenes), self.cviews, len(self.cviews), C.byref(self.cfg),
+                                  C.byref(self.sched) if self.sched is not None else None, _ptr(self.ws), nbytes,
+                                  C.byref(h)))
+        self.handle = h
+        self.graph = None
+
+    def close_plan(self):
+        if self.handle is not None:
+            _blib().gsr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close_plan()
+        except Exception:
+            pass
+
+    @property
+    def n_views(self):
+        return len(self.frames)
+
+    def counters(self):
+        off = _blib().gsr_batch_counters_offset(self.handle)
+        return self.ws[off:off + 16].view(torch.int32)
+
+    def capacity(self):
+        return int(_blib().gsr_batch_entry_capacity(self.handle))
+
+    def render_async(self):
+        """Enqueue the batch (no synchronisation)."""
+        _check(_blib().gsr_batch_render(self.handle, _ptr(self.status), _stream()))
+
+    def render(self):
+        """Render with the overflow check; grows the workspace until the entries fit."""
+        for _ in range(8):
+            self.status.zero_()
+            self.render_async()
+            if int(self.status.item()) & STATUS_OVERFLOW == 0:
+                return self.frames
+            need = int(self.counters()[3].item()) & 0xffffffff
+            if need >= (1 << 31) - 1:
+                raise GsrError(GSR_ECAPACITY, "batch needs more than 2^31 entries")
+            self._plan(min((1 << 31) - 1, int(need * 1.05) + 1024))
+        raise GsrError(GSR_ECAPACITY, "batch entries keep overflowing")
+
+    def entries(self) -> int:
+        return int(self.counters()[0].item())
+
+    def tune(self, cache_path=None, repeats=3):
+        best, ms = CSchedule(), C.c_float()
+        self.status.zero_()
+        _check(_blib().gsr_batch_tune(self.handle, _ptr(self.status), _stream(),
+                                      cache_path.encode() if cache_path else None, repeats, C.byref(best),
+                                      C.byref(ms)))
+        self.sched = best
+        self.graph = None
+        return best, ms.value
+
+    def set_schedule(self, sched: CSchedule):
+        _check(_blib().gsr_batch_set_schedule(self.handle, C.byref(sched)))
+        self.sched = sched
+        self.graph = None
+
+    def get_schedule(self) -> CSchedule:
+        s = CSchedule()
+        _check(_blib().gsr_batch_get_schedule(self.handle, C.byref(s)))
+        return s
+
+    def capture(self):
+        """Capture one gsr_batch_render into a HIP graph (torch.cuda.CUDAGraph)."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.render_async()
+        torch.cuda.synchronize()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()

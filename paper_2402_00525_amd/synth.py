@@ -214,3 +214,42 @@ def subsample(scene: Scene, n: int, seed: int = 123) -> Scene:
     idx = np.sort(_rng(seed).choice(scene.n, size=n, replace=False))
     return Scene(scene.means[idx].copy(), scene.scales[idx].copy(), scene.rots[idx].copy(),
                  scene.opacities[idx].copy(), scene.sh[idx].copy(), scene.sh_degree)
+
+
+BATCH_RESOLUTIONS = ((256, 256), (512, 512), (1280, 720), (1920, 1080))
+
+
+def sphere_camera(W: int, H: int, azimuth_deg: float, elevation_deg: float, radius: float = 3.0,
+                  fov_x_deg: float = 60.0) -> Camera:
+    az, el = math.radians(azimuth_deg), math.radians(elevation_deg)
+    pos = (radius * math.cos(el) * math.sin(az), -radius * math.sin(el), -radius * math.cos(el) * math.cos(az))
+    R, t, c = look_at(pos)
+    return pinhole(W, H, fov_x_deg, R, t, c)
+
+
+def batch_views(n_views: int, rng: np.random.Generator, scene_index: int):
+    """Cameras with resolutions drawn uniformly from 256^2, 512^2, 1280x720,
+    1920x1080 and poses uniform on the radius-3 sphere about the origin with
+    elevation in [-30, 60] degrees."""
+    out = []
+    for _ in range(n_views):
+        W, H = BATCH_RESOLUTIONS[int(rng.integers(0, len(BATCH_RESOLUTIONS)))]
+        az = float(rng.uniform(0.0, 360.0))
+        # uniform on the sphere band: sin(elevation) uniform
+        el = math.degrees(math.asin(rng.uniform(math.sin(math.radians(-30.0)), math.sin(math.radians(60.0)))))
+        out.append((scene_index, sphere_camera(W, H, az, el)))
+    return out
+
+
+def batch_workload(scale: float = 1.0, seed: int = 6, views_a: int = 64, views_b: int = 8, n_b: int = 8):
+    """One 1M-Gaussian mixture scene (the 1080p scene, seed 1) seen by 64
+    cameras, plus 8 scenes with N log-uniform in [1e5, 2e6] (seeds 7..14), 8
+    cameras each.  ``scale`` shrinks every scene for tests."""
+    rng = _rng(seed)
+    scenes = [mixture_scene(max(1, int(1_000_000 * scale)), seed=1)]
+    views = batch_views(views_a, rng, 0)
+    for k in range(n_b):
+        n = int(math.exp(rng.uniform(math.log(1e5), math.log(2e6))) * scale)
+        scenes.append(mixture_scene(max(1, n), seed=7 + k))
+        views += batch_views(views_b, rng, k + 1)
+    return scenes, views
