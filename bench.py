@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-global", action="store_true", help="skip timing the 3DGS global order alongside")
     ap.add_argument("--views", type=int, default=60, help="orbit views to cycle through (60 = full orbit)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched measurement (128 views of 9 scenes, one HIP-graph launch)")
     ap.add_argument("--no-fwd-bwd", action="store_true",
                     help="skip the forward+backward measurement (500k Gaussians, 1280x720, L1 loss)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -179,6 +181,48 @@ def fwd_bwd(steps, warmup):
                         "seeded random target, gradients for means/scales/rotations/opacities/SH"}
 
 
+def batched(steps):
+    """128 views (64 of the 1M-Gaussian scene, 8 each of 8 scenes with N
+    log-uniform in [1e5, 2e6]) at resolutions drawn from 256^2, 512^2,
+    1280x720 and 1920x1080, rendered by one captured HIP graph; the schedule is
+    chosen by the autotuner first.  Returns views/s."""
+    import torch
+    from paper_2402_00525_amd import gsr, synth
+    t0 = time.time()
+    scenes, views = synth.batch_workload()
+    log("batch workload generated in %.1fs (%d scenes, %d views)" % (time.time() - t0, len(scenes), len(views)))
+    dss = [gsr.DeviceScene.from_host(s) for s in scenes]
+    b = gsr.BatchRenderer(dss, views)
+    b.render()
+    torch.cuda.synchronize()
+    E = b.entries()
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "gsr_batch_schedule.txt")
+    sched, tune_ms = b.tune(cache_path=cache, repeats=2)
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.status.zero_()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        b.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    if int(b.status.item()) != 0:
+        raise RuntimeError("overflow during batched timing")
+    ms = t0.elapsed_time(t1) / steps
+    res = {"views_per_s": round(len(views) / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3), "views": len(views),
+           "scenes": len(scenes), "gaussians": [s.n for s in scenes], "entries": int(E),
+           "schedule": {"wgs_per_cu": sched.wgs_per_cu, "cost_order": sched.cost_order,
+                        "lb_threshold": sched.lb_threshold},
+           "workload": "64 views of the 1M-Gaussian scene + 8 views each of 8 scenes (N log-uniform in [1e5, 2e6]); "
+                       "resolutions uniform over 256^2, 512^2, 1280x720, 1920x1080; one HIP graph per batch"}
+    del b, dss
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -267,6 +311,10 @@ def main():
         line["global_order"] = {"ms_per_frame": round(g["ms"], 4), "entries": int(g["E"]),
                                 "stages_ms": {k: round(v, 4) for k, v in
                                               zip(("preprocess", "duplicate", "sort", "render"), g["stages"])}}
+    if not args.no_batch and args.workload != "small":
+        log("batched ...")
+        line["batched"] = batched(5)
+        log("batched: %s" % line["batched"])
     if not args.no_fwd_bwd and args.workload != "small":
         log("forward+backward ...")
         line["fwd_bwd"] = fwd_bwd(max(5, args.steps // 2), 3)
