@@ -31,6 +31,8 @@ namespace {
 enum { kFwd = 0, kFwdDebug = 1, kBwd = 2 };
 
 constexpr int kBatch = 32;
+// Backward: per-tile LDS accumulators for the first kAccSlots list entries.
+constexpr int kAccSlots = 256;
 constexpr int kTailCap = 64;
 constexpr int kPop = 16;
 constexpr int kMidCap = 8;
@@ -80,9 +82,18 @@ struct PixelState {
     float px, py;
 };
 
+// Adds the 9 gradient terms of one blend: into the tile's LDS accumulators
+// (slot = rank in the tile list) when the rank has a slot, else to global memory.
+__device__ __forceinline__ void add_grad(const RenderArgs& a, float* acc, uint32_t rank, uint32_t id, int c, float v) {
+    if (acc && rank < (uint32_t)kAccSlots)
+        atomicAdd(acc + c * kAccSlots + rank, v);
+    else
+        atomicAdd(a.grad2d + 9 * (size_t)id + c, v);
+}
+
 template <int K, int MODE>
 __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MODE>& s, int pix, uint32_t id,
-                                          float alpha, float t) {
+                                          float alpha, float t, uint32_t rank, float* acc) {
     if (s.done) return;
     const float Tn = s.T * (1.0f - alpha);
     if (Tn < kTMin) {
@@ -105,10 +116,9 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         const float ga = s.g0 * (e.y * s.T - ((s.F0 - s.C0) + s.TN * a.bg0) * inv) +
                          s.g1 * (e.z * s.T - ((s.F1 - s.C1) + s.TN * a.bg1) * inv) +
                          s.g2 * (e.w * s.T - ((s.F2 - s.C2) + s.TN * a.bg2) * inv);
-        float* g = a.grad2d + 9 * (size_t)id;
-        atomicAdd(g + 6, s.g0 * w);
-        atomicAdd(g + 7, s.g1 * w);
-        atomicAdd(g + 8, s.g2 * w);
+        add_grad(a, acc, rank, id, 6, s.g0 * w);
+        add_grad(a, acc, rank, id, 7, s.g1 * w);
+        add_grad(a, acc, rank, id, 8, s.g2 * w);
         const float2 m = a.xy[id];
         const float4 c = a.co[id];
         const float dx = m.x - s.px, dy = m.y - s.py;
@@ -116,12 +126,12 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         const float G = exp_cw(pw);
         if (c.w * G < kAlphaMax) {
             const float gp = ga * alpha;  // d alpha / d power = o G
-            atomicAdd(g + 0, gp * (-c.x * dx - c.y * dy));
-            atomicAdd(g + 1, gp * (-c.z * dy - c.y * dx));
-            atomicAdd(g + 2, gp * (-0.5f * dx * dx));
-            atomicAdd(g + 3, gp * (-dx * dy));
-            atomicAdd(g + 4, gp * (-0.5f * dy * dy));
-            atomicAdd(g + 5, ga * G);
+            add_grad(a, acc, rank, id, 0, gp * (-c.x * dx - c.y * dy));
+            add_grad(a, acc, rank, id, 1, gp * (-c.z * dy - c.y * dx));
+            add_grad(a, acc, rank, id, 2, gp * (-0.5f * dx * dx));
+            add_grad(a, acc, rank, id, 3, gp * (-dx * dy));
+            add_grad(a, acc, rank, id, 4, gp * (-0.5f * dy * dy));
+            add_grad(a, acc, rank, id, 5, ga * G);
         }
     }
     s.n += 1;
@@ -130,7 +140,7 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
 
 // Remove the front of the head and blend it.
 template <int K, int MODE>
-__device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, MODE>& s, int pix) {
+__device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, MODE>& s, int pix, float* acc) {
     const uint64_t k0 = s.hk[0];
     const uint32_t i0 = s.hid[0];
     const float a0 = s.ha[0];
@@ -141,7 +151,7 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
         s.ha[i] = s.ha[i + 1];
     }
     s.hn -= 1;
-    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)));
+    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
 }
 
 // Insertion into the sorted head (s.hn < K + 1 on entry).
@@ -181,6 +191,7 @@ struct HierCtx {
     // mid queue state (uniform over the quad)
     int mb, ms, mn;
     PixelState<K, MODE> st;
+    float* acc;  // backward: the tile's LDS gradient accumulators
 
     __device__ HierCtx(const RenderArgs& a_, WaveQueues& q_) : a(a_), q(q_) {}
 
@@ -196,7 +207,7 @@ struct HierCtx {
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
                     const float t = t_opt(g, dP);
                     head_insert<K, MODE>(st, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha);
-                    if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix);
+                    if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix, acc);
                 }
             }
         }
@@ -262,11 +273,12 @@ struct HierCtx {
 // the number of list entries the wavefront read before its pixels finished.
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, int range_tile, int strip,
-                                                 WaveQueues& q) {
+                                                 WaveQueues& q, float* acc) {
     const int lane = threadIdx.x & 63, wave = strip;
     const DevCam& cam = a.cam;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     HierCtx<K, MODE> h(a, q);
+    h.acc = acc;
     h.lane = lane;
     h.row = lane >> 4;
     h.j = lane & 15;
@@ -410,7 +422,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
             }
 #pragma unroll
             for (int i = 0; i <= K; ++i)
-                if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix);
+                if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix, acc);
         }
     }
     if (MODE != kBwd && h.pix_ok) {
@@ -432,14 +444,34 @@ template <int K, int MODE>
 __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     __shared__ WaveQueues s_q[4];
     __shared__ uint32_t s_consumed[4];
+    __shared__ float s_acc[MODE == kBwd ? 9 * kAccSlots : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t c = render_strip<K, MODE>(a, blockIdx.x, blockIdx.x, wave, s_q[wave]);
+    if (MODE == kBwd) {
+        for (int k = threadIdx.x; k < 9 * kAccSlots; k += 256) s_acc[k] = 0.0f;
+        __syncthreads();
+    }
+    const uint32_t c = render_strip<K, MODE>(a, blockIdx.x, blockIdx.x, wave, s_q[wave],
+                                             MODE == kBwd ? s_acc : nullptr);
     if (lane == 0) s_consumed[wave] = c;
     __syncthreads();
     if (MODE != kBwd && threadIdx.x == 0) {
         uint32_t m = s_consumed[0];
         for (int w = 1; w < 4; ++w) m = s_consumed[w] > m ? s_consumed[w] : m;
         if (m) atomicAdd(a.counters + 1, m);
+    }
+    if (MODE == kBwd) {
+        // One global atomic per (tile, Gaussian, component) instead of one per blend.
+        const uint32_t begin = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
+        const uint32_t len = end - begin < (uint32_t)kAccSlots ? end - begin : (uint32_t)kAccSlots;
+        for (uint32_t r = threadIdx.x; r < len; r += 256) {
+            uint32_t id = a.vals[begin + r];
+            id = id < a.n ? id : 0u;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float v = s_acc[k * kAccSlots + r];
+                if (v != 0.0f) atomicAdd(a.grad2d + 9 * (size_t)id + k, v);
+            }
+        }
     }
 }
 
@@ -494,7 +526,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.rgb_in = nullptr;
         a.T_in = nullptr;
         a.grad2d = nullptr;
-        render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave]);
+        render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
     }
 }
 
