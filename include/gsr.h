@@ -180,7 +180,8 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                       int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);
 
-/* Number of 8-bit radix passes a W x H frame's keys need (tile bits + 32). */
+/* Number of radix passes a W x H frame's keys need (32 + tile bits, digits of
+ * at most 9 bits). */
 int gsr_sort_passes(int32_t W, int32_t H);
 
 /* ---------------------------------------------------------------------------

@@ -47,9 +47,10 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->ranges = take(8 * (int64_t)tiles);
     L->counters = take(64);
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
-    const int64_t sp = (int64_t)std::max(gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)nb * 256)) + 2;
+    const int64_t sp =
+        (int64_t)std::max(gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)) + 2;
     *scan_partial = take(4 * sp);
-    *hist = take(4 * 256 * nb);
+    *hist = take(4 * gsr::kSortMaxBins * nb);
     L->keys = take(8 * cap);
     *keys1 = take(8 * cap);
     L->values = take(4 * cap);
@@ -169,7 +170,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     const int tiles = dc.tiles_x * dc.tiles_y;
     const int mode = cfg->mode;
     const int key_bits = 32 + bits_for_tiles(tiles);
-    const int passes = (key_bits + 7) / 8;
+    const int passes = gsr::sort_pass_count(key_bits);
     gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
 
     hipError_t e;
@@ -306,11 +307,12 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->tkeys[1] = take(8 * tiles);
     L->tvals[0] = take(4 * tiles);
     L->tvals[1] = take(4 * tiles);
-    L->thist = take(4 * 256 * nbt);
-    L->tpartial = take(4 * ((int64_t)gsr::scan_partial_len((size_t)nbt * 256) + 2));
+    L->thist = take(4 * gsr::kSortMaxBins * nbt);
+    L->tpartial = take(4 * ((int64_t)gsr::scan_partial_len((size_t)nbt * gsr::kSortMaxBins) + 2));
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
-    L->partial = take(4 * ((int64_t)std::max(gsr::scan_partial_len((size_t)R), gsr::scan_partial_len((size_t)nb * 256)) + 2));
-    L->hist = take(4 * 256 * nb);
+    L->partial = take(4 * ((int64_t)std::max(gsr::scan_partial_len((size_t)R),
+                                             gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)) + 2));
+    L->hist = take(4 * gsr::kSortMaxBins * nb);
     L->keys[0] = take(8 * cap);
     L->keys[1] = take(8 * cap);
     L->vals[0] = take(4 * cap);
@@ -391,7 +393,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.counters = (uint32_t*)(base + L.counters);
     fb.capacity = (uint32_t)L.cap;
     const int key_bits = 32 + bits_for_tiles((int)b->tiles);
-    const int passes = (key_bits + 7) / 8;
+    const int passes = gsr::sort_pass_count(key_bits);
     const int lb = b->sched.lb_threshold;
     hipError_t e;
     if ((e = gsr::launch_fill_u32(fb.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
@@ -705,7 +707,7 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 
 int gsr_sort_passes(int32_t W, int32_t H) {
     if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
-    return (32 + bits_for_tiles(tiles_of(W, H)) + 7) / 8;
+    return gsr::sort_pass_count(32 + bits_for_tiles(tiles_of(W, H)));
 }
 
 int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,

@@ -22,7 +22,7 @@ struct FrameBufs {
     uint32_t* scan_partial;   // scan scratch, >= scan_partial_len(max(n, hist)) + 2
     uint64_t* keys[2];
     uint32_t* vals[2];
-    uint32_t* hist;           // radix histograms, 256 x sort blocks
+    uint32_t* hist;           // radix histograms, kSortMaxBins x sort blocks
     uint32_t* ranges;         // [tiles][2]
     uint32_t* counters;       // [0] entries, [1] consumed by render, [2..3] spare
     uint32_t capacity;
@@ -49,7 +49,11 @@ constexpr int kSortTile = kSortThreads * kSortRounds;
 
 inline size_t div_up(size_t a, size_t b) { return (a + b - 1) / b; }
 inline size_t scan_partial_len(size_t n) { return div_up(n, kScanTile); }
-inline size_t sort_blocks(size_t cap) { return div_up(cap, kSortTile); }
+// Sort tiles for `cap` keys, rounded up to whole histogram groups of 16.
+inline size_t sort_blocks(size_t cap) { return div_up(div_up(cap, kSortTile), 16) * 16; }
+// Radix passes for `bits` key bits (digits of at most 9 bits, equal widths).
+int sort_pass_count(int bits);
+constexpr int kSortMaxBins = 512;
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
@@ -72,7 +76,8 @@ hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_
 // Stable LSD sort of the first *n_ptr pairs of (keys[start], vals[start]) on
 // the low `bits` key bits, for at most `cap` pairs; the result lands in
 // buffer start ^ (passes & 1), returned in *result_buf.  hist holds
-// 256 * sort_blocks(cap) words, partial scan_partial_len(256 * sort_blocks(cap)) + 2.
+// kSortMaxBins * sort_blocks(cap) words, partial
+// scan_partial_len(kSortMaxBins * sort_blocks(cap)) + 2.
 hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], const uint32_t* n_ptr, size_t cap,
                              uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
                              void* const* scatter_events = nullptr);
