@@ -252,7 +252,6 @@ def main():
     ds = gsr.DeviceScene.from_host(scene)
     n, W, H = scene.n, cams[0].W, cams[0].H
     P = W * H
-    passes = gsr.lib().gsr_sort_passes(W, H)
     ksh = (scene.sh_degree + 1) ** 2
 
     results = {}
@@ -260,22 +259,24 @@ def main():
         if label == "global" and args.no_global:
             continue
         cfg = gsr.config(mode=mode)
+        passes = (gsr.lib().gsr_group_passes(W, H) if mode == gsr.MODE_HIER else gsr.lib().gsr_sort_passes(W, H))
         r = gsr.Renderer(entries_hint=40 * n)
         emax, consumed = plan(r, ds, cams, cfg)
         ms, stages, scatter = time_frames(r, ds, cams, cfg, args.steps, args.warmup, passes)
         # entries of the timed views (every view was rendered once while planning)
         views = [(args.warmup + i) % len(cams) for i in range(args.steps)]
-        E_views, cons_views = [], []
+        E_views, cons_views, fb_views = [], [], []
         for v in sorted(set(views)):
             r.render(ds, cams[v], cfg)
             E_views.append(r.counter(n, cams[v], 0))
             cons_views.append(r.counter(n, cams[v], 1))
+            fb_views.append(r.counter(n, cams[v], 5) if mode == gsr.MODE_HIER else 0)
         results[label] = dict(ms=ms, stages=[mean([s[k] for s in stages]) for k in range(4)],
-                              scatter=mean([mean(s) for s in scatter]), E=mean(E_views), consumed=mean(cons_views),
-                              emax=emax)
-        log("%s: %.3f ms/frame, stages %s, scatter %.3f ms/launch, E %.0f, consumed %.0f" %
-            (label, ms, ["%.3f" % x for x in results[label]["stages"]], results[label]["scatter"],
-             results[label]["E"], results[label]["consumed"]))
+                              scatter=mean([mean(s) for s in scatter]) if passes else 0.0, E=mean(E_views),
+                              consumed=mean(cons_views), fallback=mean(fb_views), emax=emax, passes=passes)
+        log("%s: %.3f ms/frame, stages %s, scatter %.3f ms/launch x %d, E %.0f, consumed %.0f, fallback entries %.0f" %
+            (label, ms, ["%.3f" % x for x in results[label]["stages"]], results[label]["scatter"], passes,
+             results[label]["E"], results[label]["consumed"], results[label]["fallback"]))
         del r
         torch.cuda.empty_cache()
 
@@ -283,7 +284,7 @@ def main():
     # Dominant kernel and its algorithmic bytes per launch.
     cands = {
         "k_preprocess": (h["stages"][0], h["stages"][0], n * (44 + 12 * ksh) + n * 104),
-        "k_radix_scatter": (h["scatter"] * passes, h["scatter"], 24.0 * h["E"]),
+        "k_radix_scatter": (h["scatter"] * h["passes"], h["scatter"], 24.0 * h["E"]),
         "k_render_hier": (h["stages"][3], h["stages"][3], 76.0 * h["consumed"] + 24.0 * P),
     }
     dom = max(cands, key=lambda k: cands[k][0])
@@ -302,7 +303,7 @@ def main():
                                "resort 64/8/4" % (n, scene.sh_degree, W, H),
                    "gaussians": n, "width": W, "height": H, "views": len(cams), "head": 4},
         "stages_ms": {k: round(v, 4) for k, v in zip(("preprocess", "duplicate", "sort", "render"), h["stages"])},
-        "entries": int(h["E"]), "entries_consumed": int(h["consumed"]),
+        "entries": int(h["E"]), "entries_consumed": int(h["consumed"]), "fallback_entries": int(h["fallback"]),
         "frame_hbm_GBs": round(frame_bytes / (h["ms"] * 1e-3) / 1e9, 1),
         "roofline": roofline,
     }

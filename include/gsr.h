@@ -93,7 +93,9 @@ typedef struct gsr_config {
     int32_t batch, tail, pop, mid, mid_batch, head;
     int32_t lb_threshold;
     float bg[3];
-    uint32_t flags; /* reserved, must be 0 */
+    uint32_t flags;      /* reserved, must be 0 */
+    int32_t sort_prefix; /* speed only: entries per tile sorted up front (power of two,
+                            16..4096; 0 = 2048); see gsr_render */
 } gsr_config;
 
 /* Byte offsets of the regions of a workspace, for inspection and debugging.
@@ -103,14 +105,25 @@ typedef struct gsr_config {
  *   zd       float2 (view depth, |mu - o|)
  *   rect     int32[4] tile rectangle (x0, y0, x1, y1), inclusive
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
+ *   kmask    uint32 kept-tile bit mask (row-major over rect) of Gaussians whose
+ *            rectangle holds at most min(lb_threshold, 32) tiles, else 0
  * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
  * (Gaussian id), ranges uint32[tiles][2] = [start, end) per tile; counters
- * uint32[4] = (entries, entries consumed by the renderer, unused, entries needed before clamping
- * to the capacity, saturated at 2^32 - 1);
- * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb). */
+ * uint32[8] = (entries, entries consumed by the renderer, unused, entries needed before
+ * clamping to the capacity (saturated at 2^32 - 1), unused, entries of the tiles that took
+ * the fallback, number of such tiles, unused);
+ * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb).
+ * GSR_MODE_GLOBAL: keys/values are fully sorted.
+ * GSR_MODE_HIER: keys/values hold the entries grouped by tile (Gaussian id
+ * order inside a tile; the keys of tiles that took the fallback are
+ * overwritten), pre_vals uint32[capacity] each tile's sorted ids from its
+ * range start (a prefix, or the whole list for a tile that took the
+ * fallback), pre_len uint32[tiles] their number, tile_flag uint32[tiles] the
+ * entry count of a tile that took the fallback (else 0). */
 typedef struct gsr_layout {
-    int64_t xy, conic_o, sw, zd, rect, touched, offsets, grad2d;
+    int64_t xy, conic_o, sw, zd, rect, touched, kmask, offsets, grad2d;
     int64_t keys, values, ranges, counters;
+    int64_t pre_vals, pre_len, tile_flag;
     int64_t entry_capacity;
     int64_t total_bytes;
 } gsr_layout;
@@ -132,8 +145,13 @@ void gsr_default_config(gsr_config* cfg /* host */);
 int gsr_check_config(const gsr_config* cfg /* host */);
 
 /* Render one frame: preprocess, count and duplicate (tile, depth) entries,
- * radix-sort them, find tile ranges, and blend every pixel front to back with
- * early termination (Eq. volume_desc).  In GSR_MODE_HIER the blend order is
+ * sort them, find tile ranges, and blend every pixel front to back with
+ * early termination (Eq. volume_desc).  In GSR_MODE_HIER the entries are
+ * grouped by tile, each tile's first (at most sort_prefix) entries in (depth,
+ * Gaussian id) order are selected and sorted, and a tile whose pixels are
+ * still unfinished when its prefix runs out has its whole list sorted and is
+ * rendered again (enqueued always; tiles that need nothing exit at once): the
+ * order is that of a full sort by (tile, depth, id) in every case.  In GSR_MODE_HIER the blend order is
  * the hierarchical tail / mid / head resorting on per-level t_opt (Eq. dopt);
  * in GSR_MODE_GLOBAL it is the 3DGS view-space-depth order.
  *   rgb     [3,H,W] float32 out   colour + T_final * bg
@@ -172,17 +190,24 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 /* As gsr_render, and records caller-created HIP events (hipEvent_t, passed
  * as void*) on the stream at the stage boundaries of the paper's per-stage
  * timing (Sec. 4.3): events[0] before Preprocess, [1] after Preprocess, [2]
- * after Duplicate (prefix sum + key emission), [3] after Sort (radix sort +
- * tile ranges), [4] after Render.  With n_events >= 5 + 2 * passes
- * (passes = gsr_sort_passes(W, H)), events[5 + 2p] and [6 + 2p] also bracket
- * the scatter launch of radix pass p.  The caller owns the events. */
+ * after Duplicate (prefix sum + key emission), [3] after Sort (radix sort,
+ * tile ranges and, in GSR_MODE_HIER, the per-tile sorted prefixes), [4] after
+ * Render (in GSR_MODE_HIER including the fallback sort of flagged tiles and
+ * their second render).  With n_events >= 5 + 2 * passes (passes =
+ * gsr_group_passes(W, H) in GSR_MODE_HIER, gsr_sort_passes(W, H) in
+ * GSR_MODE_GLOBAL), events[5 + 2p] and [6 + 2p] also bracket the scatter
+ * launch of radix pass p.  The caller owns the events. */
 int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                       int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);
 
-/* Number of radix passes a W x H frame's keys need (32 + tile bits, digits of
- * at most 9 bits). */
+/* Number of radix passes a W x H frame's full keys need (32 + tile bits,
+ * digits of at most 9 bits): the global order, and the fallback sort. */
 int gsr_sort_passes(int32_t W, int32_t H);
+
+/* Number of radix passes that group a W x H frame's entries by tile (tile
+ * bits only; 0 for a single tile). */
+int gsr_group_passes(int32_t W, int32_t H);
 
 /* ---------------------------------------------------------------------------
  * Batched rendering: many views (cameras of any resolution) of several scenes

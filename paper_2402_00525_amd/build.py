@@ -30,7 +30,7 @@ HIP_FLAGS = [
     f"-I{INCLUDE}",
 ]
 
-SOURCES = ["frame.hip", "sort.hip", "render.hip", "capi.hip"]
+SOURCES = ["frame.hip", "sort.hip", "tile_sort.hip", "render.hip", "capi.hip"]
 
 
 def _compile(src: str) -> str:

@@ -27,6 +27,30 @@ int fail_hip(hipError_t e, const char* where) {
 
 inline int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+int bits_for_tiles(int tiles) {
+    int b = 0;
+    while ((1 << b) < tiles) ++b;
+    return b;
+}
+
+// Radix passes of the sort stage and the buffer duplication writes into.
+// HIER: entries are grouped by tile (tile bits only) and the grouped result
+// lands in buffer 0; buffer 1 is then free scratch for the per-tile fallback
+// sort.  GLOBAL: the full (tile, depth) sort, result in buffer 0.
+struct SortPlan {
+    int tile_bits, key_bits, tile_passes, full_passes, dup_buf;
+};
+
+SortPlan sort_plan(int tiles, int mode) {
+    SortPlan p;
+    p.tile_bits = bits_for_tiles(tiles);
+    p.key_bits = 32 + p.tile_bits;
+    p.full_passes = gsr::sort_pass_count(p.key_bits);
+    p.tile_passes = p.tile_bits > 0 ? gsr::sort_pass_count(p.tile_bits) : 0;
+    p.dup_buf = (mode == GSR_MODE_HIER ? p.tile_passes : p.full_passes) & 1;
+    return p;
+}
+
 // Layout for a given entry capacity.
 void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_partial, int64_t* hist,
                 int64_t* keys1, int64_t* vals1) {
@@ -42,19 +66,24 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->zd = take(8 * n);
     L->rect = take(16 * n);
     L->touched = take(4 * n);
+    L->kmask = take(4 * n);
     L->offsets = take(4 * n);
     L->grad2d = take(36 * n);
     L->ranges = take(8 * (int64_t)tiles);
     L->counters = take(64);
+    L->pre_len = take(4 * (int64_t)tiles);
+    L->tile_flag = take(4 * (int64_t)tiles);
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
-    const int64_t sp =
-        (int64_t)std::max(gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)) + 2;
+    const int64_t sp = (int64_t)std::max({gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)tiles),
+                                          gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
+                       2;
     *scan_partial = take(4 * sp);
     *hist = take(4 * gsr::kSortMaxBins * nb);
     L->keys = take(8 * cap);
     *keys1 = take(8 * cap);
     L->values = take(4 * cap);
     *vals1 = take(4 * cap);
+    L->pre_vals = take(4 * cap);
     L->entry_capacity = cap;
     L->total_bytes = off;
 }
@@ -102,12 +131,6 @@ gsr::DevCam make_cam(const gsr_camera* c) {
     return d;
 }
 
-int bits_for_tiles(int tiles) {
-    int b = 0;
-    while ((1 << b) < tiles) ++b;
-    return b;
-}
-
 int check_scene(const gsr_scene* s) {
     if (!s) return fail(GSR_EINVAL, "scene is NULL");
     if (s->n < 0) return fail(GSR_EINVAL, "scene n < 0");
@@ -132,6 +155,7 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.zd = (float2*)(base + L.zd);
     b.rect = (int4*)(base + L.rect);
     b.touched = (uint32_t*)(base + L.touched);
+    b.kmask = (uint32_t*)(base + L.kmask);
     b.offsets = (uint32_t*)(base + L.offsets);
     b.scan_partial = (uint32_t*)(base + sp);
     b.hist = (uint32_t*)(base + hist);
@@ -142,7 +166,49 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.ranges = (uint32_t*)(base + L.ranges);
     b.counters = (uint32_t*)(base + L.counters);
     b.capacity = (uint32_t)L.entry_capacity;
+    b.pre_vals = (uint32_t*)(base + L.pre_vals);
+    b.pre_len = (uint32_t*)(base + L.pre_len);
+    b.tile_flag = (uint32_t*)(base + L.tile_flag);
+    b.flist = nullptr;
     return b;
+}
+
+int prefix_len(const gsr_config* cfg) { return cfg->sort_prefix == 0 ? 2048 : cfg->sort_prefix; }
+
+// Sort stage of a frame (or a batch).  HIER: group by tile, tile ranges and
+// each tile's sorted prefix.  GLOBAL: full sort and ranges.
+hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, hipStream_t s,
+                      void* const* scatter_events) {
+    const SortPlan sp = sort_plan(tiles, mode);
+    hipError_t e;
+    int res = 0;
+    if (mode == GSR_MODE_HIER) {
+        if ((e = gsr::launch_fill_u32(b.tile_flag, (size_t)tiles, 0u, s)) != hipSuccess) return e;
+        if (sp.tile_passes > 0) {
+            if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.tile_bits,
+                                            sp.dup_buf, &res, s, scatter_events, 32)) != hipSuccess)
+                return e;
+        }
+        if ((e = gsr::launch_ranges(b.keys[0], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess) return e;
+        return gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.ranges, (uint32_t)tiles, b.pre_vals, b.pre_len, M, s);
+    }
+    if ((e = gsr::launch_sort(b, sp.key_bits, &res, s, scatter_events)) != hipSuccess) return e;
+    return gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s);
+}
+
+// Fallback of the HIER sort: the whole sorted list of every tile the prefix
+// render flagged (counters[5] = their entries, counters[6] = their number).
+hipError_t fallback_sort(const gsr::FrameBufs& b, int tiles, hipStream_t s) {
+    return gsr::launch_tile_sort_flagged(b.keys[0], b.vals[0], b.keys[1], b.ranges, b.tile_flag, (uint32_t)tiles,
+                                         b.pre_vals, b.pre_len, b.counters, b.flist, s);
+}
+
+void set_prefix_lists(gsr::RenderArgs& ra, const gsr::FrameBufs& b, int list_mode) {
+    ra.list_mode = list_mode;
+    ra.vals = b.vals[0];
+    ra.pre_vals = b.pre_vals;
+    ra.pre_len = b.pre_len;
+    ra.tile_flag = b.tile_flag;
 }
 
 int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
@@ -158,19 +224,19 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if (cfg->mode == GSR_MODE_HIER && !gsr::hier_head_supported(cfg->head))
         return fail(GSR_EUNSUPPORTED, "head size not built (1,2,3,4,6,8,12,16,20,24)");
     gsr_layout L;
-    int64_t sp, hist, k1, v1;
-    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &sp, &hist, &k1, &v1);
+    int64_t spo, hist, k1, v1;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &spo, &hist, &k1, &v1);
     if (rc) return fail(rc, "workspace too small");
     char* base = (char*)ws;
     if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
-    const gsr::FrameBufs b = frame_bufs(base, L, sp, hist, k1, v1);
+    const gsr::FrameBufs b = frame_bufs(base, L, spo, hist, k1, v1);
 
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
     const int tiles = dc.tiles_x * dc.tiles_y;
     const int mode = cfg->mode;
-    const int key_bits = 32 + bits_for_tiles(tiles);
-    const int passes = gsr::sort_pass_count(key_bits);
+    const SortPlan sp = sort_plan(tiles, mode);
+    const uint32_t M = (uint32_t)prefix_len(cfg);
     gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
 
     hipError_t e;
@@ -184,23 +250,22 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if ((e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
                               s, b.counters + 3)) != hipSuccess)
         return fail_hip(e, "scan");
-    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, b, passes & 1, status_dev, s)) != hipSuccess)
+    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, b, sp.dup_buf, status_dev, s)) != hipSuccess)
         return fail_hip(e, "duplicate");
     if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
-    int res = 0;
-    void* const* scatter_ev = (events && n_events >= 5 + 2 * passes) ? events + 5 : nullptr;
-    if ((e = gsr::launch_sort(b, key_bits, &res, s, scatter_ev)) != hipSuccess) return fail_hip(e, "sort");
-    if ((e = gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess)
-        return fail_hip(e, "ranges");
+    const int n_sort_ev = mode == GSR_MODE_HIER ? sp.tile_passes : sp.full_passes;
+    void* const* scatter_ev = (events && n_events >= 5 + 2 * n_sort_ev) ? events + 5 : nullptr;
+    if ((e = sort_stage(b, tiles, mode, M, s, scatter_ev)) != hipSuccess) return fail_hip(e, "sort");
     if ((e = mark(3)) != hipSuccess) return fail_hip(e, "event");
     gsr::RenderArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
     ra.cam = dc;
     ra.n = (uint32_t)scene->n;
     ra.xy = b.xy;
     ra.co = b.co;
     ra.sw = b.sw;
     ra.zd = b.zd;
-    ra.vals = b.vals[res];
+    ra.vals = b.vals[0];
     ra.ranges = b.ranges;
     ra.counters = b.counters;
     ra.rgb = rgb;
@@ -212,15 +277,16 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.bg0 = cfg->bg[0];
     ra.bg1 = cfg->bg[1];
     ra.bg2 = cfg->bg[2];
-    ra.dL = nullptr;
-    ra.rgb_in = nullptr;
-    ra.T_in = nullptr;
-    ra.grad2d = nullptr;
-    if (mode == GSR_MODE_HIER)
-        e = gsr::launch_render_hier(ra, cfg->head, s);
-    else
-        e = gsr::launch_render_global(ra, s);
-    if (e != hipSuccess) return fail_hip(e, "render");
+    if (mode == GSR_MODE_HIER) {
+        set_prefix_lists(ra, b, gsr::kListPrefix);
+        if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
+        if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
+        ra.list_mode = gsr::kListFlagged;
+        if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
+    } else {
+        ra.list_mode = gsr::kListFull;
+        if ((e = gsr::launch_render_global(ra, s)) != hipSuccess) return fail_hip(e, "render");
+    }
     if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
     return GSR_OK;
 }
@@ -239,12 +305,12 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     if (!ws || !dL || !rgb || !T_final) return fail(GSR_EINVAL, "input is NULL");
     if (scene->n > 0 && (!dmeans || !dscales || !drots || !dopac || !dsh)) return fail(GSR_EINVAL, "gradient is NULL");
     gsr_layout L;
-    int64_t sp, hist, k1, v1;
-    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &sp, &hist, &k1, &v1);
+    int64_t spo, hist, k1, v1;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &spo, &hist, &k1, &v1);
     if (rc) return fail(rc, "workspace too small");
     char* base = (char*)ws;
     if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
-    const gsr::FrameBufs b = frame_bufs(base, L, sp, hist, k1, v1);
+    const gsr::FrameBufs b = frame_bufs(base, L, spo, hist, k1, v1);
     float* g2 = (float*)(base + L.grad2d);
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
@@ -269,6 +335,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     ra.rgb_in = rgb;
     ra.T_in = T_final;
     ra.grad2d = g2;
+    set_prefix_lists(ra, b, gsr::kListSorted);
     if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render backward");
     if ((e = gsr::launch_preprocess_backward(sc, dc, b.co, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
         return fail_hip(e, "preprocess backward");
@@ -279,7 +346,8 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
 // Batched rendering: many views of several scenes in one launch sequence.
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-    int64_t views, xy, co, sw, zd, rect, touched, offsets, ranges, counters;
+    int64_t views, xy, co, sw, zd, rect, touched, kmask, offsets, ranges, counters;
+    int64_t pre_vals, pre_len, tile_flag, flist;
     int64_t keys[2], vals[2], hist, partial;
     int64_t tkeys[2], tvals[2], thist, tpartial;
     int64_t cap, total;
@@ -299,9 +367,13 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->zd = take(8 * R);
     L->rect = take(16 * R);
     L->touched = take(4 * R);
+    L->kmask = take(4 * R);
     L->offsets = take(4 * R);
     L->ranges = take(8 * tiles);
     L->counters = take(64);
+    L->pre_len = take(4 * tiles);
+    L->tile_flag = take(4 * tiles);
+    L->flist = take(4 * tiles);
     const int64_t nbt = (int64_t)gsr::sort_blocks((size_t)tiles);
     L->tkeys[0] = take(8 * tiles);
     L->tkeys[1] = take(8 * tiles);
@@ -310,13 +382,15 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->thist = take(4 * gsr::kSortMaxBins * nbt);
     L->tpartial = take(4 * ((int64_t)gsr::scan_partial_len((size_t)nbt * gsr::kSortMaxBins) + 2));
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
-    L->partial = take(4 * ((int64_t)std::max(gsr::scan_partial_len((size_t)R),
-                                             gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)) + 2));
+    L->partial = take(4 * ((int64_t)std::max({gsr::scan_partial_len((size_t)R), gsr::scan_partial_len((size_t)tiles),
+                                              gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
+                           2));
     L->hist = take(4 * gsr::kSortMaxBins * nb);
     L->keys[0] = take(8 * cap);
     L->keys[1] = take(8 * cap);
     L->vals[0] = take(4 * cap);
     L->vals[1] = take(4 * cap);
+    L->pre_vals = take(4 * cap);
     L->cap = cap;
     L->total = off;
 }
@@ -382,6 +456,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.zd = (float2*)(base + L.zd);
     fb.rect = (int4*)(base + L.rect);
     fb.touched = (uint32_t*)(base + L.touched);
+    fb.kmask = (uint32_t*)(base + L.kmask);
     fb.offsets = (uint32_t*)(base + L.offsets);
     fb.scan_partial = (uint32_t*)(base + L.partial);
     fb.hist = (uint32_t*)(base + L.hist);
@@ -392,8 +467,12 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.ranges = (uint32_t*)(base + L.ranges);
     fb.counters = (uint32_t*)(base + L.counters);
     fb.capacity = (uint32_t)L.cap;
-    const int key_bits = 32 + bits_for_tiles((int)b->tiles);
-    const int passes = gsr::sort_pass_count(key_bits);
+    fb.pre_vals = (uint32_t*)(base + L.pre_vals);
+    fb.pre_len = (uint32_t*)(base + L.pre_len);
+    fb.tile_flag = (uint32_t*)(base + L.tile_flag);
+    fb.flist = (uint32_t*)(base + L.flist);
+    const int tiles = (int)b->tiles;
+    const SortPlan sp = sort_plan(tiles, GSR_MODE_HIER);
     const int lb = b->sched.lb_threshold;
     hipError_t e;
     if ((e = gsr::launch_fill_u32(fb.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
@@ -406,6 +485,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
         v.zd += r0;
         v.rect += r0;
         v.touched += r0;
+        v.kmask += r0;
         v.offsets += r0;
         return v;
     };
@@ -422,14 +502,12 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     for (size_t v = 0; v < b->views.size(); ++v) {
         const gsr_scene& sc = b->scenes[b->views[v].scene];
         if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, shifted(b->rec_base[v]),
-                                       passes & 1, status_dev, s, (uint32_t)b->tile_base[v], (uint32_t)b->rec_base[v])) !=
-            hipSuccess)
+                                       sp.dup_buf, status_dev, s, (uint32_t)b->tile_base[v],
+                                       (uint32_t)b->rec_base[v])) != hipSuccess)
             return fail_hip(e, "duplicate");
     }
-    int res = 0;
-    if ((e = gsr::launch_sort(fb, key_bits, &res, s)) != hipSuccess) return fail_hip(e, "sort");
-    if ((e = gsr::launch_ranges(fb.keys[res], fb.counters, fb.ranges, fb.capacity, (int)b->tiles, s)) != hipSuccess)
-        return fail_hip(e, "ranges");
+    if ((e = sort_stage(fb, tiles, GSR_MODE_HIER, (uint32_t)prefix_len(&b->cfg), s, nullptr)) != hipSuccess)
+        return fail_hip(e, "sort");
     const uint32_t* order = nullptr;
     if (b->sched.cost_order) {
         uint64_t* tk[2] = {(uint64_t*)(base + L.tkeys[0]), (uint64_t*)(base + L.tkeys[1])};
@@ -443,6 +521,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
         order = tv[tres];
     }
     gsr::BatchArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
     ba.views = (const gsr::ViewDev*)(base + L.views);
     ba.n_views = (int)b->views.size();
     ba.n_records = (uint32_t)b->R;
@@ -450,23 +529,36 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.co = fb.co;
     ba.sw = fb.sw;
     ba.zd = fb.zd;
-    ba.vals = fb.vals[res];
+    ba.vals = fb.vals[0];
     ba.ranges = fb.ranges;
     ba.order = order;
+    ba.list_mode = gsr::kListPrefix;
+    ba.pre_vals = fb.pre_vals;
+    ba.pre_len = fb.pre_len;
+    ba.tile_flag = fb.tile_flag;
     ba.queue = fb.counters + 1;
     ba.n_items = (uint32_t)(4 * b->tiles);
+    ba.n_tiles_dev = nullptr;
     ba.bg0 = b->cfg.bg[0];
     ba.bg1 = b->cfg.bg[1];
     ba.bg2 = b->cfg.bg[2];
     const unsigned grid = (unsigned)(b->cu_count * std::max(1, b->sched.wgs_per_cu));
     if ((e = gsr::launch_render_hier_batch(ba, b->cfg.head, grid, s)) != hipSuccess) return fail_hip(e, "render");
+    // Tiles whose prefix ran out: compacted, fully sorted and rendered again.
+    if ((e = fallback_sort(fb, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
+    ba.list_mode = gsr::kListFlagged;
+    ba.order = fb.flist;
+    ba.n_tiles_dev = fb.counters + 6;
+    ba.queue = fb.counters + 7;
+    if ((e = gsr::launch_render_hier_batch(ba, b->cfg.head, grid, s)) != hipSuccess)
+        return fail_hip(e, "render fallback");
     return GSR_OK;
 }
 
 std::string batch_key(const gsr_batch* b) {
     std::ostringstream k;
     k << "gfx950-" << b->cu_count << "cu-views" << b->views.size() << "-records" << b->R << "-tiles" << b->tiles
-      << "-head" << b->cfg.head;
+      << "-head" << b->cfg.head << "-prefix" << prefix_len(&b->cfg);
     return k.str();
 }
 
@@ -606,24 +698,24 @@ int gsr_batch_tune(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream, const
     for (const gsr_schedule& c : cands) {
         b->sched = c;
         if ((rc = batch_render_impl(b, status_dev, s))) break;
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         for (int r = 0; r < reps && !rc; ++r) rc = batch_render_impl(b, status_dev, s);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         if (rc) break;
         if (hipEventSynchronize(e1) != hipSuccess) {
             rc = fail(GSR_EDEVICE, "tune sync");
             break;
         }
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)reps;
         if (ms < best) {
             best = ms;
             bs = c;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     b->sched = bs;
     if (rc) return rc;
     if (best_out) *best_out = bs;
@@ -665,6 +757,7 @@ void gsr_default_config(gsr_config* c) {
     c->mid_batch = 4;
     c->head = 4;
     c->lb_threshold = 32;
+    c->sort_prefix = 0;
 }
 
 int gsr_check_config(const gsr_config* c) {
@@ -672,6 +765,7 @@ int gsr_check_config(const gsr_config* c) {
     if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER) return fail(GSR_EINVAL, "unknown mode");
     if (c->flags != 0) return fail(GSR_EINVAL, "flags must be 0");
     if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
+    if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..4096");
     if (c->mode == GSR_MODE_HIER) {
         if (c->tail < 64 || (c->tail - 32) % 32 != 0) return fail(GSR_EINVAL, "tail must be 32n+32, n>=1");
         if (c->mid < 8 || (c->mid - 4) % 4 != 0) return fail(GSR_EINVAL, "mid must be 4m+4, m>=1");
@@ -708,6 +802,11 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 int gsr_sort_passes(int32_t W, int32_t H) {
     if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
     return gsr::sort_pass_count(32 + bits_for_tiles(tiles_of(W, H)));
+}
+
+int gsr_group_passes(int32_t W, int32_t H) {
+    if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
+    return sort_plan(tiles_of(W, H), GSR_MODE_HIER).tile_passes;
 }
 
 int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,

@@ -110,7 +110,7 @@ struct PreOut {
 // Projection and colour of Gaussian i (Sec. 2.1, App. A, App. B.2, App. B.4).
 // Returns false (and writes a zero record) when the Gaussian is culled.
 __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, int i, const PreOut& out,
-                            Splat& g, int4& rc) {
+                            const float* shp, Splat& g, int4& rc) {
     const float mu0 = sc.means[3 * i], mu1 = sc.means[3 * i + 1], mu2 = sc.means[3 * i + 2];
     const float s0 = sc.scales[3 * i], s1 = sc.scales[3 * i + 1], s2 = sc.scales[3 * i + 2];
     const float4 qv = reinterpret_cast<const float4*>(sc.rots)[i];
@@ -240,7 +240,6 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
                 const int deg = sc.deg;
                 sh_basis(deg, x, y, z, bas);
                 const int K = (deg + 1) * (deg + 1);
-                const float* shp = sc.sh + (size_t)i * 3 * K;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     float acc = bas[0] * shp[ch];
@@ -297,51 +296,116 @@ struct PreArgs {
     int mode, lb;
     PreOut out;
     uint32_t* touched;
+    uint32_t* kmask;
 };
 
-// One lane per Gaussian.  Gaussians whose rectangle holds more than `lb`
-// tiles are counted in a second phase by the whole wavefront (Sec. 3.4,
-// load balancing), one Gaussian at a time, tiles spread over the lanes.
+// Gaussians whose rectangle has at most this many tiles are handled by one
+// lane in preprocessing and keep a bit mask of their kept tiles; larger ones
+// are shared across the wavefront (load balancing, Sec. 3.4).
+__device__ __forceinline__ int lane_tile_limit(int lb) { return lb < 32 ? lb : 32; }
+
+// SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
+// stride so that lanes reading their own rows hit distinct banks.
+constexpr int kShStride = 49;
+
+// Per-wavefront staging for the flat kept-tile test (reuses the SH memory).
+struct CountStage {
+    float x[64], y[64], ca[64], cb[64], cc[64], op[64];
+    int rx0[64], ry0[64], rw[64];
+    uint32_t pfx[64], mask[64];
+};
+static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "staging fits the SH area");
+
+// One lane per Gaussian.  Gaussians whose rectangle holds more than
+// lane_tile_limit(lb) tiles are counted in a second phase by the whole
+// wavefront (Sec. 3.4, load balancing), one Gaussian at a time, tiles spread
+// over the lanes; the others record which rectangle tiles they keep.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
+    __shared__ float s_sh[256 * kShStride];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
+    // Coalesced load of this workgroup's SH coefficients into LDS.
+    const int K = (a.sc.deg + 1) * (a.sc.deg + 1), row = 3 * K;
+    const int b0 = blockIdx.x * blockDim.x;
+    const int nloc = min((int)blockDim.x, a.sc.n - b0);
+    const float* src = a.sc.sh + (size_t)b0 * row;
+    for (int f = threadIdx.x; f < nloc * row; f += blockDim.x) {
+        const int gidx = f / row;
+        s_sh[gidx * kShStride + (f - gidx * row)] = src[f];
+    }
+    __syncthreads();
     Splat g;
     int4 rc = make_int4(0, 0, -1, -1);
     bool vis = false;
-    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, i, a.out, g, rc);
+    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, i, a.out, s_sh + threadIdx.x * kShStride, g, rc);
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = vis ? wdt * hgt : 0;
-    uint32_t cnt = 0;
-    const bool deferred = vis && a.mode == kModeHier && area > a.lb;
-    if (vis && !deferred) {
-        if (a.mode == kModeGlobal) {
-            cnt = (uint32_t)area;
-        } else {
-            for (int ty = rc.y; ty <= rc.w; ++ty)
-                for (int tx = rc.x; tx <= rc.z; ++tx) {
-                    float2 xh;
-                    cnt += tile_kept(g, a.cam, tx, ty, xh) ? 1u : 0u;
-                }
+    uint32_t cnt = 0, mask = 0;
+    const bool deferred = vis && a.mode == kModeHier && area > lane_tile_limit(a.lb);
+    if (a.mode == kModeGlobal) {
+        cnt = (uint32_t)area;
+    } else {
+        // Kept-tile test of all (Gaussian, rectangle tile) pairs of the lane-
+        // handled Gaussians of this wavefront as one flat list, one pair per
+        // lane per step; kept tiles set bits of their Gaussian's mask in LDS.
+        __syncthreads();  // the SH rows are no longer needed: reuse the memory
+        CountStage& st = reinterpret_cast<CountStage*>(s_sh)[threadIdx.x >> 6];
+        const uint32_t my = (vis && !deferred) ? (uint32_t)area : 0u;
+        uint32_t incl = my;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+            if (lane >= o) incl += y;
         }
+        const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+        st.x[lane] = g.x; st.y[lane] = g.y; st.ca[lane] = g.ca; st.cb[lane] = g.cb; st.cc[lane] = g.cc;
+        st.op[lane] = g.op;
+        st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
+        st.pfx[lane] = incl - my;
+        st.mask[lane] = 0u;
+        wave_lds_sync();
+        for (uint32_t q = lane; q < total; q += 64) {
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (st.pfx[mid] <= q)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int k = (int)(q - st.pfx[lo]);
+            const int rw = st.rw[lo];
+            Splat h;
+            h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
+            float2 xh;
+            if (tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw, xh)) atomicOr(&st.mask[lo], 1u << k);
+        }
+        wave_lds_sync();
+        mask = st.mask[lane];
+        cnt = (uint32_t)__popc(mask);
     }
     uint64_t pend = __ballot(deferred);
     while (pend) {
-        const int src = __builtin_ctzll(pend);
+        const int src_lane = __builtin_ctzll(pend);
         pend &= pend - 1;
         Splat h;
-        h.x = __shfl(g.x, src); h.y = __shfl(g.y, src);
-        h.ca = __shfl(g.ca, src); h.cb = __shfl(g.cb, src); h.cc = __shfl(g.cc, src); h.op = __shfl(g.op, src);
-        const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
-        const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
+        h.x = __shfl(g.x, src_lane); h.y = __shfl(g.y, src_lane);
+        h.ca = __shfl(g.ca, src_lane); h.cb = __shfl(g.cb, src_lane); h.cc = __shfl(g.cc, src_lane);
+        h.op = __shfl(g.op, src_lane);
+        const int rx0 = __shfl(rc.x, src_lane), ry0 = __shfl(rc.y, src_lane);
+        const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
         uint32_t c = 0;
         for (int k = lane; k < rarea; k += 64) {
             float2 xh;
             c += tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw, xh) ? 1u : 0u;
         }
         c = wave_reduce_add(c);
-        if (lane == src) cnt = c;
+        if (lane == src_lane) cnt = c;
     }
-    if (i < a.sc.n) a.touched[i] = cnt;
+    if (i < a.sc.n) {
+        a.touched[i] = cnt;
+        a.kmask[i] = mask;
+    }
 }
 
 struct DupArgs {
@@ -353,6 +417,7 @@ struct DupArgs {
     const float2* zd;
     const int4* rect;
     const uint32_t* touched;
+    const uint32_t* kmask;
     const uint32_t* offsets;
     uint64_t* keys;
     uint32_t* vals;
@@ -370,14 +435,28 @@ __device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32
     }
 }
 
-// One lane per Gaussian: every kept tile of the rectangle becomes a key
-// (tile << 32 | depth bits), depth = t_opt along the ray through the tile's
-// maximum point (tile-depth adjustment, Sec. 3.4), or the view depth in the
-// global mode.  Large Gaussians go through the cooperative second phase with
-// ballot-compacted writes (App. B.4).
+// Per-wavefront staging of the 64 Gaussians whose kept tiles are enumerated.
+struct DupStage {
+    float x[64], y[64], ca[64], cb[64], cc[64], op[64];
+    float s00[64], s01[64], s02[64], s11[64], s12[64], s22[64], w0[64], w1[64], w2[64];
+    float z[64];
+    int rx0[64], ry0[64], rw[64];
+    uint32_t mask[64], off[64], pfx[64];
+};
+
+// Duplication: every kept tile becomes a key (tile << 32 | depth bits) with
+// depth = t_opt along the ray through the tile's maximum point (tile-depth
+// adjustment, Sec. 3.4), or the view depth in the global mode.  A wavefront
+// enumerates the kept (Gaussian, tile) pairs of its lane-handled Gaussians
+// as one flat list, one pair per lane per step (balanced work; consecutive
+// lanes write consecutive entries of a Gaussian); Gaussians with large
+// rectangles go through the cooperative phase with ballot-compacted writes
+// (App. B.4).
 __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
+    __shared__ DupStage s_st[4];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = __lane_id();
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    DupStage& st = s_st[wave];
     uint32_t cnt = 0;
     if (i < a.n) cnt = a.touched[i];
     Splat g;
@@ -392,23 +471,56 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     }
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = cnt > 0 ? wdt * hgt : 0;
-    const bool deferred = cnt > 0 && a.mode == kModeHier && area > a.lb;
-    if (cnt > 0 && !deferred) {
-        uint32_t k = 0;
-        for (int ty = rc.y; ty <= rc.w; ++ty)
-            for (int tx = rc.x; tx <= rc.z; ++tx) {
-                const uint32_t tile = (uint32_t)(ty * a.cam.tiles_x + tx);
-                if (a.mode == kModeGlobal) {
-                    put_entry(a, off + k, tile, depth_bits(zdepth), (uint32_t)i);
-                    ++k;
-                    continue;
-                }
-                float2 xh;
-                if (!tile_kept(g, a.cam, tx, ty, xh)) continue;
-                const float t = t_opt(g, cam_ray(a.cam, xh.x, xh.y));
-                put_entry(a, off + k, tile, depth_bits(t), (uint32_t)i);
-                ++k;
-            }
+    const bool small = cnt > 0 && area <= lane_tile_limit(a.lb);
+    const bool deferred = cnt > 0 && !small;
+    uint32_t mask = 0;
+    if (small) mask = a.mode == kModeHier ? a.kmask[i] : (area >= 32 ? 0xffffffffu : ((1u << area) - 1u));
+    const uint32_t my = small ? cnt : 0u;
+    uint32_t incl = my;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
+        if (lane >= o) incl += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    st.x[lane] = g.x; st.y[lane] = g.y; st.ca[lane] = g.ca; st.cb[lane] = g.cb; st.cc[lane] = g.cc;
+    st.op[lane] = g.op; st.s00[lane] = g.s00; st.s01[lane] = g.s01; st.s02[lane] = g.s02; st.s11[lane] = g.s11;
+    st.s12[lane] = g.s12; st.s22[lane] = g.s22; st.w0[lane] = g.w0; st.w1[lane] = g.w1; st.w2[lane] = g.w2;
+    st.z[lane] = zdepth;
+    st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
+    st.mask[lane] = mask; st.off[lane] = off; st.pfx[lane] = incl - my;
+    wave_lds_sync();
+    const uint32_t id_wave = (uint32_t)(blockIdx.x * blockDim.x + wave * 64);
+    for (uint32_t q = lane; q < total; q += 64) {
+        // owner: the last lane whose prefix is <= q
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (st.pfx[mid] <= q)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t r = q - st.pfx[lo];
+        uint32_t m = st.mask[lo];
+        for (uint32_t c = 0; c < r; ++c) m &= m - 1u;  // drop the r lowest kept tiles
+        const int k = __builtin_ctz(m);
+        const int rw = st.rw[lo];
+        const int tx = st.rx0[lo] + k % rw, ty = st.ry0[lo] + k / rw;
+        uint32_t dbits;
+        if (a.mode == kModeGlobal) {
+            dbits = depth_bits(st.z[lo]);
+        } else {
+            Splat h;
+            h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
+            h.s00 = st.s00[lo]; h.s01 = st.s01[lo]; h.s02 = st.s02[lo]; h.s11 = st.s11[lo]; h.s12 = st.s12[lo];
+            h.s22 = st.s22[lo]; h.w0 = st.w0[lo]; h.w1 = st.w1[lo]; h.w2 = st.w2[lo];
+            float x0, x1, y0, y1;
+            tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+            const float2 xh = box_max_point(h, x0, x1, y0, y1);
+            dbits = depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
+        }
+        put_entry(a, st.off[lo] + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits, id_wave + (uint32_t)lo);
     }
     uint64_t pend = __ballot(deferred);
     while (pend) {
@@ -420,6 +532,7 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         h.s00 = __shfl(g.s00, src); h.s01 = __shfl(g.s01, src); h.s02 = __shfl(g.s02, src);
         h.s11 = __shfl(g.s11, src); h.s12 = __shfl(g.s12, src); h.s22 = __shfl(g.s22, src);
         h.w0 = __shfl(g.w0, src); h.w1 = __shfl(g.w1, src); h.w2 = __shfl(g.w2, src);
+        const float hz = __shfl(zdepth, src);
         const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
         const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
         uint32_t base = __shfl(off, src);
@@ -427,18 +540,23 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         for (int k0 = 0; k0 < rarea; k0 += 64) {
             const int k = k0 + lane;
             bool keep = false;
-            float t = 0.0f;
+            uint32_t dbits = 0;
             int tx = 0, ty = 0;
             if (k < rarea) {
                 tx = rx0 + k % rw;
                 ty = ry0 + k / rw;
-                float2 xh;
-                keep = tile_kept(h, a.cam, tx, ty, xh);
-                if (keep) t = t_opt(h, cam_ray(a.cam, xh.x, xh.y));
+                if (a.mode == kModeGlobal) {
+                    keep = true;
+                    dbits = depth_bits(hz);
+                } else {
+                    float2 xh;
+                    keep = tile_kept(h, a.cam, tx, ty, xh);
+                    if (keep) dbits = depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
+                }
             }
             const uint64_t m = __ballot(keep);
             if (keep) put_entry(a, base + (uint32_t)__popcll(m & lanemask_lt()), (uint32_t)(ty * a.cam.tiles_x + tx),
-                                depth_bits(t), id);
+                                dbits, id);
             base += (uint32_t)__popcll(m);
         }
     }
@@ -755,6 +873,7 @@ hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, i
     a.lb = lb;
     a.out = PreOut{b.xy, b.co, b.sw, b.zd, b.rect};
     a.touched = b.touched;
+    a.kmask = b.kmask;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -787,6 +906,7 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const Fr
     a.zd = b.zd;
     a.rect = b.rect;
     a.touched = b.touched;
+    a.kmask = b.kmask;
     a.offsets = b.offsets;
     a.keys = b.keys[buf];
     a.vals = b.vals[buf];

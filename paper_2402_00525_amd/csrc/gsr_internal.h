@@ -18,14 +18,19 @@ struct FrameBufs {
     float2* zd;       // view depth, |mu - o|
     int4* rect;       // tile rectangle, inclusive
     uint32_t* touched;
+    uint32_t* kmask;          // kept-tile bit mask of lane-handled Gaussians
     uint32_t* offsets;
     uint32_t* scan_partial;   // scan scratch, >= scan_partial_len(max(n, hist)) + 2
     uint64_t* keys[2];
     uint32_t* vals[2];
     uint32_t* hist;           // radix histograms, kSortMaxBins x sort blocks
     uint32_t* ranges;         // [tiles][2]
-    uint32_t* counters;       // [0] entries, [1] consumed by render, [2..3] spare
+    uint32_t* counters;       // [0] entries, [1] consumed, [3] entries needed, [4] fallback flag, [5] gated n
     uint32_t capacity;
+    uint32_t* pre_vals;       // [capacity] sorted prefix ids at each tile's range begin
+    uint32_t* pre_len;        // [tiles]
+    uint32_t* tile_flag;      // [tiles] entry count of a tile rendered from the fallback, else 0
+    uint32_t* flist;          // [tiles] flagged tiles (batch)
 };
 
 struct SceneArgs {
@@ -80,7 +85,22 @@ hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_
 // scan_partial_len(kSortMaxBins * sort_blocks(cap)) + 2.
 hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], const uint32_t* n_ptr, size_t cap,
                              uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
-                             void* const* scatter_events = nullptr);
+                             void* const* scatter_events = nullptr, int shift0 = 0);
+// Largest supported sorted prefix per tile (LDS of k_tile_prefix).
+constexpr int kMaxPrefix = 4096;
+// Per-tile sorted prefix from tile-grouped keys: the C <= M entries of
+// smallest (depth, id), sorted, at out[range begin + j] (ids); len[tile] = C
+// (C = all entries when the tile has at most M).  M <= kMaxPrefix.
+hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges, uint32_t n_tiles,
+                              uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s);
+// Whole sorted list of every flagged tile (flag[t] = its entry count) at
+// out[range begin ..], len[t] = count; `scratch` is a second key buffer of the
+// same capacity and the grouped keys are overwritten.  counters[5] += flagged
+// entries, counters[6] += flagged tiles; flagged tiles appended to flist if
+// given.
+hipError_t launch_tile_sort_flagged(uint64_t* keys, const uint32_t* vals, uint64_t* scratch, const uint32_t* ranges,
+                                    const uint32_t* flag, uint32_t n_tiles, uint32_t* out, uint32_t* len,
+                                    uint32_t* counters, uint32_t* flist, hipStream_t s);
 // Cost keys for ordering tiles: key[t] = ~(list length of tile t), val[t] = t.
 hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals,
                                  hipStream_t s);
@@ -111,7 +131,19 @@ struct RenderArgs {
     const float* rgb_in;
     const float* T_in;
     float* grad2d;
+    // Which list a tile is rendered from (list_mode):
+    //   kListFull     vals + ranges (fully sorted entries)
+    //   kListPrefix   the tile's sorted prefix pre_vals[range begin ..], pre_len[tile];
+    //                 a tile whose pixels outlive a truncated prefix gets
+    //                 tile_flag[tile] = its entry count
+    //   kListFlagged  only flagged tiles, from pre_vals (now their whole list)
+    //   kListSorted   every tile from pre_vals / pre_len (after the fallback)
+    int list_mode;
+    const uint32_t* pre_vals;
+    const uint32_t* pre_len;
+    uint32_t* tile_flag;
 };
+enum { kListFull = 0, kListPrefix = 1, kListFlagged = 2, kListSorted = 3 };
 
 // Per-view descriptor of a batch, in device memory.
 struct ViewDev {
@@ -135,8 +167,13 @@ struct BatchArgs {
     const uint32_t* vals;
     const uint32_t* ranges;   // per global tile
     const uint32_t* order;    // global tiles in work order (nullptr: natural order)
+    int list_mode;            // as RenderArgs::list_mode
+    const uint32_t* pre_vals;
+    const uint32_t* pre_len;
+    uint32_t* tile_flag;
     uint32_t* queue;          // work-queue head, zero before the launch
     uint32_t n_items;         // 4 strips per global tile
+    const uint32_t* n_tiles_dev;  // if set, n_items = 4 * *n_tiles_dev (tiles listed in order)
     float bg0, bg1, bg2;
 };
 

@@ -271,6 +271,29 @@ struct HierCtx {
 // One wavefront renders one 16x4 strip (`strip` = 0..3) of four 4x4 sub-tiles
 // of tile `tile` (image tile index); its list is ranges[range_tile].  Returns
 // the number of list entries the wavefront read before its pixels finished.
+// The entry list a tile is rendered from (ranks are positions in it).
+struct TileList {
+    const uint32_t* ids;
+    uint32_t len;    // entries in ids
+    uint32_t n_all;  // entries of the tile
+    bool truncated;  // ids is a prefix of the tile's order
+    bool skip;       // nothing to do for this tile in this pass
+};
+
+__device__ __forceinline__ TileList tile_list(const RenderArgs& a, int t) {
+    const uint32_t rb = a.ranges[2 * t], re = a.ranges[2 * t + 1];
+    TileList L{a.vals + rb, re - rb, re - rb, false, false};
+    if (a.list_mode == kListFull) return L;
+    if (a.list_mode == kListFlagged && a.tile_flag[t] == 0u) {
+        L.skip = true;
+        return L;
+    }
+    L.ids = a.pre_vals + rb;
+    L.len = a.pre_len[t];
+    L.truncated = a.list_mode == kListPrefix && L.len < L.n_all;
+    return L;
+}
+
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, int range_tile, int strip,
                                                  WaveQueues& q, float* acc) {
@@ -331,7 +354,13 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     int tb = 0, ts = 0, tn = 0;  // tail state, uniform over the row
     const int row = h.row, j = h.j;
 
-    const uint32_t begin = a.ranges[2 * range_tile], end = a.ranges[2 * range_tile + 1];
+    // The tile's list: entries list[0 .. end), rank = position in the list.
+    const TileList tl = tile_list(a, range_tile);
+    if (tl.skip) return 0u;
+    const uint32_t* list = tl.ids;
+    const uint32_t end = tl.len;
+    const bool truncated = tl.truncated;
+    const uint32_t begin = 0;
     uint32_t b0 = begin;
     for (; b0 < end; b0 += kBatch) {
         const uint64_t live = __ballot(!h.st.done);
@@ -345,7 +374,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         for (int hh = 0; hh < 2; ++hh) {
             const uint32_t e = b0 + (uint32_t)(j + 16 * hh);
             if (e < end) {
-                uint32_t id = a.vals[e];
+                uint32_t id = list[e];
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
                 const Splat g = load_splat(a.xy, a.co, a.sw, id);
@@ -400,6 +429,11 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
             ts += kPop;
             tn -= kPop;
         }
+    }
+    // A prefix that ran out while pixels of this strip are still live cannot
+    // decide the tile: flag it for the full list.
+    if (truncated && b0 >= end && __ballot(!h.st.done) != 0ull) {
+        if (lane == 0) a.tile_flag[range_tile] = tl.n_all;  // same value from every strip
     }
     // Drain: the tail in chunks, then the mid queues, then the heads.
     {
@@ -461,10 +495,12 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     }
     if (MODE == kBwd) {
         // One global atomic per (tile, Gaussian, component) instead of one per blend.
-        const uint32_t begin = a.ranges[2 * blockIdx.x], end = a.ranges[2 * blockIdx.x + 1];
-        const uint32_t len = end - begin < (uint32_t)kAccSlots ? end - begin : (uint32_t)kAccSlots;
+        const TileList tl = tile_list(a, blockIdx.x);
+        const uint32_t* list = tl.ids;
+        const uint32_t n_list = tl.skip ? 0u : tl.len;
+        const uint32_t len = n_list < (uint32_t)kAccSlots ? n_list : (uint32_t)kAccSlots;
         for (uint32_t r = threadIdx.x; r < len; r += 256) {
-            uint32_t id = a.vals[begin + r];
+            uint32_t id = list[r];
             id = id < a.n ? id : 0u;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -484,12 +520,13 @@ template <int K>
 __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
     __shared__ WaveQueues s_q[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t n_items = b.n_tiles_dev ? 4u * *b.n_tiles_dev : b.n_items;
     for (;;) {
         uint32_t item = 0;
         if (lane == 0) item = atomicAdd(b.queue, 1u);
         item = (uint32_t)__shfl((int)item, 0);
         item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= b.n_items) break;
+        if (item >= n_items) break;
         const uint32_t slot = item >> 2;
         const uint32_t gt = b.order ? b.order[slot] : slot;
         // view of global tile gt: the last view whose first tile is <= gt
@@ -526,6 +563,10 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.rgb_in = nullptr;
         a.T_in = nullptr;
         a.grad2d = nullptr;
+        a.list_mode = b.list_mode;
+        a.pre_vals = b.pre_vals;
+        a.pre_len = b.pre_len;
+        a.tile_flag = b.tile_flag;
         render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
     }
 }

@@ -9,6 +9,8 @@
 // keys stably (rounds in index order, wavefronts in order, lanes in order).
 // The number of keys is read on the device, so the sort can be enqueued
 // without knowing it on the host.
+#include <algorithm>
+
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -197,20 +199,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     }
 }
 
+
 }  // namespace
 
 int sort_pass_count(int bits) { return (bits + kMaxDigitBits - 1) / kMaxDigitBits; }
 
 hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], const uint32_t* n_ptr, size_t cap,
                              uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
-                             void* const* scatter_events) {
+                             void* const* scatter_events, int shift0) {
     const size_t nb = sort_blocks(cap);   // a multiple of kHistGroup
     const int passes = sort_pass_count(bits);
     const int width = (bits + passes - 1) / passes;
     int cur = start;
     hipError_t e = hipSuccess;
     for (int p = 0; p < passes; ++p) {
-        const int shift = width * p;
+        const int shift = shift0 + width * p;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)(nb / kHistGroup)), dim3(kSortThreads), 0, s,
                            (const uint64_t*)keys[cur], n_ptr, shift, width, hist, (uint32_t)nb);
         e = launch_scan(hist, hist, nb * ((size_t)1 << width), partial, nullptr, 0xffffffffu, nullptr, s);
@@ -230,7 +233,7 @@ hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_
     // Duplication writes into buffer (passes & 1) so that the result lands in buffer 0.
     const int passes = sort_pass_count(bits);
     return launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, bits, passes & 1,
-                             result_buf, s, scatter_events);
+                             result_buf, s, scatter_events, 0);
 }
 
 namespace {

@@ -40,19 +40,20 @@ class CCamera(C.Structure):
 class CConfig(C.Structure):
     _fields_ = [("mode", C.c_int32), ("batch", C.c_int32), ("tail", C.c_int32), ("pop", C.c_int32),
                 ("mid", C.c_int32), ("mid_batch", C.c_int32), ("head", C.c_int32), ("lb_threshold", C.c_int32),
-                ("bg", C.c_float * 3), ("flags", C.c_uint32)]
+                ("bg", C.c_float * 3), ("flags", C.c_uint32), ("sort_prefix", C.c_int32)]
 
 
 class CLayout(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
-                ("xy", "conic_o", "sw", "zd", "rect", "touched", "offsets", "grad2d", "keys", "values", "ranges",
-                 "counters", "entry_capacity", "total_bytes")]
+                ("xy", "conic_o", "sw", "zd", "rect", "touched", "kmask", "offsets", "grad2d", "keys", "values",
+                 "ranges", "counters", "pre_vals", "pre_len", "tile_flag", "entry_capacity", "total_bytes")]
 
 
 _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
-           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_sort_passes", "gsr_probe_math",
+           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_sort_passes", "gsr_group_passes",
+           "gsr_probe_math",
            "gsr_last_error", "gsr_version")
 
 
@@ -86,6 +87,8 @@ def lib():
                                         C.c_void_p, C.c_void_p, C.c_int32]
         L.gsr_sort_passes.restype = C.c_int
         L.gsr_sort_passes.argtypes = [C.c_int32, C.c_int32]
+        L.gsr_group_passes.restype = C.c_int
+        L.gsr_group_passes.argtypes = [C.c_int32, C.c_int32]
         L.gsr_probe_math.restype = C.c_int
         L.gsr_probe_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.gsr_last_error.restype = C.c_char_p
@@ -107,10 +110,10 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0)) -> CConfig:
+def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0), sort_prefix=0) -> CConfig:
     c = CConfig()
     lib().gsr_default_config(C.byref(c))
-    c.mode, c.head, c.lb_threshold = mode, head, lb_threshold
+    c.mode, c.head, c.lb_threshold, c.sort_prefix = mode, head, lb_threshold, sort_prefix
     for i in range(3):
         c.bg[i] = bg[i]
     return c
@@ -252,8 +255,9 @@ class Renderer:
         return self.ws[off:off + nbytes].view(dtype)
 
     def counter(self, n, cam, k):
-        """counters[k]: 0 entries, 1 entries consumed by the renderer, 3 entries needed."""
-        c = self.region(n, cam, "counters", torch.int32, 4)
+        """counters[k]: 0 entries, 1 entries consumed by the renderer, 3 entries
+        needed, 5 entries and 6 number of the tiles that took the fallback."""
+        c = self.region(n, cam, "counters", torch.int32, 8)
         return int(c[k].item())
 
     def records(self, n, cam):
@@ -274,6 +278,19 @@ class Renderer:
         tiles = ((cam.W + 15) // 16) * ((cam.H + 15) // 16)
         ranges = self.region(n, cam, "ranges", torch.int32, 2 * tiles).view(tiles, 2)
         return keys, vals, ranges
+
+    def tile_lists(self, n, cam):
+        """Hierarchical mode: per-tile sorted ids of the last frame (a prefix, or
+        the whole list for tiles that took the fallback) as host numpy arrays;
+        pre_vals is indexed by range start."""
+        E = self.counter(n, cam, 0)
+        F = self.counter(n, cam, 5)
+        tiles = ((cam.W + 15) // 16) * ((cam.H + 15) // 16)
+        get = lambda name, dt, cnt: self.region(n, cam, name, dt, cnt).cpu().numpy().copy()
+        return dict(ranges=get("ranges", torch.int32, 2 * tiles).reshape(tiles, 2),
+                    pre_vals=get("pre_vals", torch.int32, E), pre_len=get("pre_len", torch.int32, tiles),
+                    tile_flag=get("tile_flag", torch.int32, tiles), fallback_entries=F,
+                    fallback_tiles=self.counter(n, cam, 6))
 
 
 def probe_math(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
@@ -464,7 +481,7 @@ class BatchRenderer:
 
     def counters(self):
         off = _blib().gsr_batch_counters_offset(self.handle)
-        return self.ws[off:off + 16].view(torch.int32)
+        return self.ws[off:off + 32].view(torch.int32)
 
     def capacity(self):
         return int(_blib().gsr_batch_entry_capacity(self.handle))

@@ -39,12 +39,17 @@ def test_version_and_default_config(L):
     assert b"gfx950" in L.lib().gsr_version()
     c = L.config()
     assert (c.mode, c.batch, c.tail, c.pop, c.mid, c.mid_batch, c.head, c.lb_threshold) == (1, 32, 64, 16, 8, 4, 4, 32)
+    assert c.sort_prefix == 0
     assert L.lib().gsr_check_config(C.byref(c)) == 0
+    for m in (1, 100, 4096):
+        c.sort_prefix = m
+        assert L.lib().gsr_check_config(C.byref(c)) == 0
 
 
 @pytest.mark.parametrize("field,value,code", [
     ("tail", 48, -1), ("tail", 96, -4), ("mid", 6, -1), ("mid", 12, -4), ("head", 0, -1), ("head", 25, -4),
-    ("mode", 7, -1), ("flags", 1, -1), ("lb_threshold", -1, -1)])
+    ("mode", 7, -1), ("flags", 1, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
+    ("sort_prefix", 4097, -1)])
 def test_config_validation(L, field, value, code):
     # Sec. 3.4: tail = 32n+32, mid = 4m+4, head >= 1; only the built sizes run.
     c = L.config()
@@ -71,3 +76,45 @@ def test_workspace_errors(L):
     with pytest.raises(L.GsrError) as e:
         L.layout(1000, 64, 64, 1024)
     assert e.value.code == L.GSR_ECAPACITY
+
+
+def _batch_structs(L, sizes):
+    from paper_2402_00525_amd import gsr
+    scenes = (gsr.CScene * 2)()
+    for k, n in enumerate((1000, 500)):
+        scenes[k].n, scenes[k].sh_degree = n, 3
+        for f in ("means", "scales", "rots", "opacities", "sh"):
+            setattr(scenes[k], f, 0x1000)       # never dereferenced by the host functions
+    views = (gsr.CView * len(sizes))()
+    for k, (W, H) in enumerate(sizes):
+        views[k].scene = k % 2
+        views[k].cam.W, views[k].cam.H, views[k].cam.fx, views[k].cam.fy = W, H, 100.0, 100.0
+        views[k].rgb = views[k].depth = views[k].count = views[k].T = 0x1000
+    return scenes, views
+
+
+def test_batch_workspace_planning(L):
+    from paper_2402_00525_amd import gsr
+    B = gsr._blib()
+    scenes, views = _batch_structs(L, [(256, 256), (1920, 1080), (33, 17)])
+    small = B.gsr_batch_workspace_bytes(scenes, 2, views, 3, 1000)
+    big = B.gsr_batch_workspace_bytes(scenes, 2, views, 3, 10_000_000)
+    assert 0 < small < big
+    assert big - small >= 24 * (10_000_000 - 1000)      # two key and two value buffers
+    assert B.gsr_batch_workspace_bytes(scenes, 2, views, 3, 0) == 0
+    views[1].scene = 5                                    # out-of-range scene index
+    assert B.gsr_batch_workspace_bytes(scenes, 2, views, 3, 1000) == 0
+    s = gsr.schedule()
+    assert (s.wgs_per_cu, s.cost_order, s.lb_threshold) == (2, 1, 32)
+
+
+def test_sort_pass_count(L):
+    # 32 depth bits + tile bits, digits of at most 9 bits
+    assert L.lib().gsr_sort_passes(1920, 1080) == 5      # 8160 tiles -> 13 bits -> 45 bits
+    assert L.lib().gsr_sort_passes(128, 128) == 5        # 64 tiles -> 38 bits
+    assert L.lib().gsr_sort_passes(16, 16) == 4          # 1 tile -> 32 bits
+    # grouping by tile alone
+    assert L.lib().gsr_group_passes(1920, 1080) == 2     # 13 bits
+    assert L.lib().gsr_group_passes(128, 128) == 1       # 6 bits
+    assert L.lib().gsr_group_passes(16, 16) == 0
+    assert L.lib().gsr_group_passes(0, 16) < 0

@@ -32,22 +32,22 @@ def _compare(gpu, ref, rtol=2e-3):
         assert not bad.any(), (name, err.max() / scale, int(bad.sum()))
 
 
-def _gpu_grads(scene, cam, dL, head=4):
+def _gpu_grads(scene, cam, dL, head=4, sort_prefix=0):
     from paper_2402_00525_amd import gsr
     ds = gsr.DeviceScene.from_host(scene)
     r = gsr.Renderer(entries_hint=max(1 << 16, 64 * scene.n))
-    cfg = gsr.config(head=head)
+    cfg = gsr.config(head=head, sort_prefix=sort_prefix)
     fr = r.render(ds, cam, cfg)
     g = gsr.render_backward(r, ds, cam, cfg, fr, torch.from_numpy(np.ascontiguousarray(dL, np.float32)).cuda())
     torch.cuda.synchronize()
     return fr.rgb.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}
 
 
-@pytest.mark.parametrize("case", ["fd64", "small", "mixture720"])
+@pytest.mark.parametrize("case", ["fd64", "small", "mixture720", "small_prefix16"])
 def test_backward_matches_oracle(case):
     if case == "fd64":
         scene, cam = synth.uniform_scene(64, seed=5, sh_degree=3), synth.front_camera(32, 32)
-    elif case == "small":
+    elif case.startswith("small"):
         scene, cam = synth.uniform_scene(2000, seed=0, sh_degree=1), synth.orbit_camera(128, 96, 2)
     else:
         scene, cam = synth.subsample(synth.mixture_scene(100_000, seed=3), 10_000), synth.orbit_camera(1280, 720, 7)
@@ -56,7 +56,7 @@ def test_backward_matches_oracle(case):
     rgb_o, _, _ = oracle.backward(scene, cam, np.zeros((3, cam.H, cam.W), np.float32), "f32")
     dL = (np.sign(rgb_o - target) / rgb_o.size).astype(np.float32)
     rgb_r, g_ref, _ = oracle.backward(scene, cam, dL, "f32")
-    rgb_g, g_gpu = _gpu_grads(scene, cam, dL)
+    rgb_g, g_gpu = _gpu_grads(scene, cam, dL, sort_prefix=16 if case.endswith("prefix16") else 0)
     np.testing.assert_array_equal(rgb_g.view(np.uint32), rgb_r.view(np.uint32))
     _compare(g_gpu, g_ref)
 

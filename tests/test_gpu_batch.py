@@ -123,6 +123,18 @@ def test_batch_autotune_and_cache(tmp_path):
     _assert_same(_frames_np(b.render()), ref)
 
 
+def test_batch_prefix_fallback_matches():
+    from paper_2402_00525_amd import gsr
+    scenes, views = small_batch()
+    say("case: batch sort prefix 16")
+    b, _ = _batch(scenes, views, cfg=gsr.config(sort_prefix=16))
+    got = _frames_np(b.render())
+    torch.cuda.synchronize()
+    c = b.counters().cpu().numpy()
+    assert c[5] > 0 and c[6] > 0          # fallback entries and tiles
+    _assert_same(got, _single(scenes, views))
+
+
 def test_batch_overflow_replans():
     scenes, views = small_batch()
     say("case: batch overflow")

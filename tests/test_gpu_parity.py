@@ -102,6 +102,40 @@ def test_mixture_scene_1080p_subsample_bit_exact():
     np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
 
 
+@pytest.mark.parametrize("prefix", [1, 16, 100, 4096])
+def test_prefix_fallback_bit_exact(prefix):
+    """Short sorted prefixes force many tiles through the fallback sort; the
+    blend order and images stay those of the full sort."""
+    sc, cam = synth.workload_small()
+    say("case: sort prefix", prefix)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=48)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=48, sort_prefix=prefix)
+    assert_sorted_equal(g, o)
+    if prefix <= 16:
+        assert g["lists"]["fallback_entries"] > 0
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    np.testing.assert_array_equal(g["count"], o.count)
+
+
+def test_prefix_fallback_long_lists():
+    """Faint Gaussians keep pixels alive past every prefix, so tiles of more
+    than 4096 entries take the fallback's radix path."""
+    sc = synth.uniform_scene(30_000, seed=3, sh_degree=0)
+    sc.opacities[:] = (sc.opacities * 0.02).astype(np.float32)
+    cam = synth.front_camera(64, 48)
+    say("case: long fallback lists")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=64)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=64, sort_prefix=256)
+    assert np.diff(o.ranges, axis=1).max() > 4096
+    assert_sorted_equal(g, o)
+    flag = g["lists"]["tile_flag"]
+    assert flag.max() > 4096
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    np.testing.assert_array_equal(g["count"], o.count)
+
+
 def test_edge_cases_empty_culled_nan():
     from paper_2402_00525_amd import gsr
     cam = synth.front_camera(64, 48)
