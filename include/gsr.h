@@ -46,7 +46,17 @@ enum {
     GSR_EUNSUPPORTED = -4  /* device is not gfx950 */
 };
 
-enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1 };
+/* Blend orders:
+ *   GSR_MODE_GLOBAL  3DGS: 3-sigma rectangles, view-space depth keys, each
+ *                    pixel blends its tile's list in key order (Sec. 2.1);
+ *   GSR_MODE_HIER    the hierarchical resorting of Sec. 3.4 (opacity-aware
+ *                    bounds, exact tile culling, tile-depth keys, tail / mid /
+ *                    head queues on per-level t_opt);
+ *   GSR_MODE_WINDOW  per-ray resorting (Sec. 3.3): the 3DGS lists of
+ *                    GSR_MODE_GLOBAL, each pixel keeping a window of `head`
+ *                    samples ordered by t_opt along its ray and blending the
+ *                    front whenever the window overflows. */
+enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1, GSR_MODE_WINDOW = 3 };
 
 enum { GSR_STATUS_OVERFLOW = 1 };
 
@@ -84,7 +94,8 @@ typedef struct gsr_camera {
  *   pop       tail -> mid chunk (16)
  *   mid       mid capacity, 4 m + 4 with m >= 1 (8)
  *   mid_batch mid sub-batch (4)
- *   head      per-pixel head capacity K in 1..24 (4)
+ *   head      per-pixel head capacity K (HIER) or window size (WINDOW),
+ *             one of 1, 2, 3, 4, 6, 8, 12, 16, 20, 24 (4)
  * lb_threshold only changes speed (tiles above which preprocessing and
  * duplication share a Gaussian across the wavefront; 32).
  * bg is the background colour. */
@@ -151,11 +162,10 @@ int gsr_check_config(const gsr_config* cfg /* host */);
  * Gaussian id) order are selected and sorted, and a tile whose pixels are
  * still unfinished when its prefix runs out has its whole list sorted and is
  * rendered again (enqueued always; tiles that need nothing exit at once): the
- * order is that of a full sort by (tile, depth, id) in every case.  In GSR_MODE_HIER the blend order is
- * the hierarchical tail / mid / head resorting on per-level t_opt (Eq. dopt);
- * in GSR_MODE_GLOBAL it is the 3DGS view-space-depth order.
+ * order is that of a full sort by (tile, depth, id) in every case.  The
+ * blend order is that of the mode (see GSR_MODE_*).
  *   rgb     [3,H,W] float32 out   colour + T_final * bg
- *   depth   [H,W]   float32 out   sum of t_opt alpha T (GLOBAL: |mu - o|)
+ *   depth   [H,W]   float32 out   sum of t_opt alpha T (GLOBAL: |mu - o|; WINDOW: t_opt)
  *   count   [H,W]   int32   out   number of Gaussians blended
  *   T_final [H,W]   float32 out   final transmittance
  *   status_dev      int32   in/out, see above

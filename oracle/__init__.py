@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gsr_oracle.cpp")
 LIB = os.path.join(HERE, "libgsr_oracle.so")
 
-MODE_GLOBAL, MODE_HIER, MODE_FULL = 0, 1, 2
+MODE_GLOBAL, MODE_HIER, MODE_FULL, MODE_WINDOW = 0, 1, 2, 3
 
 _lib = None
 

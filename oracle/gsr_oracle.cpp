@@ -207,7 +207,12 @@ struct OCfg {
     float bg[3];
 };
 
-enum { MODE_GLOBAL = 0, MODE_HIER = 1, MODE_FULL = 2 };
+enum { MODE_GLOBAL = 0, MODE_HIER = 1, MODE_FULL = 2, MODE_WINDOW = 3 };
+
+// Modes whose tile lists are those of 3DGS (3-sigma rectangle, every
+// rectangle tile kept, view-space depth keys): the global order, and the
+// per-ray resorting window of Sec. 3.3 that walks the same lists.
+inline bool gs_lists(int mode) { return mode == MODE_GLOBAL || mode == MODE_WINDOW; }
 
 template <class F> struct Cam {
     F R[9], t[3], o[3], fx, fy, cx, cy, znear, limx, limy;
@@ -422,7 +427,7 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
     F mid = F(0.5) * (a + c);
     F lam = mid + std::sqrt(smax(F(0.1), mid * mid - det));
     F rr;
-    if (mode == MODE_GLOBAL) {
+    if (gs_lists(mode)) {
         // 3DGS: a 3-sigma circle.
         rr = std::ceil(F(3) * std::sqrt(lam));
     } else {
@@ -482,7 +487,7 @@ template <class F> int count_tiles(const Cam<F>& cam, int mode, const Rec<F>& g)
     int n = 0;
     for (int ty = g.rect[1]; ty <= g.rect[3]; ++ty)
         for (int tx = g.rect[0]; tx <= g.rect[2]; ++tx) {
-            if (mode == MODE_GLOBAL) { ++n; continue; }
+            if (gs_lists(mode)) { ++n; continue; }
             F a, b, c, d, hx, hy;
             hull(cam, tx * 16, ty * 16, 16, a, b, c, d);
             if (keep_block(g, a, b, c, d, hx, hy)) ++n;
@@ -509,7 +514,7 @@ template <class F> void emit_entries(const Cam<F>& cam, int mode, const Rec<F>& 
     for (int ty = g.rect[1]; ty <= g.rect[3]; ++ty)
         for (int tx = g.rect[0]; tx <= g.rect[2]; ++tx) {
             u32 tile = (u32)(ty * cam.tiles_x + tx);
-            if (mode == MODE_GLOBAL) { out.push_back({tile, ord_key(g.z), id}); continue; }
+            if (gs_lists(mode)) { out.push_back({tile, ord_key(g.z), id}); continue; }
             F a, b, c, d, hx, hy;
             hull(cam, tx * 16, ty * 16, 16, a, b, c, d);
             if (!keep_block(g, a, b, c, d, hx, hy)) continue;
@@ -828,6 +833,45 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
                         // Depth output uses |mu - o|; the per-pixel t_opt is kept for the sort error.
                         blend(P, g, a, topt(g, d), (int)ids[e], true);
                     }
+                }
+        }
+        fr.ms[3] = now_ms() - t0;
+        return;
+    }
+    if (mode == MODE_WINDOW) {
+        // Per-ray resorting (Sec. 3.3): each pixel walks its tile's 3DGS list;
+        // a sample that passes the alpha test is placed by insertion into a
+        // window ordered by (t_opt along the pixel ray, rank in the list); when
+        // the window holds more than cfg.head samples its front is blended.
+        // The walk stops once the pixel has terminated; at the end of the list
+        // the window is blended in order.
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int tile = 0; tile < ntiles; ++tile) {
+            if (tile_mask && !tile_mask[tile]) continue;
+            int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+            const u32 lo = fr.range_lo[tile], hi = fr.range_hi[tile];
+            for (int y = ty * 16; y < std::min(ty * 16 + 16, cam.H); ++y)
+                for (int x = tx * 16; x < std::min(tx * 16 + 16, cam.W); ++x) {
+                    Pixel<F>& P = fr.pix[(size_t)y * cam.W + x];
+                    F d[3];
+                    cam.ray((F)x, (F)y, d);
+                    std::vector<HE<F>> win;
+                    for (u32 e = lo; e < hi && !P.done; ++e) {
+                        const Rec<F>& g = fr.recs[ids[e]];
+                        F a;
+                        if (!pixel_alpha(g, (F)x, (F)y, a)) continue;
+                        const F t = topt(g, d);
+                        HE<F> h{ord_key(t), e - lo, (int)ids[e], a, t};
+                        size_t pos = 0;
+                        while (pos < win.size() && win[pos].before(h)) ++pos;
+                        win.insert(win.begin() + pos, h);
+                        if ((int)win.size() > fr.cfg.head) {
+                            const HE<F> f = win.front();
+                            win.erase(win.begin());
+                            blend(P, fr.recs[f.id], f.alpha, f.t, f.id, false);
+                        }
+                    }
+                    for (const HE<F>& f : win) blend(P, fr.recs[f.id], f.alpha, f.t, f.id, false);
                 }
         }
         fr.ms[3] = now_ms() - t0;

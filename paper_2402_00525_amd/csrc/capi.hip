@@ -221,7 +221,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if ((rc = gsr_check_config(cfg))) return rc;
     if (!ws || !rgb || !depth || !count || !T_final || !status_dev) return fail(GSR_EINVAL, "output or workspace is NULL");
     if (blend_ids && max_k <= 0) return fail(GSR_EINVAL, "max_k must be > 0");
-    if (cfg->mode == GSR_MODE_HIER && !gsr::hier_head_supported(cfg->head))
+    if (cfg->mode != GSR_MODE_GLOBAL && !gsr::hier_head_supported(cfg->head))
         return fail(GSR_EUNSUPPORTED, "head size not built (1,2,3,4,6,8,12,16,20,24)");
     gsr_layout L;
     int64_t spo, hist, k1, v1;
@@ -234,7 +234,8 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
     const int tiles = dc.tiles_x * dc.tiles_y;
-    const int mode = cfg->mode;
+    // GSR_MODE_WINDOW walks the lists of the global order.
+    const int mode = cfg->mode == GSR_MODE_WINDOW ? GSR_MODE_GLOBAL : cfg->mode;
     const SortPlan sp = sort_plan(tiles, mode);
     const uint32_t M = (uint32_t)prefix_len(cfg);
     gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
@@ -283,6 +284,9 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
         if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
         ra.list_mode = gsr::kListFlagged;
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
+    } else if (cfg->mode == GSR_MODE_WINDOW) {
+        ra.list_mode = gsr::kListFull;
+        if ((e = gsr::launch_render_window(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
     } else {
         ra.list_mode = gsr::kListFull;
         if ((e = gsr::launch_render_global(ra, s)) != hipSuccess) return fail_hip(e, "render");
@@ -762,7 +766,8 @@ void gsr_default_config(gsr_config* c) {
 
 int gsr_check_config(const gsr_config* c) {
     if (!c) return fail(GSR_EINVAL, "config is NULL");
-    if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER) return fail(GSR_EINVAL, "unknown mode");
+    if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER && c->mode != GSR_MODE_WINDOW)
+        return fail(GSR_EINVAL, "unknown mode");
     if (c->flags != 0) return fail(GSR_EINVAL, "flags must be 0");
     if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
     if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..4096");
@@ -772,6 +777,10 @@ int gsr_check_config(const gsr_config* c) {
         if (c->head < 1) return fail(GSR_EINVAL, "head must be >= 1");
         if (c->batch != 32 || c->tail != 64 || c->pop != 16 || c->mid != 8 || c->mid_batch != 4 || c->head > 24)
             return fail(GSR_EUNSUPPORTED, "only batch/tail/pop/mid/mid_batch = 32/64/16/8/4 and head <= 24 are built");
+    }
+    if (c->mode == GSR_MODE_WINDOW) {
+        if (c->head < 1) return fail(GSR_EINVAL, "window must be >= 1");
+        if (c->head > 24) return fail(GSR_EUNSUPPORTED, "windows up to 24 are built");
     }
     return GSR_OK;
 }

@@ -178,6 +178,8 @@ struct BatchArgs {
 };
 
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s);
+// Per-ray resorting window of `head` samples over the global order's lists.
+hipError_t launch_render_window(const RenderArgs& a, int head, hipStream_t s);
 hipError_t launch_render_hier_batch(const BatchArgs& b, int head, unsigned grid, hipStream_t s);
 bool hier_head_supported(int head);
 // Hierarchical render with head capacity `head` (1..24).

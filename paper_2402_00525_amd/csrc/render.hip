@@ -21,6 +21,11 @@
 //
 // k_render_global: the 3DGS order -- each pixel blends its tile's list in
 // key order.
+//
+// k_render_window: per-ray resorting (Sec. 3.3) -- each pixel walks its
+// tile's 3DGS list and keeps a window of K samples in registers, ordered by
+// (t_opt along the pixel ray, list rank); the front is blended whenever the
+// window overflows, the rest at the end of the list.
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -644,6 +649,83 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
     if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
 }
 
+// One workgroup per tile; list entries staged through LDS 256 at a time; one
+// lane per pixel with its window in registers (the head machinery of the
+// hierarchical renderer).
+template <int K, int MODE>
+__global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
+    __shared__ Splat s_g[256];
+    __shared__ uint32_t s_id[256];
+    const DevCam& cam = a.cam;
+    const int tile = blockIdx.x;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const int pix = py * cam.W + px;
+    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const float3 d = cam_ray(cam, (float)px, (float)py);
+    PixelState<K, MODE> st;
+    st.T = 1.0f;
+    st.C0 = st.C1 = st.C2 = st.D = 0.0f;
+    st.n = 0;
+    st.done = !inside;
+    st.hn = 0;
+#pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        st.hk[i] = kInvalidKey;
+        st.hid[i] = 0;
+        st.ha[i] = 0.0f;
+    }
+    uint32_t consumed = 0;
+    for (uint32_t start = begin; start < end; start += 256) {
+        if (__syncthreads_count(st.done ? 1 : 0) == 256) break;
+        const uint32_t idx = start + threadIdx.x;
+        if (idx < end) {
+            uint32_t id = a.vals[idx];
+            id = id < a.n ? id : 0u;
+            s_id[threadIdx.x] = id;
+            s_g[threadIdx.x] = load_splat(a.xy, a.co, a.sw, id);
+        }
+        __syncthreads();
+        const uint32_t cnt = (end - start) < 256u ? (end - start) : 256u;
+        consumed += cnt;
+        for (uint32_t k = 0; k < cnt && !st.done; ++k) {
+            const Splat& g = s_g[k];
+            float alpha;
+            if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
+            const uint64_t key = ((uint64_t)depth_bits(t_opt(g, d)) << 32) | (uint64_t)(start - begin + k);
+            head_insert<K, MODE>(st, key, s_id[k], alpha);
+            if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix, nullptr);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i <= K; ++i)
+        if (st.hn > 0) head_pop_blend<K, MODE>(a, st, pix, nullptr);
+    if (inside) {
+        const size_t P = (size_t)cam.W * cam.H;
+        a.rgb[pix] = st.C0 + st.T * a.bg0;
+        a.rgb[P + pix] = st.C1 + st.T * a.bg1;
+        a.rgb[2 * P + pix] = st.C2 + st.T * a.bg2;
+        a.depth[pix] = st.D;
+        a.count[pix] = st.n;
+        a.T[pix] = st.T;
+        if (MODE == kFwdDebug)
+            for (int k = st.n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+    }
+    if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
+}
+
+template <int K>
+hipError_t launch_window_k(const RenderArgs& a, hipStream_t s) {
+    const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
+    if (a.blend_ids)
+        hipLaunchKernelGGL((k_render_window<K, kFwdDebug>), dim3(tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_render_window<K, kFwd>), dim3(tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
@@ -701,6 +783,22 @@ hipError_t launch_render_hier_batch(const BatchArgs& b, int head, unsigned grid,
         case 16: return launch_hier_batch_k<16>(b, grid, s);
         case 20: return launch_hier_batch_k<20>(b, grid, s);
         case 24: return launch_hier_batch_k<24>(b, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_render_window(const RenderArgs& a, int head, hipStream_t s) {
+    switch (head) {
+        case 1: return launch_window_k<1>(a, s);
+        case 2: return launch_window_k<2>(a, s);
+        case 3: return launch_window_k<3>(a, s);
+        case 4: return launch_window_k<4>(a, s);
+        case 6: return launch_window_k<6>(a, s);
+        case 8: return launch_window_k<8>(a, s);
+        case 12: return launch_window_k<12>(a, s);
+        case 16: return launch_window_k<16>(a, s);
+        case 20: return launch_window_k<20>(a, s);
+        case 24: return launch_window_k<24>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

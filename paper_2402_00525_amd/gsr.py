@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsr.so")
 
 GSR_OK, GSR_EINVAL, GSR_ECAPACITY, GSR_EDEVICE, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4
-MODE_GLOBAL, MODE_HIER = 0, 1
+MODE_GLOBAL, MODE_HIER, MODE_WINDOW = 0, 1, 3
 STATUS_OVERFLOW = 1
 
 

@@ -136,6 +136,32 @@ def test_prefix_fallback_long_lists():
     np.testing.assert_array_equal(g["count"], o.count)
 
 
+@pytest.mark.parametrize("K", [1, 4, 8, 16, 24])
+def test_window_mode_bit_exact(K):
+    """Per-ray resorting window (Sec. 3.3) over the 3DGS lists."""
+    sc, _ = synth.workload_small()
+    cam = synth.orbit_camera(144, 100, view=9)
+    say("case: window", K)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_WINDOW, head=K, max_k=64)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_WINDOW, head=K, max_k=64)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+
+
+def test_window_mode_mixture_1080p():
+    sc = synth.subsample(synth.mixture_scene(200_000, seed=1), 20_000)
+    cam = synth.orbit_camera(1920, 1080, view=21)
+    say("case: window 16, 20k mixture at 1080p")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_WINDOW, head=16, max_k=16)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_WINDOW, head=16, max_k=16)
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    assert_images_close(g, o, TOL)
+
+
 def test_edge_cases_empty_culled_nan():
     from paper_2402_00525_amd import gsr
     cam = synth.front_camera(64, 48)

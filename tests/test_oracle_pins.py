@@ -15,6 +15,9 @@ method, brute force, or an invariant that the paper's definitions imply:
 * the hierarchical order against the brute-force full per-pixel sort when
   the head queue can hold every contributor;
 * the full order under an exact 180-degree camera roll;
+* the per-ray resorting window (Sec. 3.3) against the global order when the
+  per-ray order is the list order, and against the brute-force full sort when
+  the window never overflows;
 * queue-capacity invariants of the hierarchy (Sec. 3.4);
 * conservativeness and exactness of tile culling against brute force over
   pixel centres.
@@ -368,6 +371,56 @@ def test_hier_sorts_better_than_global_and_queue_invariants():
     assert st["min_tail_after_pop"] >= 17
     # 16 sub-tiles per tile see every tile entry; culling only removes
     assert st["tail_in"] <= 16 * st["entries"]
+
+
+# ---------------------------------------------------------------------------
+# Per-ray resorting window (Sec. 3.3)
+# ---------------------------------------------------------------------------
+def test_window_equals_global_when_ray_order_is_list_order():
+    # Isotropic Gaussians on the optical axis: along any pixel ray d the
+    # depth of maximum contribution is d . (mu - o), a positive multiple of
+    # the view depth, so every ray sees them in the 3DGS list order and the
+    # window can never reorder them, whatever its size.
+    cam = synth.front_camera(64, 48)
+    rng = np.random.default_rng(11)
+    z = np.sort(rng.uniform(-1.5, 1.5, 40))[::-1].copy()        # far first in index order
+    sc = make_scene([[0.0, 0.0, zz] for zz in z], [[s] * 3 for s in rng.uniform(0.05, 0.4, 40)],
+                    [[1, 0, 0, 0]] * 40, rng.uniform(0.05, 0.5, 40), rng.uniform(-1, 1, (40, 1, 3)))
+    g = oracle.frame(sc, cam, mode=oracle.MODE_GLOBAL, max_k=48)
+    assert g.count.max() > 10
+    for K in (1, 4, 24):
+        w = oracle.frame(sc, cam, mode=oracle.MODE_WINDOW, head=K, max_k=48)
+        np.testing.assert_array_equal(w.blend_ids, g.blend_ids)
+        np.testing.assert_array_equal(w.count, g.count)
+        np.testing.assert_array_equal(w.rgb.view(np.uint32), g.rgb.view(np.uint32))
+        np.testing.assert_array_equal(w.T.view(np.uint32), g.T.view(np.uint32))
+
+
+def test_window_without_overflow_equals_full_sort():
+    # With opacity <= 0.35 a Gaussian clears alpha >= 1/255 only where
+    # (x - mu)^T Sigma_2^-1 (x - mu) <= 2 ln(255 o) < 9, i.e. inside its
+    # 3-sigma circle, so every contributor of a pixel is in that pixel's 3DGS
+    # tile list; a window larger than any list then blends exactly the
+    # brute-force per-pixel sort.
+    sc = synth.uniform_scene(400, seed=17)
+    sc.opacities[:] = np.float32(0.05) + sc.opacities * np.float32(0.3 / 0.99)
+    assert sc.opacities.max() <= 0.35
+    cam = synth.front_camera(80, 64)
+    full = oracle.frame(sc, cam, mode=oracle.MODE_FULL, max_k=128)
+    win = oracle.frame(sc, cam, mode=oracle.MODE_WINDOW, head=100000, max_k=128)
+    assert full.count.max() < 128
+    np.testing.assert_array_equal(win.blend_ids, full.blend_ids)
+    np.testing.assert_array_equal(win.count, full.count)
+    np.testing.assert_array_equal(win.rgb.view(np.uint32), full.rgb.view(np.uint32))
+    assert win.delta.max() == 0.0
+
+
+def test_window_sort_error_falls_with_window_size():
+    # Table sortcost: the per-ray sort error shrinks as the window grows.
+    sc, cam = synth.workload_small()
+    g = oracle.frame(sc, cam, mode=oracle.MODE_GLOBAL)
+    d = [oracle.frame(sc, cam, mode=oracle.MODE_WINDOW, head=K).delta.mean() for K in (1, 4, 16)]
+    assert g.delta.mean() > d[0] > d[1] > d[2], (g.delta.mean(), d)
 
 
 def test_keys_sorted_and_ranges_consistent():
