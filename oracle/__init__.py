@@ -43,7 +43,8 @@ class OCam(C.Structure):
 
 class OCfg(C.Structure):
     _fields_ = [("mode", C.c_int32), ("batch", C.c_int32), ("tail", C.c_int32), ("pop", C.c_int32),
-                ("mid", C.c_int32), ("mid_batch", C.c_int32), ("head", C.c_int32), ("bg", C.c_float * 3)]
+                ("mid", C.c_int32), ("mid_batch", C.c_int32), ("head", C.c_int32), ("bg", C.c_float * 3),
+                ("flags", C.c_int32)]
 
 
 class OFrameOut(C.Structure):
@@ -97,9 +98,16 @@ def ocam(cam) -> OCam:
     return c
 
 
-def ocfg(mode=MODE_HIER, head=4, tail=64, mid=8, batch=32, pop=16, mid_batch=4, bg=(0.0, 0.0, 0.0)) -> OCfg:
+# Ablations of the hierarchical mode (see the C++ source): no tile-depth
+# adjustment, no tile-based culling, no culling at the 4x4 / 2x2 levels.
+ABL_TILE_DEPTH, ABL_TILE_CULL, ABL_HIER_CULL = 1, 2, 4
+
+
+def ocfg(mode=MODE_HIER, head=4, tail=64, mid=8, batch=32, pop=16, mid_batch=4, bg=(0.0, 0.0, 0.0),
+         flags=0) -> OCfg:
     f = OCfg()
     f.mode, f.batch, f.tail, f.pop, f.mid, f.mid_batch, f.head = mode, batch, tail, pop, mid, mid_batch, head
+    f.flags = flags
     for i in range(3):
         f.bg[i] = bg[i]
     return f

@@ -205,7 +205,17 @@ struct OCfg {
     int32_t mid_batch;  // mid sub-batch b (4)
     int32_t head;       // head capacity K (4)
     float bg[3];
+    int32_t flags;      // ablations of the hierarchical mode (ABL_*)
 };
+
+// Ablations of the hierarchical mode (Sec. 4.3, Table performance_ablation):
+//   ABL_TILE_DEPTH  (B) no tile-depth adjustment: every key of a Gaussian
+//                   uses its distance |mu - o| (t_opt along the ray through
+//                   its own mean) instead of t_opt through the tile's x^;
+//   ABL_TILE_CULL   (D) no tile-based culling: every rectangle tile is kept;
+//   ABL_HIER_CULL   (E) no culling at the 4x4 and 2x2 levels of the render.
+// Load balancing (C) changes no result and has no switch here.
+enum { ABL_TILE_DEPTH = 1, ABL_TILE_CULL = 2, ABL_HIER_CULL = 4 };
 
 enum { MODE_GLOBAL = 0, MODE_HIER = 1, MODE_FULL = 2, MODE_WINDOW = 3 };
 
@@ -482,12 +492,12 @@ void preprocess_one(const Cam<F>& cam, int mode, int deg, const float* mu_in, co
 // Number of rectangle tiles the Gaussian is kept for.  In hierarchical and
 // full modes every rectangle tile goes through Algorithm 1; the global mode
 // keeps every rectangle tile (3DGS).
-template <class F> int count_tiles(const Cam<F>& cam, int mode, const Rec<F>& g) {
+template <class F> int count_tiles(const Cam<F>& cam, int mode, int flags, const Rec<F>& g) {
     if (!g.vis) return 0;
     int n = 0;
     for (int ty = g.rect[1]; ty <= g.rect[3]; ++ty)
         for (int tx = g.rect[0]; tx <= g.rect[2]; ++tx) {
-            if (gs_lists(mode)) { ++n; continue; }
+            if (gs_lists(mode) || (flags & ABL_TILE_CULL)) { ++n; continue; }
             F a, b, c, d, hx, hy;
             hull(cam, tx * 16, ty * 16, 16, a, b, c, d);
             if (keep_block(g, a, b, c, d, hx, hy)) ++n;
@@ -509,7 +519,8 @@ struct Entry {
 
 // Duplication (Sec. 2.1 keys; Sec. 3.4 tile-depth adjustment): for every kept
 // tile the depth is t_opt along the ray through the tile's maximum point x^.
-template <class F> void emit_entries(const Cam<F>& cam, int mode, const Rec<F>& g, u32 id, std::vector<Entry>& out) {
+template <class F> void emit_entries(const Cam<F>& cam, int mode, int flags, const Rec<F>& g, u32 id,
+                                     std::vector<Entry>& out) {
     if (!g.vis) return;
     for (int ty = g.rect[1]; ty <= g.rect[3]; ++ty)
         for (int tx = g.rect[0]; tx <= g.rect[2]; ++tx) {
@@ -517,7 +528,9 @@ template <class F> void emit_entries(const Cam<F>& cam, int mode, const Rec<F>& 
             if (gs_lists(mode)) { out.push_back({tile, ord_key(g.z), id}); continue; }
             F a, b, c, d, hx, hy;
             hull(cam, tx * 16, ty * 16, 16, a, b, c, d);
-            if (!keep_block(g, a, b, c, d, hx, hy)) continue;
+            const bool keep = keep_block(g, a, b, c, d, hx, hy);
+            if (!keep && !(flags & ABL_TILE_CULL)) continue;
+            if (flags & ABL_TILE_DEPTH) { out.push_back({tile, ord_key(g.dist), id}); continue; }
             F dir[3];
             cam.ray(hx, hy, dir);
             out.push_back({tile, ord_key(topt(g, dir)), id});
@@ -678,7 +691,8 @@ template <class F> struct HierSubtile {
                 for (size_t j = r0; j < std::min(chunk.size(), r0 + (size_t)cfg.mid_batch); ++j) {
                     const Rec<F>& g = recs[chunk[j].id];
                     F hx, hy;
-                    if (!keep_block(g, qh[q][0], qh[q][1], qh[q][2], qh[q][3], hx, hy)) continue;
+                    if (!(cfg.flags & ABL_HIER_CULL) && !keep_block(g, qh[q][0], qh[q][1], qh[q][2], qh[q][3], hx, hy))
+                        continue;
                     nv.push_back({ord_key(topt(g, dQ[q])), chunk[j].rank, chunk[j].id});
                 }
                 std::sort(nv.begin(), nv.end());
@@ -697,7 +711,7 @@ template <class F> struct HierSubtile {
             for (u32 e = b0; e < std::min(end, b0 + (u32)cfg.batch); ++e) {
                 const Rec<F>& g = recs[ids[e]];
                 F hx, hy;
-                if (!keep_block(g, sx0, sx1, sy0, sy1, hx, hy)) continue;
+                if (!(cfg.flags & ABL_HIER_CULL) && !keep_block(g, sx0, sx1, sy0, sy1, hx, hy)) continue;
                 nv.push_back({ord_key(topt(g, dS)), e - begin, (int)ids[e]});
             }
             std::sort(nv.begin(), nv.end());
@@ -756,7 +770,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
 #pragma omp parallel for schedule(dynamic, 256)
     for (int i = 0; i < n; ++i) {
         preprocess_one<F>(cam, mode, deg, means + 3 * i, scales + 3 * i, rots + 4 * i, opac[i], sh + 3 * K * i, fr.recs[i]);
-        fr.touched[i] = (mode == MODE_FULL) ? 0 : count_tiles(cam, mode, fr.recs[i]);
+        fr.touched[i] = (mode == MODE_FULL) ? 0 : count_tiles(cam, mode, fr.cfg.flags, fr.recs[i]);
     }
     const int ntiles = cam.tiles_x * cam.tiles_y;
     fr.ms[0] = now_ms() - t0;
@@ -794,7 +808,7 @@ void run_frame(Frame<F>& fr, int n, int deg, const float* means, const float* sc
     t0 = now_ms();
     std::vector<std::vector<Entry>> per(n);
 #pragma omp parallel for schedule(dynamic, 256)
-    for (int i = 0; i < n; ++i) emit_entries(cam, mode, fr.recs[i], (u32)i, per[i]);
+    for (int i = 0; i < n; ++i) emit_entries(cam, mode, fr.cfg.flags, fr.recs[i], (u32)i, per[i]);
     fr.entries.clear();
     for (int i = 0; i < n; ++i) {
         fr.entries.insert(fr.entries.end(), per[i].begin(), per[i].end());

@@ -15,6 +15,8 @@ method, brute force, or an invariant that the paper's definitions imply:
 * the hierarchical order against the brute-force full per-pixel sort when
   the head queue can hold every contributor;
 * the full order under an exact 180-degree camera roll;
+* the ablations of Table performance_ablation: closed forms of their keys
+  and counts, and the brute-force full sort when the head holds everything;
 * the per-ray resorting window (Sec. 3.3) against the global order when the
   per-ray order is the list order, and against the brute-force full sort when
   the window never overflows;
@@ -371,6 +373,63 @@ def test_hier_sorts_better_than_global_and_queue_invariants():
     assert st["min_tail_after_pop"] >= 17
     # 16 sub-tiles per tile see every tile entry; culling only removes
     assert st["tail_in"] <= 16 * st["entries"]
+
+
+# ---------------------------------------------------------------------------
+# Ablations of the hierarchical mode (Sec. 4.3, Table performance_ablation)
+# ---------------------------------------------------------------------------
+def _ord32(x):
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return np.where(u >= 2 ** 31, (~u) & 0xffffffff, u | 2 ** 31)
+
+
+def _pairs(fr):
+    return set(zip((fr.keys >> np.uint64(32)).tolist(), fr.values.tolist()))
+
+
+def test_ablation_keys_and_counts_closed_forms():
+    sc, _ = synth.workload_small()
+    cam = synth.orbit_camera(128, 96, view=5)
+    a = oracle.frame(sc, cam, mode=oracle.MODE_HIER)
+    b = oracle.frame(sc, cam, mode=oracle.MODE_HIER, flags=oracle.ABL_TILE_DEPTH)
+    d = oracle.frame(sc, cam, mode=oracle.MODE_HIER, flags=oracle.ABL_TILE_CULL)
+    # (B) keeps the same (tile, Gaussian) entries; every depth key is the
+    # order-preserving bits of the Gaussian's distance |mu - o|.
+    assert _pairs(b) == _pairs(a)
+    np.testing.assert_array_equal(b.keys & np.uint64(0xffffffff), _ord32(b.zd[b.values, 1]))
+    # (D) keeps every tile of the rectangle: the count is its area, the
+    # entries include those of (A), with the same keys.
+    r = d.rect.astype(np.int64)
+    area = (r[:, 2] - r[:, 0] + 1) * (r[:, 3] - r[:, 1] + 1)
+    vis = d.touched > 0
+    np.testing.assert_array_equal(d.touched[vis], area[vis])
+    assert np.all(a.touched <= d.touched) and a.touched.sum() < d.touched.sum()
+    ka = dict(zip(zip((a.keys >> np.uint64(32)).tolist(), a.values.tolist()), a.keys.tolist()))
+    kd = dict(zip(zip((d.keys >> np.uint64(32)).tolist(), d.values.tolist()), d.keys.tolist()))
+    assert all(kd[p] == k for p, k in ka.items())
+
+
+@pytest.mark.parametrize("flags", [oracle.ABL_TILE_DEPTH, oracle.ABL_TILE_CULL, oracle.ABL_HIER_CULL, 7])
+def test_ablations_with_large_head_equal_full_sort(flags):
+    # Whatever the pre-sort keys and culling, a head able to hold every
+    # contributor of a pixel blends them in the full per-pixel order.
+    sc, cam = synth.workload_small()
+    full = oracle.frame(sc, cam, mode=oracle.MODE_FULL, max_k=64)
+    K = int(full.count.max()) + 8
+    h = oracle.frame(sc, cam, mode=oracle.MODE_HIER, head=K, max_k=64, flags=flags)
+    np.testing.assert_array_equal(h.blend_ids, full.blend_ids)
+    np.testing.assert_array_equal(h.count, full.count)
+    np.testing.assert_array_equal(h.rgb.view(np.uint32), full.rgb.view(np.uint32))
+
+
+def test_tile_depth_adjustment_lowers_sort_error():
+    # Sec. 3.4: keying tiles by t_opt through x^ lowers the per-ray sort
+    # error compared with one depth per Gaussian.
+    sc = synth.subsample(synth.mixture_scene(100_000, seed=1), 8000)
+    cam = synth.orbit_camera(160, 120, view=3)
+    a = oracle.frame(sc, cam, mode=oracle.MODE_HIER)
+    b = oracle.frame(sc, cam, mode=oracle.MODE_HIER, flags=oracle.ABL_TILE_DEPTH)
+    assert a.delta.mean() < b.delta.mean(), (a.delta.mean(), b.delta.mean())
 
 
 # ---------------------------------------------------------------------------
