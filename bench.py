@@ -71,7 +71,7 @@ def time_frames(r, ds, cams, cfg, steps, warmup, passes):
     out = gsr.Frame(H, W, "cuda")
     for i in range(warmup):
         r.render_async(ds, cams[i % len(cams)], cfg, out)
-    nev = 5 + 2 * passes
+    nev = 9 + 2 * passes
     frames = [make_events(nev) for _ in range(steps)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     r.status.zero_()
@@ -84,11 +84,13 @@ def time_frames(r, ds, cams, cfg, steps, warmup, passes):
     if int(r.status.item()) != 0:
         raise RuntimeError("tile entries overflowed the planned workspace during timing")
     total = start.elapsed_time(end)
-    stages, scatter = [], []
+    stages, scatter, kernels = [], [], []
     for evs, _ in frames:
         stages.append([evs[k].elapsed_time(evs[k + 1]) for k in range(4)])
         scatter.append([evs[5 + 2 * p].elapsed_time(evs[6 + 2 * p]) for p in range(passes)])
-    return total / steps, stages, scatter
+        k0 = 5 + 2 * passes    # per-tile ordering launch, then the first render launch
+        kernels.append([evs[k0].elapsed_time(evs[k0 + 1]), evs[k0 + 2].elapsed_time(evs[k0 + 3])])
+    return total / steps, stages, scatter, kernels
 
 
 def plan(r, ds, cams, cfg):
@@ -262,7 +264,7 @@ def main():
         passes = (gsr.lib().gsr_group_passes(W, H) if mode == gsr.MODE_HIER else gsr.lib().gsr_sort_passes(W, H))
         r = gsr.Renderer(entries_hint=40 * n)
         emax, consumed = plan(r, ds, cams, cfg)
-        ms, stages, scatter = time_frames(r, ds, cams, cfg, args.steps, args.warmup, passes)
+        ms, stages, scatter, kernels = time_frames(r, ds, cams, cfg, args.steps, args.warmup, passes)
         # entries of the timed views (every view was rendered once while planning)
         views = [(args.warmup + i) % len(cams) for i in range(args.steps)]
         E_views, cons_views, fb_views = [], [], []
@@ -273,28 +275,37 @@ def main():
             fb_views.append(r.counter(n, cams[v], 5) if mode == gsr.MODE_HIER else 0)
         results[label] = dict(ms=ms, stages=[mean([s[k] for s in stages]) for k in range(4)],
                               scatter=mean([mean(s) for s in scatter]) if passes else 0.0, E=mean(E_views),
-                              consumed=mean(cons_views), fallback=mean(fb_views), emax=emax, passes=passes)
-        log("%s: %.3f ms/frame, stages %s, scatter %.3f ms/launch x %d, E %.0f, consumed %.0f, fallback entries %.0f" %
+                              consumed=mean(cons_views), fallback=mean(fb_views), emax=emax, passes=passes,
+                              order_ms=mean([k[0] for k in kernels]), render_ms=mean([k[1] for k in kernels]))
+        log("%s: %.3f ms/frame, stages %s, scatter %.3f ms/launch x %d, ordering %.3f ms, render %.3f ms, E %.0f, "
+            "consumed %.0f, fallback entries %.0f" %
             (label, ms, ["%.3f" % x for x in results[label]["stages"]], results[label]["scatter"], passes,
-             results[label]["E"], results[label]["consumed"], results[label]["fallback"]))
+             results[label]["order_ms"], results[label]["render_ms"], results[label]["E"], results[label]["consumed"],
+             results[label]["fallback"]))
         del r
         torch.cuda.empty_cache()
 
     h = results["hier"]
-    # Dominant kernel and its algorithmic bytes per launch.
+    # Kernels of a hierarchical frame: (ms per frame, ms per launch, algorithmic HBM bytes per launch).
+    pre_bytes = n * (44 + 12 * ksh) + n * 168          # inputs; records incl. the packed splat
+    dup_bytes = n * 108 + 12.0 * h["E"]                # records of every Gaussian; one key + id per entry
     cands = {
-        "k_preprocess": (h["stages"][0], h["stages"][0], n * (44 + 12 * ksh) + n * 104),
+        "k_preprocess": (h["stages"][0], h["stages"][0], pre_bytes),
+        "k_duplicate": (h["stages"][1], h["stages"][1], dup_bytes),
         "k_radix_scatter": (h["scatter"] * h["passes"], h["scatter"], 24.0 * h["E"]),
-        "k_render_hier": (h["stages"][3], h["stages"][3], 76.0 * h["consumed"] + 24.0 * P),
+        "k_tile_prefix": (h["order_ms"], h["order_ms"], 16.0 * h["E"]),
+        "k_render_hier": (h["render_ms"], h["render_ms"], 76.0 * h["consumed"] + 24.0 * P),
     }
+    kernels = {k: {"ms_per_frame": round(v[0], 4), "GBs": round(v[2] / (v[1] * 1e-3) / 1e9, 1)}
+               for k, v in cands.items() if v[1] > 0}
     dom = max(cands, key=lambda k: cands[k][0])
     per_frame, dur, nbytes = cands[dom]
     achieved = nbytes / (dur * 1e-3) / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": int(nbytes), "avg_launch_ms": round(dur, 4)}
-    frame_bytes = (n * (44 + 12 * ksh) + n * 104) + 8.0 * n + 12.0 * h["E"] + 24.0 * h["E"] + 8.0 * h["E"] \
-        + 76.0 * h["consumed"] + 24.0 * P
+    frame_bytes = pre_bytes + dup_bytes + h["passes"] * 32.0 * h["E"] + 16.0 * h["E"] + 76.0 * h["consumed"] \
+        + 24.0 * P
     line = {
         "metric": METRIC, "value": round(h["ms"], 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(h["ms"], 4), "higher_is_better": False, "scaling": "weak",
@@ -306,6 +317,7 @@ def main():
         "entries": int(h["E"]), "entries_consumed": int(h["consumed"]), "fallback_entries": int(h["fallback"]),
         "frame_hbm_GBs": round(frame_bytes / (h["ms"] * 1e-3) / 1e9, 1),
         "roofline": roofline,
+        "kernels": kernels,
     }
     if "global" in results:
         g = results["global"]

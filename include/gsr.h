@@ -52,13 +52,31 @@ enum {
  *   GSR_MODE_HIER    the hierarchical resorting of Sec. 3.4 (opacity-aware
  *                    bounds, exact tile culling, tile-depth keys, tail / mid /
  *                    head queues on per-level t_opt);
+ *   GSR_MODE_FULL    the full per-pixel sort (Sec. 3.2), a quality
+ *                    reference: every contributor of a pixel (from the
+ *                    exactly culled tile lists of GSR_MODE_HIER) blended in
+ *                    (t_opt along the pixel ray, Gaussian id) order; many
+ *                    times slower than the other modes;
  *   GSR_MODE_WINDOW  per-ray resorting (Sec. 3.3): the 3DGS lists of
  *                    GSR_MODE_GLOBAL, each pixel keeping a window of `head`
  *                    samples ordered by t_opt along its ray and blending the
  *                    front whenever the window overflows. */
-enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1, GSR_MODE_WINDOW = 3 };
+enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1, GSR_MODE_FULL = 2, GSR_MODE_WINDOW = 3 };
 
 enum { GSR_STATUS_OVERFLOW = 1 };
+
+/* Ablations of GSR_MODE_HIER (Sec. 4.3, Table performance_ablation), bits of
+ * gsr_config.flags:
+ *   GSR_ABLATE_TILE_DEPTH  (B) no tile-depth adjustment: every key of a
+ *                          Gaussian uses its distance |mu - o| (t_opt along
+ *                          the ray through its own mean);
+ *   GSR_ABLATE_TILE_CULL   (D) no tile-based culling: every tile of the
+ *                          opacity-aware rectangle gets an entry;
+ *   GSR_ABLATE_HIER_CULL   (E) no culling at the 4x4 and 2x2 levels of the
+ *                          render (the per-pixel alpha test remains).
+ * (C), no load balancing, is lb_threshold >= GSR_NO_LOAD_BALANCE. */
+enum { GSR_ABLATE_TILE_DEPTH = 1, GSR_ABLATE_TILE_CULL = 2, GSR_ABLATE_HIER_CULL = 4 };
+#define GSR_NO_LOAD_BALANCE (1 << 30)
 
 /* Gaussians of one scene (Sec. 2.1): N rows per array, row-major, float32.
  *   means     [N,3]  centre mu
@@ -97,22 +115,28 @@ typedef struct gsr_camera {
  *   head      per-pixel head capacity K (HIER) or window size (WINDOW),
  *             one of 1, 2, 3, 4, 6, 8, 12, 16, 20, 24 (4)
  * lb_threshold only changes speed (tiles above which preprocessing and
- * duplication share a Gaussian across the wavefront; 32).
+ * duplication share a Gaussian across the wavefront; 32; Gaussians of at most
+ * min(lb_threshold, 32) tiles share their tiles with the other lanes, those
+ * between 32 and lb_threshold are walked by their own lane, and at
+ * GSR_NO_LOAD_BALANCE or above every Gaussian is walked by its own lane).
  * bg is the background colour. */
 typedef struct gsr_config {
     int32_t mode;
     int32_t batch, tail, pop, mid, mid_batch, head;
     int32_t lb_threshold;
     float bg[3];
-    uint32_t flags;      /* reserved, must be 0 */
-    int32_t sort_prefix; /* speed only: entries per tile sorted up front (power of two,
-                            16..4096; 0 = 2048); see gsr_render */
+    uint32_t flags;      /* GSR_ABLATE_* bits (GSR_MODE_HIER only), else 0 */
+    int32_t sort_prefix; /* speed only: entries per tile sorted up front (1..4096;
+                            0 = 1024); see gsr_render */
 } gsr_config;
 
 /* Byte offsets of the regions of a workspace, for inspection and debugging.
  * Records (App. B.4), one row per Gaussian:
  *   xy       float2 2D mean            conic_o  float4 (a, b, c, opacity)
  *   sw       float[12] Sigma^-1 (s00 s01 s02 s11 s12 s22), w = Sigma^-1 (mu - o), rgb
+ *   splat    float[16] the renderer's packed copy: x y a b | c opacity s00 s01 |
+ *            s02 s11 s12 s22 | w0 w1 w2 ln(eps_O / opacity) (one 64-byte line
+ *            per Gaussian; zero when culled)
  *   zd       float2 (view depth, |mu - o|)
  *   rect     int32[4] tile rectangle (x0, y0, x1, y1), inclusive
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
@@ -132,7 +156,7 @@ typedef struct gsr_config {
  * fallback), pre_len uint32[tiles] their number, tile_flag uint32[tiles] the
  * entry count of a tile that took the fallback (else 0). */
 typedef struct gsr_layout {
-    int64_t xy, conic_o, sw, zd, rect, touched, kmask, offsets, grad2d;
+    int64_t xy, conic_o, sw, splat, zd, rect, touched, kmask, offsets, grad2d;
     int64_t keys, values, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag;
     int64_t entry_capacity;
@@ -165,7 +189,8 @@ int gsr_check_config(const gsr_config* cfg /* host */);
  * order is that of a full sort by (tile, depth, id) in every case.  The
  * blend order is that of the mode (see GSR_MODE_*).
  *   rgb     [3,H,W] float32 out   colour + T_final * bg
- *   depth   [H,W]   float32 out   sum of t_opt alpha T (GLOBAL: |mu - o|; WINDOW: t_opt)
+ *   depth   [H,W]   float32 out   sum of t_opt alpha T (t_opt along the pixel ray in FULL and
+ *                                 WINDOW; GLOBAL: |mu - o|)
  *   count   [H,W]   int32   out   number of Gaussians blended
  *   T_final [H,W]   float32 out   final transmittance
  *   status_dev      int32   in/out, see above
@@ -206,7 +231,10 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
  * their second render).  With n_events >= 5 + 2 * passes (passes =
  * gsr_group_passes(W, H) in GSR_MODE_HIER, gsr_sort_passes(W, H) in
  * GSR_MODE_GLOBAL), events[5 + 2p] and [6 + 2p] also bracket the scatter
- * launch of radix pass p.  The caller owns the events. */
+ * launch of radix pass p; with n_events >= 9 + 2 * passes, events[5 + 2 passes]
+ * and [6 + 2 passes] bracket the per-tile ordering launch (the tile prefixes in
+ * GSR_MODE_HIER, the tile ranges otherwise) and [7 + 2 passes] and
+ * [8 + 2 passes] the first render launch.  The caller owns the events. */
 int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                       int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);

@@ -63,6 +63,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->xy = take(8 * n);
     L->conic_o = take(16 * n);
     L->sw = take(48 * n);
+    L->splat = take(64 * n);
     L->zd = take(8 * n);
     L->rect = take(16 * n);
     L->touched = take(4 * n);
@@ -152,6 +153,7 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.xy = (float2*)(base + L.xy);
     b.co = (float4*)(base + L.conic_o);
     b.sw = (float4*)(base + L.sw);
+    b.pk = (float4*)(base + L.splat);
     b.zd = (float2*)(base + L.zd);
     b.rect = (int4*)(base + L.rect);
     b.touched = (uint32_t*)(base + L.touched);
@@ -173,15 +175,18 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     return b;
 }
 
-int prefix_len(const gsr_config* cfg) { return cfg->sort_prefix == 0 ? 2048 : cfg->sort_prefix; }
+int prefix_len(const gsr_config* cfg) { return cfg->sort_prefix == 0 ? 1024 : cfg->sort_prefix; }
 
 // Sort stage of a frame (or a batch).  HIER: group by tile, tile ranges and
 // each tile's sorted prefix.  GLOBAL: full sort and ranges.
 hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, hipStream_t s,
-                      void* const* scatter_events) {
+                      void* const* scatter_events, void* const* order_events = nullptr) {
     const SortPlan sp = sort_plan(tiles, mode);
     hipError_t e;
     int res = 0;
+    auto mark = [&](int k) -> hipError_t {
+        return order_events ? hipEventRecord((hipEvent_t)order_events[k], s) : hipSuccess;
+    };
     if (mode == GSR_MODE_HIER) {
         if ((e = gsr::launch_fill_u32(b.tile_flag, (size_t)tiles, 0u, s)) != hipSuccess) return e;
         if (sp.tile_passes > 0) {
@@ -189,11 +194,16 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
                                             sp.dup_buf, &res, s, scatter_events, 32)) != hipSuccess)
                 return e;
         }
-        if ((e = gsr::launch_ranges(b.keys[0], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess) return e;
-        return gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.ranges, (uint32_t)tiles, b.pre_vals, b.pre_len, M, s);
+        if ((e = mark(0)) != hipSuccess) return e;
+        if ((e = gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.counters, (uint32_t)tiles, b.ranges, b.pre_vals,
+                                         b.pre_len, M, s)) != hipSuccess)
+            return e;
+        return mark(1);
     }
     if ((e = gsr::launch_sort(b, sp.key_bits, &res, s, scatter_events)) != hipSuccess) return e;
-    return gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s);
+    if ((e = mark(0)) != hipSuccess) return e;
+    if ((e = gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess) return e;
+    return mark(1);
 }
 
 // Fallback of the HIER sort: the whole sorted list of every tile the prefix
@@ -221,7 +231,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if ((rc = gsr_check_config(cfg))) return rc;
     if (!ws || !rgb || !depth || !count || !T_final || !status_dev) return fail(GSR_EINVAL, "output or workspace is NULL");
     if (blend_ids && max_k <= 0) return fail(GSR_EINVAL, "max_k must be > 0");
-    if (cfg->mode != GSR_MODE_GLOBAL && !gsr::hier_head_supported(cfg->head))
+    if ((cfg->mode == GSR_MODE_HIER || cfg->mode == GSR_MODE_WINDOW) && !gsr::hier_head_supported(cfg->head))
         return fail(GSR_EUNSUPPORTED, "head size not built (1,2,3,4,6,8,12,16,20,24)");
     gsr_layout L;
     int64_t spo, hist, k1, v1;
@@ -234,8 +244,11 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
     const int tiles = dc.tiles_x * dc.tiles_y;
-    // GSR_MODE_WINDOW walks the lists of the global order.
-    const int mode = cfg->mode == GSR_MODE_WINDOW ? GSR_MODE_GLOBAL : cfg->mode;
+    // GSR_MODE_WINDOW walks the lists of the global order, GSR_MODE_FULL the
+    // exactly culled lists of the hierarchical one.
+    const int mode = cfg->mode == GSR_MODE_WINDOW ? GSR_MODE_GLOBAL
+                     : cfg->mode == GSR_MODE_FULL ? GSR_MODE_HIER
+                                                  : cfg->mode;
     const SortPlan sp = sort_plan(tiles, mode);
     const uint32_t M = (uint32_t)prefix_len(cfg);
     gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
@@ -246,17 +259,23 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     };
     if ((e = mark(0)) != hipSuccess) return fail_hip(e, "event");
     if ((e = gsr::launch_fill_u32(b.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
-    if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, b, s)) != hipSuccess) return fail_hip(e, "preprocess");
+    if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, cfg->flags, b, s)) != hipSuccess) return fail_hip(e, "preprocess");
     if ((e = mark(1)) != hipSuccess) return fail_hip(e, "event");
     if ((e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
                               s, b.counters + 3)) != hipSuccess)
         return fail_hip(e, "scan");
-    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, b, sp.dup_buf, status_dev, s)) != hipSuccess)
+    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, cfg->flags, b, sp.dup_buf, status_dev, s)) != hipSuccess)
         return fail_hip(e, "duplicate");
     if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
     const int n_sort_ev = mode == GSR_MODE_HIER ? sp.tile_passes : sp.full_passes;
     void* const* scatter_ev = (events && n_events >= 5 + 2 * n_sort_ev) ? events + 5 : nullptr;
-    if ((e = sort_stage(b, tiles, mode, M, s, scatter_ev)) != hipSuccess) return fail_hip(e, "sort");
+    // Optional brackets of single launches: the per-tile ordering and the
+    // first render pass.
+    void* const* kernel_ev = (events && n_events >= 9 + 2 * n_sort_ev) ? events + 5 + 2 * n_sort_ev : nullptr;
+    auto kmark = [&](int k) -> hipError_t {
+        return kernel_ev ? hipEventRecord((hipEvent_t)kernel_ev[k], s) : hipSuccess;
+    };
+    if ((e = sort_stage(b, tiles, mode, M, s, scatter_ev, kernel_ev)) != hipSuccess) return fail_hip(e, "sort");
     if ((e = mark(3)) != hipSuccess) return fail_hip(e, "event");
     gsr::RenderArgs ra;
     std::memset(&ra, 0, sizeof(ra));
@@ -265,6 +284,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.xy = b.xy;
     ra.co = b.co;
     ra.sw = b.sw;
+    ra.pk = b.pk;
     ra.zd = b.zd;
     ra.vals = b.vals[0];
     ra.ranges = b.ranges;
@@ -278,18 +298,30 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.bg0 = cfg->bg[0];
     ra.bg1 = cfg->bg[1];
     ra.bg2 = cfg->bg[2];
-    if (mode == GSR_MODE_HIER) {
+    ra.flags = (int)cfg->flags;
+    if (cfg->mode == GSR_MODE_FULL) {
+        ra.list_mode = gsr::kListFull;  // the grouped lists, in any order
+        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
+        if ((e = gsr::launch_render_full(ra, s)) != hipSuccess) return fail_hip(e, "render");
+        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
+    } else if (mode == GSR_MODE_HIER) {
         set_prefix_lists(ra, b, gsr::kListPrefix);
+        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
+        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
         if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
         ra.list_mode = gsr::kListFlagged;
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
     } else if (cfg->mode == GSR_MODE_WINDOW) {
         ra.list_mode = gsr::kListFull;
+        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
         if ((e = gsr::launch_render_window(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
+        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
     } else {
         ra.list_mode = gsr::kListFull;
+        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
         if ((e = gsr::launch_render_global(ra, s)) != hipSuccess) return fail_hip(e, "render");
+        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
     }
     if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
     return GSR_OK;
@@ -328,6 +360,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     ra.xy = b.xy;
     ra.co = b.co;
     ra.sw = b.sw;
+    ra.pk = b.pk;
     ra.zd = b.zd;
     ra.vals = b.vals[0];
     ra.ranges = b.ranges;
@@ -339,6 +372,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     ra.rgb_in = rgb;
     ra.T_in = T_final;
     ra.grad2d = g2;
+    ra.flags = (int)cfg->flags;
     set_prefix_lists(ra, b, gsr::kListSorted);
     if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render backward");
     if ((e = gsr::launch_preprocess_backward(sc, dc, b.co, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
@@ -350,7 +384,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
 // Batched rendering: many views of several scenes in one launch sequence.
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-    int64_t views, xy, co, sw, zd, rect, touched, kmask, offsets, ranges, counters;
+    int64_t views, xy, co, sw, pk, zd, rect, touched, kmask, offsets, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag, flist;
     int64_t keys[2], vals[2], hist, partial;
     int64_t tkeys[2], tvals[2], thist, tpartial;
@@ -368,6 +402,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->xy = take(8 * R);
     L->co = take(16 * R);
     L->sw = take(48 * R);
+    L->pk = take(64 * R);
     L->zd = take(8 * R);
     L->rect = take(16 * R);
     L->touched = take(4 * R);
@@ -457,6 +492,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.xy = (float2*)(base + L.xy);
     fb.co = (float4*)(base + L.co);
     fb.sw = (float4*)(base + L.sw);
+    fb.pk = (float4*)(base + L.pk);
     fb.zd = (float2*)(base + L.zd);
     fb.rect = (int4*)(base + L.rect);
     fb.touched = (uint32_t*)(base + L.touched);
@@ -486,6 +522,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
         v.xy += r0;
         v.co += r0;
         v.sw += 3 * r0;
+        v.pk += 4 * r0;
         v.zd += r0;
         v.rect += r0;
         v.touched += r0;
@@ -496,7 +533,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     for (size_t v = 0; v < b->views.size(); ++v) {
         const gsr_scene& sc = b->scenes[b->views[v].scene];
         const gsr::SceneArgs sa{sc.n, sc.sh_degree, sc.means, sc.scales, sc.rots, sc.opacities, sc.sh};
-        if ((e = gsr::launch_preprocess(sa, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, shifted(b->rec_base[v]), s)) !=
+        if ((e = gsr::launch_preprocess(sa, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags, shifted(b->rec_base[v]), s)) !=
             hipSuccess)
             return fail_hip(e, "preprocess");
     }
@@ -505,7 +542,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
         return fail_hip(e, "scan");
     for (size_t v = 0; v < b->views.size(); ++v) {
         const gsr_scene& sc = b->scenes[b->views[v].scene];
-        if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, shifted(b->rec_base[v]),
+        if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags, shifted(b->rec_base[v]),
                                        sp.dup_buf, status_dev, s, (uint32_t)b->tile_base[v],
                                        (uint32_t)b->rec_base[v])) != hipSuccess)
             return fail_hip(e, "duplicate");
@@ -532,6 +569,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.xy = fb.xy;
     ba.co = fb.co;
     ba.sw = fb.sw;
+    ba.pk = fb.pk;
     ba.zd = fb.zd;
     ba.vals = fb.vals[0];
     ba.ranges = fb.ranges;
@@ -540,6 +578,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.pre_vals = fb.pre_vals;
     ba.pre_len = fb.pre_len;
     ba.tile_flag = fb.tile_flag;
+    ba.flags = (int)b->cfg.flags;
     ba.queue = fb.counters + 1;
     ba.n_items = (uint32_t)(4 * b->tiles);
     ba.n_tiles_dev = nullptr;
@@ -766,9 +805,12 @@ void gsr_default_config(gsr_config* c) {
 
 int gsr_check_config(const gsr_config* c) {
     if (!c) return fail(GSR_EINVAL, "config is NULL");
-    if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER && c->mode != GSR_MODE_WINDOW)
+    if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER && c->mode != GSR_MODE_FULL &&
+        c->mode != GSR_MODE_WINDOW)
         return fail(GSR_EINVAL, "unknown mode");
-    if (c->flags != 0) return fail(GSR_EINVAL, "flags must be 0");
+    if ((c->flags & ~(uint32_t)(GSR_ABLATE_TILE_DEPTH | GSR_ABLATE_TILE_CULL | GSR_ABLATE_HIER_CULL)) != 0)
+        return fail(GSR_EINVAL, "unknown flag");
+    if (c->flags != 0 && c->mode != GSR_MODE_HIER) return fail(GSR_EINVAL, "ablation flags apply to GSR_MODE_HIER");
     if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
     if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..4096");
     if (c->mode == GSR_MODE_HIER) {

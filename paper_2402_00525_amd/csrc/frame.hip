@@ -103,6 +103,7 @@ struct PreOut {
     float2* xy;
     float4* co;
     float4* sw;
+    float4* pk;
     float2* zd;
     int4* rect;
 };
@@ -253,6 +254,7 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
     }
     if (ok) {
         g.x = mx; g.y = my; g.ca = ca; g.cb = cb; g.cc = cc; g.op = op;
+        g.lt = -ln_atanh(op / kEpsO);
         g.s00 = Si[0][0]; g.s01 = Si[0][1]; g.s02 = Si[0][2]; g.s11 = Si[1][1]; g.s12 = Si[1][2]; g.s22 = Si[2][2];
         g.w0 = w[0]; g.w1 = w[1]; g.w2 = w[2];
         rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
@@ -261,6 +263,10 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
         out.sw[3 * i] = make_float4(Si[0][0], Si[0][1], Si[0][2], Si[1][1]);
         out.sw[3 * i + 1] = make_float4(Si[1][2], Si[2][2], w[0], w[1]);
         out.sw[3 * i + 2] = make_float4(w[2], rgb[0], rgb[1], rgb[2]);
+        out.pk[4 * i] = make_float4(mx, my, ca, cb);
+        out.pk[4 * i + 1] = make_float4(cc, op, Si[0][0], Si[0][1]);
+        out.pk[4 * i + 2] = make_float4(Si[0][2], Si[1][1], Si[1][2], Si[2][2]);
+        out.pk[4 * i + 3] = make_float4(w[0], w[1], w[2], g.lt);
         out.zd[i] = make_float2(pz, dist);
         out.rect[i] = rc;
     } else {
@@ -270,6 +276,10 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
         out.sw[3 * i] = z4;
         out.sw[3 * i + 1] = z4;
         out.sw[3 * i + 2] = z4;
+        out.pk[4 * i] = z4;
+        out.pk[4 * i + 1] = z4;
+        out.pk[4 * i + 2] = z4;
+        out.pk[4 * i + 3] = z4;
         out.zd[i] = make_float2(0.0f, 0.0f);
         out.rect[i] = make_int4(0, 0, 0, 0);
     }
@@ -293,16 +303,23 @@ __device__ __forceinline__ bool tile_kept(const Splat& g, const DevCam& cam, int
 struct PreArgs {
     SceneArgs sc;
     DevCam cam;
-    int mode, lb;
+    int mode, lb, flags;
     PreOut out;
     uint32_t* touched;
     uint32_t* kmask;
 };
 
-// Gaussians whose rectangle has at most this many tiles are handled by one
-// lane in preprocessing and keep a bit mask of their kept tiles; larger ones
-// are shared across the wavefront (load balancing, Sec. 3.4).
+// Work classes of a visible Gaussian in preprocessing and duplication
+// (load balancing, Sec. 3.4), by the number of tiles of its rectangle:
+//   masked    <= min(lb, 32): its (Gaussian, tile) pairs are spread over the
+//             wavefront as one flat list; preprocessing records its kept
+//             tiles as a bit mask;
+//   deferred  > lb: the whole wavefront works on it, one Gaussian at a time;
+//   serial    the rest (32 < tiles <= lb), and every Gaussian when lb is
+//             kNoLoadBalance: its own lane walks its rectangle.
 __device__ __forceinline__ int lane_tile_limit(int lb) { return lb < 32 ? lb : 32; }
+__device__ __forceinline__ bool class_masked(int area, int lb) { return lb < kNoLoadBalance && area <= lane_tile_limit(lb); }
+__device__ __forceinline__ bool class_deferred(int area, int lb) { return lb < kNoLoadBalance && area > lb; }
 
 // SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
 // stride so that lanes reading their own rows hit distinct banks.
@@ -310,7 +327,7 @@ constexpr int kShStride = 49;
 
 // Per-wavefront staging for the flat kept-tile test (reuses the SH memory).
 struct CountStage {
-    float x[64], y[64], ca[64], cb[64], cc[64], op[64];
+    float x[64], y[64], ca[64], cb[64], cc[64], op[64], lt[64];
     int rx0[64], ry0[64], rw[64];
     uint32_t pfx[64], mask[64];
 };
@@ -341,16 +358,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = vis ? wdt * hgt : 0;
     uint32_t cnt = 0, mask = 0;
-    const bool deferred = vis && a.mode == kModeHier && area > lane_tile_limit(a.lb);
+    const bool no_cull = (a.flags & kAblateTileCull) != 0;
+    const bool masked = vis && class_masked(area, a.lb);
+    const bool deferred = vis && a.mode == kModeHier && class_deferred(area, a.lb);
+    const bool serial = vis && a.mode == kModeHier && !masked && !deferred;
     if (a.mode == kModeGlobal) {
         cnt = (uint32_t)area;
     } else {
-        // Kept-tile test of all (Gaussian, rectangle tile) pairs of the lane-
-        // handled Gaussians of this wavefront as one flat list, one pair per
-        // lane per step; kept tiles set bits of their Gaussian's mask in LDS.
+        // Kept-tile test of all (Gaussian, rectangle tile) pairs of the masked
+        // Gaussians of this wavefront as one flat list, one pair per lane per
+        // step; kept tiles set bits of their Gaussian's mask in LDS.
         __syncthreads();  // the SH rows are no longer needed: reuse the memory
         CountStage& st = reinterpret_cast<CountStage*>(s_sh)[threadIdx.x >> 6];
-        const uint32_t my = (vis && !deferred) ? (uint32_t)area : 0u;
+        const uint32_t my = masked ? (uint32_t)area : 0u;
         uint32_t incl = my;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -359,7 +379,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         }
         const uint32_t total = (uint32_t)__shfl((int)incl, 63);
         st.x[lane] = g.x; st.y[lane] = g.y; st.ca[lane] = g.ca; st.cb[lane] = g.cb; st.cc[lane] = g.cc;
-        st.op[lane] = g.op;
+        st.op[lane] = g.op; st.lt[lane] = g.lt;
         st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
         st.pfx[lane] = incl - my;
         st.mask[lane] = 0u;
@@ -377,12 +397,20 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             const int rw = st.rw[lo];
             Splat h;
             h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
+            h.lt = st.lt[lo];
             float2 xh;
-            if (tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw, xh)) atomicOr(&st.mask[lo], 1u << k);
+            if (no_cull || tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw, xh))
+                atomicOr(&st.mask[lo], 1u << k);
         }
         wave_lds_sync();
         mask = st.mask[lane];
         cnt = (uint32_t)__popc(mask);
+        if (serial) {
+            for (int k = 0; k < area; ++k) {
+                float2 xh;
+                if (no_cull || tile_kept(g, a.cam, rc.x + k % wdt, rc.y + k / wdt, xh)) ++cnt;
+            }
+        }
     }
     uint64_t pend = __ballot(deferred);
     while (pend) {
@@ -391,13 +419,13 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         Splat h;
         h.x = __shfl(g.x, src_lane); h.y = __shfl(g.y, src_lane);
         h.ca = __shfl(g.ca, src_lane); h.cb = __shfl(g.cb, src_lane); h.cc = __shfl(g.cc, src_lane);
-        h.op = __shfl(g.op, src_lane);
+        h.op = __shfl(g.op, src_lane); h.lt = __shfl(g.lt, src_lane);
         const int rx0 = __shfl(rc.x, src_lane), ry0 = __shfl(rc.y, src_lane);
         const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
         uint32_t c = 0;
         for (int k = lane; k < rarea; k += 64) {
             float2 xh;
-            c += tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw, xh) ? 1u : 0u;
+            c += (no_cull || tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw, xh)) ? 1u : 0u;
         }
         c = wave_reduce_add(c);
         if (lane == src_lane) cnt = c;
@@ -410,10 +438,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 
 struct DupArgs {
     DevCam cam;
-    int n, mode, lb;
+    int n, mode, lb, flags;
     const float2* xy;
     const float4* co;
     const float4* sw;
+    const float4* pk;
     const float2* zd;
     const int4* rect;
     const uint32_t* touched;
@@ -433,6 +462,31 @@ __device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32
     } else {
         atomicOr(a.status, 1);
     }
+}
+
+// Key depth of a kept tile: the view depth z (global order), the Gaussian's
+// distance (ablation without tile-depth adjustment), or t_opt along the ray
+// through the tile's maximum point x^ (Sec. 3.4).
+__device__ __forceinline__ uint32_t key_depth(const DupArgs& a, const Splat& h, float z, int tx, int ty) {
+    if (a.mode == kModeGlobal || (a.flags & kAblateTileDepth)) return depth_bits(z);
+    float x0, x1, y0, y1;
+    tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+    const float2 xh = box_max_point(h, x0, x1, y0, y1);
+    return depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
+}
+
+// Keep test and key depth of one rectangle tile (every tile is kept in the
+// global order and in the ablation without tile-based culling).
+__device__ __forceinline__ bool keep_and_depth(const DupArgs& a, const Splat& h, float z, int tx, int ty,
+                                               uint32_t& dbits) {
+    if (a.mode == kModeGlobal || (a.flags & kAblateTileCull)) {
+        dbits = key_depth(a, h, z, tx, ty);
+        return true;
+    }
+    float2 xh;
+    if (!tile_kept(h, a.cam, tx, ty, xh)) return false;
+    dbits = (a.flags & kAblateTileDepth) ? depth_bits(z) : depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
+    return true;
 }
 
 // Per-wavefront staging of the 64 Gaussians whose kept tiles are enumerated.
@@ -462,17 +516,19 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     Splat g;
     int4 rc = make_int4(0, 0, -1, -1);
     uint32_t off = 0;
-    float zdepth = 0.0f;
+    float zdepth = 0.0f;  // the depth used by keys without tile-depth adjustment
     if (cnt > 0) {
-        g = load_splat(a.xy, a.co, a.sw, (uint32_t)i);
+        g = load_packed(a.pk, (uint32_t)i);
         rc = a.rect[i];
         off = a.offsets[i];
-        zdepth = a.zd[i].x;
+        const float2 zd = a.zd[i];
+        zdepth = a.mode == kModeGlobal ? zd.x : zd.y;
     }
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = cnt > 0 ? wdt * hgt : 0;
-    const bool small = cnt > 0 && area <= lane_tile_limit(a.lb);
-    const bool deferred = cnt > 0 && !small;
+    const bool small = cnt > 0 && class_masked(area, a.lb);
+    const bool deferred = cnt > 0 && class_deferred(area, a.lb);
+    const bool serial = cnt > 0 && !small && !deferred;
     uint32_t mask = 0;
     if (small) mask = a.mode == kModeHier ? a.kmask[i] : (area >= 32 ? 0xffffffffu : ((1u << area) - 1u));
     const uint32_t my = small ? cnt : 0u;
@@ -507,20 +563,25 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         const int k = __builtin_ctz(m);
         const int rw = st.rw[lo];
         const int tx = st.rx0[lo] + k % rw, ty = st.ry0[lo] + k / rw;
-        uint32_t dbits;
-        if (a.mode == kModeGlobal) {
-            dbits = depth_bits(st.z[lo]);
-        } else {
-            Splat h;
-            h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
-            h.s00 = st.s00[lo]; h.s01 = st.s01[lo]; h.s02 = st.s02[lo]; h.s11 = st.s11[lo]; h.s12 = st.s12[lo];
-            h.s22 = st.s22[lo]; h.w0 = st.w0[lo]; h.w1 = st.w1[lo]; h.w2 = st.w2[lo];
-            float x0, x1, y0, y1;
-            tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
-            const float2 xh = box_max_point(h, x0, x1, y0, y1);
-            dbits = depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
-        }
+        Splat h;
+        h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
+        h.s00 = st.s00[lo]; h.s01 = st.s01[lo]; h.s02 = st.s02[lo]; h.s11 = st.s11[lo]; h.s12 = st.s12[lo];
+        h.s22 = st.s22[lo]; h.w0 = st.w0[lo]; h.w1 = st.w1[lo]; h.w2 = st.w2[lo];
+        h.lt = __int_as_float(0x7fc00000);  // no culling here: the mask decided
+        const uint32_t dbits = key_depth(a, h, st.z[lo], tx, ty);
         put_entry(a, st.off[lo] + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits, id_wave + (uint32_t)lo);
+    }
+    if (serial) {
+        // No load balancing for this Gaussian: its lane walks its rectangle.
+        uint32_t r = 0;
+        for (int k = 0; k < area; ++k) {
+            const int tx = rc.x + k % wdt, ty = rc.y + k / wdt;
+            uint32_t dbits;
+            if (keep_and_depth(a, g, zdepth, tx, ty, dbits)) {
+                put_entry(a, off + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits, (uint32_t)i);
+                ++r;
+            }
+        }
     }
     uint64_t pend = __ballot(deferred);
     while (pend) {
@@ -532,6 +593,7 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         h.s00 = __shfl(g.s00, src); h.s01 = __shfl(g.s01, src); h.s02 = __shfl(g.s02, src);
         h.s11 = __shfl(g.s11, src); h.s12 = __shfl(g.s12, src); h.s22 = __shfl(g.s22, src);
         h.w0 = __shfl(g.w0, src); h.w1 = __shfl(g.w1, src); h.w2 = __shfl(g.w2, src);
+        h.lt = __shfl(g.lt, src);
         const float hz = __shfl(zdepth, src);
         const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
         const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
@@ -545,14 +607,7 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
             if (k < rarea) {
                 tx = rx0 + k % rw;
                 ty = ry0 + k / rw;
-                if (a.mode == kModeGlobal) {
-                    keep = true;
-                    dbits = depth_bits(hz);
-                } else {
-                    float2 xh;
-                    keep = tile_kept(h, a.cam, tx, ty, xh);
-                    if (keep) dbits = depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
-                }
+                keep = keep_and_depth(a, h, hz, tx, ty, dbits);
             }
             const uint64_t m = __ballot(keep);
             if (keep) put_entry(a, base + (uint32_t)__popcll(m & lanemask_lt()), (uint32_t)(ty * a.cam.tiles_x + tx),
@@ -863,7 +918,7 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
+hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b,
                              hipStream_t s) {
     if (sc.n == 0) return hipSuccess;
     PreArgs a;
@@ -871,7 +926,8 @@ hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, i
     a.cam = cam;
     a.mode = mode;
     a.lb = lb;
-    a.out = PreOut{b.xy, b.co, b.sw, b.zd, b.rect};
+    a.flags = flags;
+    a.out = PreOut{b.xy, b.co, b.sw, b.pk, b.zd, b.rect};
     a.touched = b.touched;
     a.kmask = b.kmask;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
@@ -892,17 +948,19 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* pa
     return hipGetLastError();
 }
 
-hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
-                            hipStream_t s, uint32_t tile_base, uint32_t id_base) {
+hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf,
+                            int32_t* status, hipStream_t s, uint32_t tile_base, uint32_t id_base) {
     if (n == 0) return hipSuccess;
     DupArgs a;
     a.cam = cam;
     a.n = n;
     a.mode = mode;
     a.lb = lb;
+    a.flags = flags;
     a.xy = b.xy;
     a.co = b.co;
     a.sw = b.sw;
+    a.pk = b.pk;
     a.zd = b.zd;
     a.rect = b.rect;
     a.touched = b.touched;

@@ -89,10 +89,12 @@ __device__ __forceinline__ float3 cam_ray(const DevCam& c, float u, float v) {
 }
 
 // The per-Gaussian data the render levels use: 2D mean, conic, opacity,
-// Sigma^-1 (6 unique entries) and w = Sigma^-1 (mu - o).
+// Sigma^-1 (6 unique entries), w = Sigma^-1 (mu - o), and lt = ln(eps_O /
+// opacity) (NaN when not at hand), which lets culling skip exp (clears_eps).
 struct Splat {
     float x, y, ca, cb, cc, op;
     float s00, s01, s02, s11, s12, s22, w0, w1, w2;
+    float lt;
 };
 
 __device__ __forceinline__ Splat load_splat(const float2* __restrict__ xy, const float4* __restrict__ co,
@@ -108,6 +110,21 @@ __device__ __forceinline__ Splat load_splat(const float2* __restrict__ xy, const
     g.s00 = a.x; g.s01 = a.y; g.s02 = a.z; g.s11 = a.w;
     g.s12 = b.x; g.s22 = b.y; g.w0 = b.z; g.w1 = b.w;
     g.w2 = e.x;
+    g.lt = __int_as_float(0x7fc00000);
+    return g;
+}
+
+// The same splat from its packed 64-byte record (one cache line):
+// (x, y, a, b), (c, opacity, s00, s01), (s02, s11, s12, s22), (w0, w1, w2, lt).
+__device__ __forceinline__ Splat load_packed(const float4* __restrict__ pk, uint32_t id) {
+    const float4 p0 = pk[4 * (size_t)id], p1 = pk[4 * (size_t)id + 1];
+    const float4 p2 = pk[4 * (size_t)id + 2], p3 = pk[4 * (size_t)id + 3];
+    Splat g;
+    g.x = p0.x; g.y = p0.y; g.ca = p0.z; g.cb = p0.w;
+    g.cc = p1.x; g.op = p1.y; g.s00 = p1.z; g.s01 = p1.w;
+    g.s02 = p2.x; g.s11 = p2.y; g.s12 = p2.z; g.s22 = p2.w;
+    g.w0 = p3.x; g.w1 = p3.y; g.w2 = p3.z;
+    g.lt = p3.w;
     return g;
 }
 
@@ -147,17 +164,31 @@ __device__ __forceinline__ float2 box_max_point(const Splat& g, float x0, float 
     return make_float2(px + tx * lx, py + ty * ly);
 }
 
+// opacity * exp(p) >= eps_O, decided as that comparison.  When the exponent
+// is more than kCullMargin away from lt = ln(eps_O / opacity) the answer is
+// settled without exp: exp, the logarithm and the products are accurate to
+// about 1e-6, far inside the margin, so the result is the exact comparison's.
+constexpr float kCullMargin = 1e-3f;
+
+__device__ __forceinline__ bool clears_eps(const Splat& g, float p) {
+    if (!(p <= 0.0f)) return false;
+    if (p < g.lt - kCullMargin) return false;
+    if (p > g.lt + kCullMargin) return true;
+    return g.op * exp_cw(p) >= kEpsO;
+}
+
 // Exact culling: keep iff the maximum over the block clears eps_O.
 __device__ __forceinline__ bool keeps_block(const Splat& g, float x0, float x1, float y0, float y1, float2& xh) {
     xh = box_max_point(g, x0, x1, y0, y1);
-    const float p = splat_power(g, xh.x, xh.y);
-    return p <= 0.0f && g.op * exp_cw(p) >= kEpsO;
+    return clears_eps(g, splat_power(g, xh.x, xh.y));
 }
 
-// alpha at a pixel centre; false when the Gaussian is skipped there.
+// alpha at a pixel centre; false when the Gaussian is skipped there (alpha is
+// then not set).
 __device__ __forceinline__ bool pixel_alpha(const Splat& g, float px, float py, float& alpha) {
     const float p = splat_power(g, px, py);
     if (p > 0.0f) return false;
+    if (p < g.lt - kCullMargin) return false;
     const float a = g.op * exp_cw(p);
     alpha = a < kAlphaMax ? a : kAlphaMax;
     return !(alpha < kEpsO);

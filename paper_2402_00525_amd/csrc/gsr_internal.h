@@ -9,12 +9,18 @@
 namespace gsr {
 
 enum { kModeGlobal = 0, kModeHier = 1 };
+// Ablations of the hierarchical mode (bits of gsr_config.flags).
+enum { kAblateTileDepth = 1, kAblateTileCull = 2, kAblateHierCull = 4 };
+// lb_threshold at or above this: no load balancing (every lane walks its own
+// Gaussian's rectangle).
+constexpr int kNoLoadBalance = 1 << 30;
 
 // Device regions of one frame inside the caller's workspace.
 struct FrameBufs {
     float2* xy;
     float4* co;       // conic (a, b, c) + opacity
     float4* sw;       // 3 float4 per Gaussian: Sigma^-1 (6), w (3), rgb (3)
+    float4* pk;       // 4 float4 per Gaussian: the splat as the renderer reads it
     float2* zd;       // view depth, |mu - o|
     int4* rect;       // tile rectangle, inclusive
     uint32_t* touched;
@@ -61,7 +67,7 @@ int sort_pass_count(int bits);
 constexpr int kSortMaxBins = 512;
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, const FrameBufs& b,
+hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b,
                              hipStream_t s);
 // Exclusive scan of n uint32 values; the total (clamped to `clamp`) goes to
 // *total, and `status` gets the overflow bit if the total exceeds `clamp`;
@@ -70,7 +76,7 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* pa
                        uint32_t clamp, int32_t* status, hipStream_t s, uint32_t* raw_total = nullptr);
 // Writes the unsorted entries into key/value buffer `buf`; tile ids are
 // offset by tile_base and Gaussian ids by id_base (zero for one view).
-hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, const FrameBufs& b, int buf, int32_t* status,
+hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf, int32_t* status,
                             hipStream_t s, uint32_t tile_base = 0, uint32_t id_base = 0);
 // Stable LSD radix sort of the first counters[0] (key, value) pairs on the
 // low `bits` key bits; returns the buffer index (0/1) holding the result.
@@ -88,11 +94,12 @@ hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], c
                              void* const* scatter_events = nullptr, int shift0 = 0);
 // Largest supported sorted prefix per tile (LDS of k_tile_prefix).
 constexpr int kMaxPrefix = 4096;
-// Per-tile sorted prefix from tile-grouped keys: the C <= M entries of
-// smallest (depth, id), sorted, at out[range begin + j] (ids); len[tile] = C
-// (C = all entries when the tile has at most M).  M <= kMaxPrefix.
-hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges, uint32_t n_tiles,
-                              uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s);
+// Per tile of the tile-grouped keys[0, *n_ptr): its range [start, end) into
+// ranges, and its sorted prefix -- the C <= M entries of smallest (depth, id)
+// -- as ids at out[start + j], len[tile] = C (C = all entries when the tile
+// has at most M).  M <= kMaxPrefix.
+hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* n_ptr, uint32_t n_tiles,
+                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s);
 // Whole sorted list of every flagged tile (flag[t] = its entry count) at
 // out[range begin ..], len[t] = count; `scratch` is a second key buffer of the
 // same capacity and the grouped keys are overwritten.  counters[5] += flagged
@@ -113,6 +120,7 @@ struct RenderArgs {
     const float2* xy;
     const float4* co;
     const float4* sw;
+    const float4* pk;
     const float2* zd;
     const uint32_t* vals;
     const uint32_t* ranges;
@@ -142,6 +150,7 @@ struct RenderArgs {
     const uint32_t* pre_vals;
     const uint32_t* pre_len;
     uint32_t* tile_flag;
+    int flags;  // kAblateHierCull: no culling at the 4x4 and 2x2 levels
 };
 enum { kListFull = 0, kListPrefix = 1, kListFlagged = 2, kListSorted = 3 };
 
@@ -163,6 +172,7 @@ struct BatchArgs {
     const float2* xy;
     const float4* co;
     const float4* sw;
+    const float4* pk;
     const float2* zd;
     const uint32_t* vals;
     const uint32_t* ranges;   // per global tile
@@ -171,6 +181,7 @@ struct BatchArgs {
     const uint32_t* pre_vals;
     const uint32_t* pre_len;
     uint32_t* tile_flag;
+    int flags;                // as RenderArgs::flags
     uint32_t* queue;          // work-queue head, zero before the launch
     uint32_t n_items;         // 4 strips per global tile
     const uint32_t* n_tiles_dev;  // if set, n_items = 4 * *n_tiles_dev (tiles listed in order)
@@ -178,6 +189,8 @@ struct BatchArgs {
 };
 
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s);
+// Full per-pixel sort over the tile-grouped (exactly culled) lists.
+hipError_t launch_render_full(const RenderArgs& a, hipStream_t s);
 // Per-ray resorting window of `head` samples over the global order's lists.
 hipError_t launch_render_window(const RenderArgs& a, int head, hipStream_t s);
 hipError_t launch_render_hier_batch(const BatchArgs& b, int head, unsigned grid, hipStream_t s);

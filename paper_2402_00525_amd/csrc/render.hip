@@ -22,6 +22,9 @@
 // k_render_global: the 3DGS order -- each pixel blends its tile's list in
 // key order.
 //
+// k_render_full: the full per-pixel sort (Sec. 3.2) as a reference -- each
+// pixel blends every contributor in (t_opt along its ray, id) order.
+//
 // k_render_window: per-ray resorting (Sec. 3.3) -- each pixel walks its
 // tile's 3DGS list and keeps a window of K samples in registers, ordered by
 // (t_opt along the pixel ray, list rank); the front is blended whenever the
@@ -62,15 +65,17 @@ __device__ __forceinline__ int count_below(const uint64_t* arr, int n, uint64_t 
     return lo;
 }
 
+// Queues of one wavefront.  Merges are done in place: every lane reads the
+// entries it moves into registers, the wavefront synchronises, then writes.
 struct WaveQueues {
-    uint64_t tkey[2][4][kTailCap];
-    uint32_t tid[2][4][kTailCap];
+    uint64_t tkey[4][kTailCap];
+    uint32_t tid[4][kTailCap];
     uint64_t nkey[4][kBatch];
     uint32_t nid[4][kBatch];
     uint64_t skey[4][kBatch];
     uint32_t sid[4][kBatch];
-    uint64_t mkey[2][16][kMidCap];
-    uint32_t mid[2][16][kMidCap];
+    uint64_t mkey[16][kMidCap];
+    uint32_t mid[16][kMidCap];
 };
 
 template <int K, int MODE>
@@ -194,7 +199,7 @@ struct HierCtx {
     float Q0, Q1, Q2, Q3;
     float3 dQ, dP;
     // mid queue state (uniform over the quad)
-    int mb, ms, mn;
+    int ms, mn;
     PixelState<K, MODE> st;
     float* acc;  // backward: the tile's LDS gradient accumulators
 
@@ -203,11 +208,11 @@ struct HierCtx {
     // Head level: the c entries of this quad's mid buffer from position ms0.
     __device__ void push_head(int c, int ms0) {
         for (int e = 0; e < c; ++e) {
-            const uint64_t mk = q.mkey[mb][gq][ms0 + e];
-            uint32_t id = q.mid[mb][gq][ms0 + e];
+            const uint64_t mk = q.mkey[gq][ms0 + e];
+            uint32_t id = q.mid[gq][ms0 + e];
             id = id < a.n ? id : 0u;
             if (!st.done && pix_ok) {
-                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                const Splat g = load_packed(a.pk, id);
                 float alpha;
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
                     const float t = t_opt(g, dP);
@@ -218,8 +223,8 @@ struct HierCtx {
         }
     }
 
-    // Mid level: a chunk of cl tail entries of row `row` (buffer tb, from cs).
-    __device__ void push_mid(int tb, int cs, int cl) {
+    // Mid level: a chunk of cl tail entries of row `row`, from position cs.
+    __device__ void push_mid(int cs, int cl) {
         if (!quad_ok) return;
         const int qbase = lane & ~3;
         for (int r0 = 0; r0 < cl; r0 += kMidBatch) {
@@ -227,12 +232,12 @@ struct HierCtx {
             uint64_t key = kInvalidKey;
             uint32_t id = 0;
             if (idx < cl) {
-                const uint64_t tk = q.tkey[tb][row][cs + idx];
-                id = q.tid[tb][row][cs + idx];
+                const uint64_t tk = q.tkey[row][cs + idx];
+                id = q.tid[row][cs + idx];
                 id = id < a.n ? id : 0u;
-                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                const Splat g = load_packed(a.pk, id);
                 float2 xh;
-                if (keeps_block(g, Q0, Q1, Q2, Q3, xh))
+                if ((a.flags & kAblateHierCull) || keeps_block(g, Q0, Q1, Q2, Q3, xh))
                     key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
             }
             uint64_t qk[4];
@@ -244,24 +249,32 @@ struct HierCtx {
                 rnk += qk[m] < key ? 1 : 0;
                 nnew += qk[m] != kInvalidKey ? 1 : 0;
             }
-            const int ob = mb ^ 1;
+            // The queue holds mn <= 4 entries from ms: one per lane of the quad.
+            uint64_t ek = kInvalidKey;
+            uint32_t eid = 0;
             if (pl < mn) {
-                const uint64_t ek = q.mkey[mb][gq][ms + pl];
-                const uint32_t eid = q.mid[mb][gq][ms + pl];
+                ek = q.mkey[gq][ms + pl];
+                eid = q.mid[gq][ms + pl];
+            }
+            uint64_t qe[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) qe[m] = shfl_u64(ek, qbase + m);
+            wave_lds_sync();
+            if (pl < mn) {
                 int c = 0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) c += qk[m] < ek ? 1 : 0;
-                q.mkey[ob][gq][pl + c] = ek;
-                q.mid[ob][gq][pl + c] = eid;
+                q.mkey[gq][pl + c] = ek;
+                q.mid[gq][pl + c] = eid;
             }
             if (key != kInvalidKey) {
                 int c = 0;
-                for (int m = 0; m < mn; ++m) c += q.mkey[mb][gq][ms + m] < key ? 1 : 0;
-                q.mkey[ob][gq][rnk + c] = key;
-                q.mid[ob][gq][rnk + c] = id;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) c += (m < mn && qe[m] < key) ? 1 : 0;
+                q.mkey[gq][rnk + c] = key;
+                q.mid[gq][rnk + c] = id;
             }
             wave_lds_sync();
-            mb = ob;
             ms = 0;
             mn += nnew;
             while (mn > kMidCap - kMidBatch) {
@@ -353,10 +366,9 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         h.st.hid[i] = 0;
         h.st.ha[i] = 0.0f;
     }
-    h.mb = 0;
     h.ms = 0;
     h.mn = 0;
-    int tb = 0, ts = 0, tn = 0;  // tail state, uniform over the row
+    int ts = 0, tn = 0;  // tail state, uniform over the row
     const int row = h.row, j = h.j;
 
     // The tile's list: entries list[0 .. end), rank = position in the list.
@@ -382,9 +394,9 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 uint32_t id = list[e];
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
-                const Splat g = load_splat(a.xy, a.co, a.sw, id);
+                const Splat g = load_packed(a.pk, id);
                 float2 xh;
-                if (keeps_block(g, S0, S1, S2, S3, xh))
+                if ((a.flags & kAblateHierCull) || keeps_block(g, S0, S1, S2, S3, xh))
                     k2[hh] = ((uint64_t)depth_bits(t_opt(g, dS)) << 32) | (uint64_t)(e - begin);
             }
             q.nkey[row][j + 16 * hh] = k2[hh];
@@ -407,30 +419,38 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 q.sid[row][r2[hh]] = i2[hh];
             }
         wave_lds_sync();
-        // Merge with the tail (both sorted, keys distinct) into the other buffer.
-        const int ob = tb ^ 1;
+        // Merge with the tail (both sorted, keys distinct; tn <= 32 entries
+        // from ts, two per lane) in place from position 0.
+        uint64_t ek[2] = {kInvalidKey, kInvalidKey};
+        uint32_t eid[2] = {0, 0};
+        int pe[2] = {0, 0}, pn[2] = {0, 0};
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int idx = j + 16 * hh;
             if (idx < tn) {
-                const uint64_t ek = q.tkey[tb][row][ts + idx];
-                const uint32_t eid = q.tid[tb][row][ts + idx];
-                const int pos = idx + count_below(q.skey[row], nv, ek);
-                q.tkey[ob][row][pos] = ek;
-                q.tid[ob][row][pos] = eid;
+                ek[hh] = q.tkey[row][ts + idx];
+                eid[hh] = q.tid[row][ts + idx];
+                pe[hh] = idx + count_below(q.skey[row], nv, ek[hh]);
+            }
+            if (k2[hh] != kInvalidKey) pn[hh] = r2[hh] + count_below(&q.tkey[row][ts], tn, k2[hh]);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            if (j + 16 * hh < tn) {
+                q.tkey[row][pe[hh]] = ek[hh];
+                q.tid[row][pe[hh]] = eid[hh];
             }
             if (k2[hh] != kInvalidKey) {
-                const int pos = r2[hh] + count_below(&q.tkey[tb][row][ts], tn, k2[hh]);
-                q.tkey[ob][row][pos] = k2[hh];
-                q.tid[ob][row][pos] = i2[hh];
+                q.tkey[row][pn[hh]] = k2[hh];
+                q.tid[row][pn[hh]] = i2[hh];
             }
         }
         wave_lds_sync();
-        tb = ob;
         ts = 0;
         tn += nv;
         while (tn > kTailCap - kBatch) {
-            h.push_mid(tb, ts, kPop);
+            h.push_mid(ts, kPop);
             ts += kPop;
             tn -= kPop;
         }
@@ -447,7 +467,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         if (row_live) {
             while (tn > 0) {
                 const int c = tn < kPop ? tn : kPop;
-                h.push_mid(tb, ts, c);
+                h.push_mid(ts, c);
                 ts += c;
                 tn -= c;
             }
@@ -551,6 +571,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.xy = b.xy;
         a.co = b.co;
         a.sw = b.sw;
+        a.pk = b.pk;
         a.zd = b.zd;
         a.vals = b.vals;
         a.ranges = b.ranges;
@@ -572,6 +593,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.pre_vals = b.pre_vals;
         a.pre_len = b.pre_len;
         a.tile_flag = b.tile_flag;
+        a.flags = b.flags;
         render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
     }
 }
@@ -617,6 +639,7 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
             g.cb = c.y;
             g.cc = c.z;
             g.op = c.w;
+            g.lt = __int_as_float(0x7fc00000);
             float alpha;
             if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
             const float Tn = T * (1.0f - alpha);
@@ -684,7 +707,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
             uint32_t id = a.vals[idx];
             id = id < a.n ? id : 0u;
             s_id[threadIdx.x] = id;
-            s_g[threadIdx.x] = load_splat(a.xy, a.co, a.sw, id);
+            s_g[threadIdx.x] = load_packed(a.pk, id);
         }
         __syncthreads();
         const uint32_t cnt = (end - start) < 256u ? (end - start) : 256u;
@@ -714,6 +737,105 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
             for (int k = st.n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
     }
     if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
+}
+
+// Full per-pixel order without per-pixel storage: in rounds, every pixel
+// scans its tile's list (exactly culled, so it holds every contributor) and
+// keeps in registers the kFullSel smallest keys (t_opt bits << 32 | id) above
+// the last key it blended, then blends them in order.  A round that finds
+// fewer than kFullSel keys ends the pixel's list; a terminated pixel stops.
+constexpr int kFullSel = 16;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
+    constexpr int K = kFullSel;
+    __shared__ Splat s_g[256];
+    __shared__ uint32_t s_id[256];
+    const DevCam& cam = a.cam;
+    const int tile = blockIdx.x;
+    const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+    const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
+    const bool inside = px < cam.W && py < cam.H;
+    const int pix = py * cam.W + px;
+    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const float3 d = cam_ray(cam, (float)px, (float)py);
+    PixelState<K, MODE> st;
+    st.T = 1.0f;
+    st.C0 = st.C1 = st.C2 = st.D = 0.0f;
+    st.n = 0;
+    st.done = !inside;
+    st.hn = 0;
+    bool more = true;
+    uint64_t floor_key = 0;  // keys below this were blended in earlier rounds
+    while (__syncthreads_or(!st.done && more)) {
+        const bool active = !st.done && more;
+#pragma unroll
+        for (int i = 0; i <= K; ++i) {
+            st.hk[i] = kInvalidKey;
+            st.hid[i] = 0;
+            st.ha[i] = 0.0f;
+        }
+        int found = 0;
+        for (uint32_t start = begin; start < end; start += 256) {
+            const uint32_t idx = start + threadIdx.x;
+            __syncthreads();
+            if (idx < end) {
+                uint32_t id = a.vals[idx];
+                id = id < a.n ? id : 0u;
+                s_id[threadIdx.x] = id;
+                s_g[threadIdx.x] = load_packed(a.pk, id);
+            }
+            __syncthreads();
+            const uint32_t cnt = (end - start) < 256u ? (end - start) : 256u;
+            if (!active) continue;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const Splat& g = s_g[k];
+                float alpha;
+                if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
+                const uint64_t key = ((uint64_t)depth_bits(t_opt(g, d)) << 32) | (uint64_t)s_id[k];
+                if (key < floor_key || key >= st.hk[K - 1]) continue;
+                // insertion into the sorted K smallest; the largest drops out
+#pragma unroll
+                for (int i = K - 1; i >= 1; --i) {
+                    if (st.hk[i - 1] > key) {
+                        st.hk[i] = st.hk[i - 1];
+                        st.hid[i] = st.hid[i - 1];
+                        st.ha[i] = st.ha[i - 1];
+                    } else if (st.hk[i] > key) {
+                        st.hk[i] = key;
+                        st.hid[i] = s_id[k];
+                        st.ha[i] = alpha;
+                    }
+                }
+                if (st.hk[0] > key) {
+                    st.hk[0] = key;
+                    st.hid[0] = s_id[k];
+                    st.ha[0] = alpha;
+                }
+                found = found < K ? found + 1 : K;
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i < found)
+                    blend_one<K, MODE>(a, st, pix, st.hid[i], st.ha[i], depth_from_bits((uint32_t)(st.hk[i] >> 32)),
+                                       0u, nullptr);
+            more = found == K;
+            floor_key = st.hk[K - 1] + 1ull;
+        }
+    }
+    if (inside) {
+        const size_t P = (size_t)cam.W * cam.H;
+        a.rgb[pix] = st.C0 + st.T * a.bg0;
+        a.rgb[P + pix] = st.C1 + st.T * a.bg1;
+        a.rgb[2 * P + pix] = st.C2 + st.T * a.bg2;
+        a.depth[pix] = st.D;
+        a.count[pix] = st.n;
+        a.T[pix] = st.T;
+        if (MODE == kFwdDebug)
+            for (int k = st.n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+    }
 }
 
 template <int K>
@@ -801,6 +923,15 @@ hipError_t launch_render_window(const RenderArgs& a, int head, hipStream_t s) {
         case 24: return launch_window_k<24>(a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_render_full(const RenderArgs& a, hipStream_t s) {
+    const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
+    if (a.blend_ids)
+        hipLaunchKernelGGL(k_render_full<kFwdDebug>, dim3(tiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_render_full<kFwd>, dim3(tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s) {

@@ -8,7 +8,8 @@
 // by (depth bits, Gaussian id) -- the order a full sort of (tile, depth) keys
 // with ties in id order gives -- is produced here in two steps:
 //
-//   k_tile_prefix        every tile: the first C <= M entries of that order,
+//   k_tile_prefix        every tile: its range [start, end) in the grouped
+//                        keys, and the first C <= M entries of that order,
 //                        sorted in LDS;
 //   k_tile_sort_flagged  tiles the renderer flagged because their pixels
 //                        outlived the prefix: the whole list, sorted.
@@ -24,8 +25,22 @@ namespace {
 
 constexpr int kT = 256;              // threads per workgroup
 constexpr int kTW = kT / 64;         // wavefronts per workgroup
-constexpr int kPrefixBins = 2048;    // histogram bins of the prefix selection
+constexpr int kPrefixBins = 4096;    // histogram bins of the prefix selection
 constexpr int kBinsPerThread = kPrefixBins / kT;
+
+// Fixed histogram bins over the order-preserving depth bits: bits 16..30 of
+// (key - ord(2^-8)), i.e. 128 bins per octave of depth from 2^-8 to 2^24;
+// nearer depths (and negative ones) fall into bin 0, farther ones into the
+// last bin.  The map is monotone, so all entries of a bin follow all entries
+// of earlier bins.
+constexpr uint32_t kBinBase = 0xBB800000u;  // order-preserving bits of 2^-8
+constexpr int kBinShift = 16;
+
+__device__ __forceinline__ uint32_t depth_bin(uint32_t d) {
+    if (d < kBinBase) return 0u;
+    const uint32_t b = (d - kBinBase) >> kBinShift;
+    return b < (uint32_t)(kPrefixBins - 1) ? b : (uint32_t)(kPrefixBins - 1);
+}
 
 __device__ __forceinline__ uint32_t depth_of(uint64_t key) { return (uint32_t)key; }
 
@@ -128,17 +143,52 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
     return base + (uint32_t)__popcll(m & lt);
 }
 
-// One workgroup per tile.  Lists of at most M entries are taken whole;
-// longer ones: a histogram of (depth - min) >> shift over kPrefixBins bins,
-// C = the entries of the bins before the first bin at which the running
-// count exceeds M (every entry of a bin precedes every entry of a later bin,
-// so these are the C smallest).  The selected (depth << 32 | id) keys are
+// First positions in the tile-grouped keys[0, E) of tiles ta (threads
+// 0..127) and tb (threads 128..255): each half narrows its interval 128-fold
+// per round by probing 128 evenly spaced keys.  `cnt` holds 4 words.
+__device__ void tile_starts(const uint64_t* __restrict__ keys, uint32_t E, uint32_t ta, uint32_t tb, uint32_t* cnt,
+                            uint32_t& start_a, uint32_t& start_b) {
+    const int tid = threadIdx.x, half = tid >> 7, k = tid & 127, wave = tid >> 6;
+    const uint32_t target = half ? tb : ta;
+    uint32_t lo = 0, hi = E;  // the answer lies in [lo, hi]; uniform over the half
+    while (__syncthreads_or(hi > lo)) {
+        const uint32_t span = hi - lo;
+        const uint32_t step = span == 0u ? 0u : (span + 127u) / 128u;
+        const uint64_t p = (uint64_t)lo + (uint64_t)k * step;
+        const bool valid = span != 0u && p < hi;
+        const bool below = valid && (uint32_t)(keys[p] >> 32) < target;
+        const uint64_t m = __ballot(below);
+        if ((tid & 63) == 0) cnt[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        const uint32_t c = cnt[2 * half] + cnt[2 * half + 1];
+        __syncthreads();
+        if (span != 0u) {
+            const uint32_t nvalid = (span + step - 1u) / step;  // probes inside [lo, hi)
+            const uint32_t nlo = c > 0u ? lo + (c - 1u) * step + 1u : lo;
+            const uint32_t nhi = c < nvalid ? lo + c * step : hi;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (tid == 0) cnt[0] = lo;
+    if (tid == 128) cnt[1] = lo;
+    __syncthreads();
+    start_a = cnt[0];
+    start_b = cnt[1];
+    __syncthreads();
+}
+
+// One workgroup per tile.  Finds the tile's range in the grouped keys (and
+// writes it to ranges), then: a list of at most M entries is taken whole;
+// a longer one gets a histogram of depth_bin over its entries, and C = the
+// entries of the bins before the first bin at which the running count
+// exceeds M (the C smallest keys).  The selected (depth << 32 | id) keys are
 // sorted in LDS (dynamic, 8 * pow2ceil(M) bytes).
 __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles,
-                                                    uint32_t* __restrict__ out, uint32_t* __restrict__ len,
-                                                    uint32_t M) {
+                                                    const uint32_t* __restrict__ n_ptr, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ ranges, uint32_t* __restrict__ out,
+                                                    uint32_t* __restrict__ len, uint32_t M) {
     extern __shared__ uint64_t sk[];
     __shared__ uint32_t hist[kPrefixBins];
     __shared__ uint32_t red[2 * kTW];
@@ -146,7 +196,12 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     const uint32_t tile = blockIdx.x;
     const int tid = threadIdx.x;
     if (tile >= n_tiles) return;
-    const uint32_t rb = ranges[2 * (size_t)tile], re = ranges[2 * (size_t)tile + 1];
+    uint32_t rb, re;
+    tile_starts(keys, *n_ptr, tile, tile + 1u, red, rb, re);
+    if (tid == 0) {  // an empty tile's range is written as [0, 0)
+        ranges[2 * (size_t)tile] = re > rb ? rb : 0u;
+        ranges[2 * (size_t)tile + 1] = re > rb ? re : 0u;
+    }
     const uint32_t n = re - rb;
     if (n <= M) {
         for (uint32_t i = tid; i < n; i += kT) sk[i] = ((uint64_t)depth_of(keys[rb + i]) << 32) | vals[rb + i];
@@ -156,10 +211,6 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
         if (tid == 0) len[tile] = n;
         return;
     }
-    uint32_t dlo, dhi;
-    depth_range(keys, rb, re, red, dlo, dhi);
-    uint32_t shift = 0;
-    while (((dhi - dlo) >> shift) >= (uint32_t)kPrefixBins) ++shift;
     for (int k = tid; k < kPrefixBins; k += kT) hist[k] = 0;
     if (tid == 0) s_fill = 0;
     __syncthreads();
@@ -168,12 +219,12 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
         for (; i + 3 * kT < re; i += 4 * kT) {
             const uint32_t d0 = depth_of(keys[i]), d1 = depth_of(keys[i + kT]);
             const uint32_t d2 = depth_of(keys[i + 2 * kT]), d3 = depth_of(keys[i + 3 * kT]);
-            atomicAdd(&hist[(d0 - dlo) >> shift], 1u);
-            atomicAdd(&hist[(d1 - dlo) >> shift], 1u);
-            atomicAdd(&hist[(d2 - dlo) >> shift], 1u);
-            atomicAdd(&hist[(d3 - dlo) >> shift], 1u);
+            atomicAdd(&hist[depth_bin(d0)], 1u);
+            atomicAdd(&hist[depth_bin(d1)], 1u);
+            atomicAdd(&hist[depth_bin(d2)], 1u);
+            atomicAdd(&hist[depth_bin(d3)], 1u);
         }
-        for (; i < re; i += kT) atomicAdd(&hist[(depth_of(keys[i]) - dlo) >> shift], 1u);
+        for (; i < re; i += kT) atomicAdd(&hist[depth_bin(depth_of(keys[i]))], 1u);
     }
     __syncthreads();
     // The first bin at which the running count exceeds M: each thread owns
@@ -204,7 +255,7 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
         bool take = false;
         if (i < re) {
             k = keys[i];
-            take = ((depth_of(k) - dlo) >> shift) < limit;
+            take = depth_bin(depth_of(k)) < limit;
         }
         const uint32_t slot = wave_append(take, &s_fill);
         if (take) sk[slot] = ((uint64_t)depth_of(k) << 32) | vals[i];
@@ -335,11 +386,12 @@ uint32_t pow2ceil(uint32_t x) {
 
 }  // namespace
 
-hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges, uint32_t n_tiles,
-                              uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s) {
+hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* n_ptr, uint32_t n_tiles,
+                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const size_t shmem = 8 * (size_t)pow2ceil(std::max<uint32_t>(M, 1u));
-    hipLaunchKernelGGL(k_tile_prefix, dim3(n_tiles), dim3(kT), shmem, s, keys, vals, ranges, n_tiles, out, len, M);
+    hipLaunchKernelGGL(k_tile_prefix, dim3(n_tiles), dim3(kT), shmem, s, keys, vals, n_ptr, n_tiles, ranges, out, len,
+                       M);
     return hipGetLastError();
 }
 

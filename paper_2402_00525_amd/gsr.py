@@ -16,7 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgsr.so")
 
 GSR_OK, GSR_EINVAL, GSR_ECAPACITY, GSR_EDEVICE, GSR_EUNSUPPORTED = 0, -1, -2, -3, -4
-MODE_GLOBAL, MODE_HIER, MODE_WINDOW = 0, 1, 3
+MODE_GLOBAL, MODE_HIER, MODE_FULL, MODE_WINDOW = 0, 1, 2, 3
+# Ablations of the hierarchical mode (gsr_config.flags) and the load-balancing
+# threshold that turns load balancing off.
+ABLATE_TILE_DEPTH, ABLATE_TILE_CULL, ABLATE_HIER_CULL = 1, 2, 4
+NO_LOAD_BALANCE = 1 << 30
 STATUS_OVERFLOW = 1
 
 
@@ -45,7 +49,7 @@ class CConfig(C.Structure):
 
 class CLayout(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
-                ("xy", "conic_o", "sw", "zd", "rect", "touched", "kmask", "offsets", "grad2d", "keys", "values",
+                ("xy", "conic_o", "sw", "splat", "zd", "rect", "touched", "kmask", "offsets", "grad2d", "keys", "values",
                  "ranges", "counters", "pre_vals", "pre_len", "tile_flag", "entry_capacity", "total_bytes")]
 
 
@@ -110,10 +114,10 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0), sort_prefix=0) -> CConfig:
+def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0), sort_prefix=0, flags=0) -> CConfig:
     c = CConfig()
     lib().gsr_default_config(C.byref(c))
-    c.mode, c.head, c.lb_threshold, c.sort_prefix = mode, head, lb_threshold, sort_prefix
+    c.mode, c.head, c.lb_threshold, c.sort_prefix, c.flags = mode, head, lb_threshold, sort_prefix, flags
     for i in range(3):
         c.bg[i] = bg[i]
     return c
@@ -266,6 +270,7 @@ class Renderer:
             xy=self.region(n, cam, "xy", torch.float32, 2 * n).view(n, 2),
             conic_o=self.region(n, cam, "conic_o", torch.float32, 4 * n).view(n, 4),
             sw=self.region(n, cam, "sw", torch.float32, 12 * n).view(n, 12),
+            splat=self.region(n, cam, "splat", torch.float32, 16 * n).view(n, 16),
             zd=self.region(n, cam, "zd", torch.float32, 2 * n).view(n, 2),
             rect=self.region(n, cam, "rect", torch.int32, 4 * n).view(n, 4),
             touched=self.region(n, cam, "touched", torch.int32, n),

@@ -11,11 +11,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=None, sort_prefix=0):
+def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=None, sort_prefix=0, flags=0,
+              lb_threshold=32):
     from paper_2402_00525_amd import gsr
     ds = gsr.DeviceScene.from_host(scene)
     r = renderer or gsr.Renderer(entries_hint=entries_hint or max(1 << 16, 64 * scene.n))
-    cfg = gsr.config(mode=mode, head=head, sort_prefix=sort_prefix)
+    cfg = gsr.config(mode=mode, head=head, sort_prefix=sort_prefix, flags=flags, lb_threshold=lb_threshold)
     out = r.render(ds, cam, cfg, max_k=max_k)
     torch.cuda.synchronize()
     n = scene.n
@@ -25,7 +26,7 @@ def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=N
                T=out.T.cpu().numpy(), keys=keys.cpu().numpy().view(np.uint64), values=vals.cpu().numpy().view(np.uint32),
                ranges=ranges.cpu().numpy().view(np.uint32), consumed=r.counter(n, cam, 1), **rec)
     res["mode"] = mode
-    res["sort_prefix"] = sort_prefix or 2048
+    res["sort_prefix"] = sort_prefix or 1024
     if mode == 1:
         res["lists"] = r.tile_lists(n, cam)
     if max_k > 0:
@@ -41,6 +42,15 @@ def assert_records_equal(g, o):
     np.testing.assert_array_equal(g["sw"].view(np.uint32), o.sw.view(np.uint32))
     np.testing.assert_array_equal(g["zd"].view(np.uint32), o.zd.view(np.uint32))
     np.testing.assert_array_equal(g["rect"], o.rect)
+    # the renderer's packed copy holds the same bits, and ln(eps_O / opacity)
+    pk = g["splat"]
+    ref = np.concatenate([o.xy, o.conic_o, o.sw[:, :9]], axis=1)
+    live = o.conic_o[:, 3] > 0
+    ref[~live] = 0.0
+    np.testing.assert_array_equal(pk[:, :15].view(np.uint32), ref.view(np.uint32))
+    lt = np.log((1.0 / 255.0) / o.conic_o[live, 3].astype(np.float64))
+    np.testing.assert_allclose(pk[live, 15], lt, rtol=0, atol=2e-6)
+    assert np.all(pk[~live, 15] == 0.0)
 
 
 def assert_sorted_equal(g, o):

@@ -45,6 +45,12 @@ def test_version_and_default_config(L):
         c.sort_prefix = m
         assert L.lib().gsr_check_config(C.byref(c)) == 0
     c.sort_prefix = 0
+    for f in (1, 2, 4, 7):                                # ablations of the hierarchical mode
+        c.flags = f
+        assert L.lib().gsr_check_config(C.byref(c)) == 0
+    c.mode = L.MODE_GLOBAL
+    assert L.lib().gsr_check_config(C.byref(c)) == -1    # ablations need GSR_MODE_HIER
+    c.flags = 0
     c.mode = L.MODE_WINDOW                                # per-ray window of `head` samples
     for K, code in ((1, 0), (24, 0), (25, -4), (0, -1)):
         c.head = K
@@ -53,7 +59,7 @@ def test_version_and_default_config(L):
 
 @pytest.mark.parametrize("field,value,code", [
     ("tail", 48, -1), ("tail", 96, -4), ("mid", 6, -1), ("mid", 12, -4), ("head", 0, -1), ("head", 25, -4),
-    ("mode", 7, -1), ("mode", 2, -1), ("flags", 1, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
+    ("mode", 7, -1), ("mode", -1, -1), ("flags", 8, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
     ("sort_prefix", 4097, -1)])
 def test_config_validation(L, field, value, code):
     # Sec. 3.4: tail = 32n+32, mid = 4m+4, head >= 1; only the built sizes run.

@@ -162,6 +162,69 @@ def test_window_mode_mixture_1080p():
     assert_images_close(g, o, TOL)
 
 
+@pytest.mark.parametrize("flags", [1, 2, 4, 7])
+def test_ablations_bit_exact(flags):
+    """Table performance_ablation (B) no tile depth, (D) no tile culling,
+    (E) no hierarchical culling, and all three."""
+    sc, _ = synth.workload_small()
+    cam = synth.orbit_camera(160, 112, view=13)
+    say("case: ablation flags", flags)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=48, flags=flags)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=48, flags=flags)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    assert_images_close(g, o, TOL)
+
+
+def _big_gaussian_scene():
+    sc = synth.uniform_scene(1500, seed=31, sh_degree=1)
+    rng = np.random.default_rng(31)
+    big = rng.choice(sc.n, 60, replace=False)
+    sc.scales[big] = rng.uniform(0.15, 0.5, (60, 3)).astype(np.float32)
+    return sc
+
+
+@pytest.mark.parametrize("lb", [0, 1, 16, 64, 1000, 1 << 30])
+def test_load_balancing_threshold_changes_nothing(lb):
+    """(C) and the threshold sweep: masked, serial and cooperative work
+    classes give the same entries and images."""
+    sc = _big_gaussian_scene()
+    cam = synth.front_camera(320, 240)
+    say("case: lb threshold", lb)
+    for mode in (oracle.MODE_HIER, oracle.MODE_GLOBAL):
+        o = oracle.frame(sc, cam, mode=mode, max_k=32)
+        g = gpu_frame(sc, cam, mode=mode, max_k=32, lb_threshold=lb)
+        r = o.rect.astype(np.int64)
+        area = (r[:, 2] - r[:, 0] + 1) * (r[:, 3] - r[:, 1] + 1)
+        assert area[o.touched > 0].max() > 64          # every work class occurs
+        assert_records_equal(g, o)
+        assert_sorted_equal(g, o)
+        np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+        assert_images_close(g, o, TOL)
+
+
+@pytest.mark.parametrize("case", ["small", "ragged", "mixture"])
+def test_full_sort_bit_exact(case):
+    """The full per-pixel sort (Sec. 3.2) against the oracle's brute force
+    over every Gaussian."""
+    if case == "small":
+        sc, cam = synth.workload_small()
+    elif case == "ragged":
+        sc, cam = synth.uniform_scene(1500, seed=21, sh_degree=2), synth.orbit_camera(200, 120, view=11)
+    else:
+        sc, cam = synth.subsample(synth.mixture_scene(100_000, seed=3), 3000), synth.orbit_camera(480, 270, 7)
+    say("case: full sort", case)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_FULL, max_k=128)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_FULL, max_k=128)
+    assert o.count.max() < 128
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["count"], o.count)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    assert_images_close(g, o, TOL)
+
+
 def test_edge_cases_empty_culled_nan():
     from paper_2402_00525_amd import gsr
     cam = synth.front_camera(64, 48)
