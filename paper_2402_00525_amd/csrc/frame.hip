@@ -110,7 +110,8 @@ struct PreOut {
 
 // Projection and colour of Gaussian i (Sec. 2.1, App. A, App. B.2, App. B.4).
 // Returns false (and writes a zero record) when the Gaussian is culled.
-__device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, int i, const PreOut& out,
+// `tight`: the tile rectangle is cut down to the box of the alpha ellipse.
+__device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, bool tight, int i, const PreOut& out,
                             const float* shp, Splat& g, int4& rc) {
     const float mu0 = sc.means[3 * i], mu1 = sc.means[3 * i + 1], mu2 = sc.means[3 * i + 2];
     const float s0 = sc.scales[3 * i], s1 = sc.scales[3 * i + 1], s2 = sc.scales[3 * i + 2];
@@ -230,6 +231,19 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, in
                 fx1 = sel_clamp(fx1, -1.0f, (float)(cam.tiles_x - 1));
                 fy1 = sel_clamp(fy1, -1.0f, (float)(cam.tiles_y - 1));
                 ok = (fx0 <= fx1) && (fy0 <= fy1);
+                if (ok && tight) {
+                    // The tiles tested are those of the alpha ellipse's box:
+                    // q <= t_O^2 has half-widths t_O sqrt(Sigma_2 diagonal), at
+                    // most the radius above; widened the same way (the box may
+                    // be empty when the square is not).
+                    const float tO = sqrtf(2.0f * ln_atanh(op / kEpsO));
+                    const float rx = (tO * sqrtf(a)) * 1.00390625f + 1.0f;
+                    const float ry = (tO * sqrtf(c)) * 1.00390625f + 1.0f;
+                    fx0 = sel_max(fx0, ceilf(((mx - rx) - 15.0f) / 16.0f));
+                    fx1 = sel_min(fx1, floorf((mx + rx) / 16.0f));
+                    fy0 = sel_max(fy0, ceilf(((my - ry) - 15.0f) / 16.0f));
+                    fy1 = sel_min(fy1, floorf((my + ry) / 16.0f));
+                }
             }
             if (ok) {
                 // Colour: SH along the direction camera -> mean (App. B.4).
@@ -294,10 +308,11 @@ __device__ __forceinline__ void tile_hull(const DevCam& cam, int tx, int ty, flo
     y1 = (float)min(ty * 16 + 15, cam.H - 1);
 }
 
-__device__ __forceinline__ bool tile_kept(const Splat& g, const DevCam& cam, int tx, int ty, float2& xh) {
+// Exact tile culling decision (Sec. 3.4) for tile (tx, ty).
+__device__ __forceinline__ bool tile_kept(const Splat& g, const DevCam& cam, int tx, int ty) {
     float x0, x1, y0, y1;
     tile_hull(cam, tx, ty, x0, x1, y0, y1);
-    return keeps_block(g, x0, x1, y0, y1, xh);
+    return block_clears(g, x0, x1, y0, y1);
 }
 
 struct PreArgs {
@@ -354,9 +369,10 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     Splat g;
     int4 rc = make_int4(0, 0, -1, -1);
     bool vis = false;
-    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, i, a.out, s_sh + threadIdx.x * kShStride, g, rc);
+    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, a.mode == kModeHier && !(a.flags & kAblateTileCull), i, a.out,
+                                       s_sh + threadIdx.x * kShStride, g, rc);
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
-    const int area = vis ? wdt * hgt : 0;
+    const int area = (vis && wdt > 0 && hgt > 0) ? wdt * hgt : 0;  // the ellipse box may be empty
     uint32_t cnt = 0, mask = 0;
     const bool no_cull = (a.flags & kAblateTileCull) != 0;
     const bool masked = vis && class_masked(area, a.lb);
@@ -398,8 +414,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             Splat h;
             h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
             h.lt = st.lt[lo];
-            float2 xh;
-            if (no_cull || tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw, xh))
+            if (no_cull || tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw))
                 atomicOr(&st.mask[lo], 1u << k);
         }
         wave_lds_sync();
@@ -407,8 +422,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         cnt = (uint32_t)__popc(mask);
         if (serial) {
             for (int k = 0; k < area; ++k) {
-                float2 xh;
-                if (no_cull || tile_kept(g, a.cam, rc.x + k % wdt, rc.y + k / wdt, xh)) ++cnt;
+                if (no_cull || tile_kept(g, a.cam, rc.x + k % wdt, rc.y + k / wdt)) ++cnt;
             }
         }
     }
@@ -424,8 +438,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
         uint32_t c = 0;
         for (int k = lane; k < rarea; k += 64) {
-            float2 xh;
-            c += (no_cull || tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw, xh)) ? 1u : 0u;
+            c += (no_cull || tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw)) ? 1u : 0u;
         }
         c = wave_reduce_add(c);
         if (lane == src_lane) cnt = c;
@@ -483,9 +496,8 @@ __device__ __forceinline__ bool keep_and_depth(const DupArgs& a, const Splat& h,
         dbits = key_depth(a, h, z, tx, ty);
         return true;
     }
-    float2 xh;
-    if (!tile_kept(h, a.cam, tx, ty, xh)) return false;
-    dbits = (a.flags & kAblateTileDepth) ? depth_bits(z) : depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
+    if (!tile_kept(h, a.cam, tx, ty)) return false;
+    dbits = key_depth(a, h, z, tx, ty);  // exact x^ for the key
     return true;
 }
 

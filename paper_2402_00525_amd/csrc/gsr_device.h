@@ -148,6 +148,9 @@ __device__ __forceinline__ float splat_power(const Splat& g, float px, float py)
 
 // Algorithm 1 (App. B.1): the point of box [x0,x1] x [y0,y1] where the 2D
 // Gaussian is largest, found on the two edges at the corner nearest the mean.
+// FAST: the two edge parameters use a reciprocal instead of a correctly
+// rounded division (for decisions that tolerate it, see block_clears).
+template <bool FAST = false>
 __device__ __forceinline__ float2 box_max_point(const Splat& g, float x0, float x1, float y0, float y1) {
     const float mx = g.x, my = g.y;
     const bool in_x = (x0 <= mx && mx <= x1);
@@ -159,8 +162,13 @@ __device__ __forceinline__ float2 box_max_point(const Splat& g, float x0, float 
     const float ly = ((py == y0) ? y1 : y0) - py;
     const float dx = mx - px, dy = my - py;
     float tx = 0.0f, ty = 0.0f;
-    if (!in_x && ly != 0.0f) ty = sel_clamp((g.cb * dx + g.cc * dy) / (g.cc * ly), 0.0f, 1.0f);
-    if (!in_y && lx != 0.0f) tx = sel_clamp((g.ca * dx + g.cb * dy) / (g.ca * lx), 0.0f, 1.0f);
+    if (FAST) {
+        if (!in_x && ly != 0.0f) ty = sel_clamp(__fdividef(g.cb * dx + g.cc * dy, g.cc * ly), 0.0f, 1.0f);
+        if (!in_y && lx != 0.0f) tx = sel_clamp(__fdividef(g.ca * dx + g.cb * dy, g.ca * lx), 0.0f, 1.0f);
+    } else {
+        if (!in_x && ly != 0.0f) ty = sel_clamp((g.cb * dx + g.cc * dy) / (g.cc * ly), 0.0f, 1.0f);
+        if (!in_y && lx != 0.0f) tx = sel_clamp((g.ca * dx + g.cb * dy) / (g.ca * lx), 0.0f, 1.0f);
+    }
     return make_float2(px + tx * lx, py + ty * ly);
 }
 
@@ -177,10 +185,27 @@ __device__ __forceinline__ bool clears_eps(const Splat& g, float p) {
     return g.op * exp_cw(p) >= kEpsO;
 }
 
-// Exact culling: keep iff the maximum over the block clears eps_O.
+// Exact culling: keep iff the maximum over the block clears eps_O; xh = the
+// block's maximum point x^.
 __device__ __forceinline__ bool keeps_block(const Splat& g, float x0, float x1, float y0, float y1, float2& xh) {
     xh = box_max_point(g, x0, x1, y0, y1);
     return clears_eps(g, splat_power(g, xh.x, xh.y));
+}
+
+// The same decision without x^.  The maximum point is first found with
+// reciprocals; that moves the exponent by about 1e-5 (the 0.3 px^2 dilation
+// bounds the conic), so an exponent more than kFastMargin from lt = ln(eps_O /
+// opacity), and clearly below 0, settles the test; anything else is decided
+// by keeps_block.
+constexpr float kFastMargin = 2e-3f;
+
+__device__ __forceinline__ bool block_clears(const Splat& g, float x0, float x1, float y0, float y1) {
+    const float2 xa = box_max_point<true>(g, x0, x1, y0, y1);
+    const float pa = splat_power(g, xa.x, xa.y);
+    if (pa < g.lt - kFastMargin) return false;
+    if (pa > g.lt + kFastMargin && pa < -kFastMargin) return true;
+    float2 xh;
+    return keeps_block(g, x0, x1, y0, y1, xh);
 }
 
 // alpha at a pixel centre; false when the Gaussian is skipped there (alpha is

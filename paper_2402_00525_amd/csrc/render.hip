@@ -236,8 +236,7 @@ struct HierCtx {
                 id = q.tid[row][cs + idx];
                 id = id < a.n ? id : 0u;
                 const Splat g = load_packed(a.pk, id);
-                float2 xh;
-                if ((a.flags & kAblateHierCull) || keeps_block(g, Q0, Q1, Q2, Q3, xh))
+                if ((a.flags & kAblateHierCull) || block_clears(g, Q0, Q1, Q2, Q3))
                     key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
             }
             uint64_t qk[4];
@@ -395,8 +394,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
                 const Splat g = load_packed(a.pk, id);
-                float2 xh;
-                if ((a.flags & kAblateHierCull) || keeps_block(g, S0, S1, S2, S3, xh))
+                if ((a.flags & kAblateHierCull) || block_clears(g, S0, S1, S2, S3))
                     k2[hh] = ((uint64_t)depth_bits(t_opt(g, dS)) << 32) | (uint64_t)(e - begin);
             }
             q.nkey[row][j + 16 * hh] = k2[hh];
