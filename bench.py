@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-global", action="store_true", help="skip timing the 3DGS global order alongside")
     ap.add_argument("--views", type=int, default=60, help="orbit views to cycle through (60 = full orbit)")
+    ap.add_argument("--sort-prefix", type=int, default=0,
+                    help="entries per tile sorted up front in the hierarchical mode (0 = library default)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched measurement (128 views of 9 scenes, one HIP-graph launch)")
     ap.add_argument("--no-fwd-bwd", action="store_true",
@@ -260,7 +262,7 @@ def main():
     for label, mode in (("hier", gsr.MODE_HIER), ("global", gsr.MODE_GLOBAL)):
         if label == "global" and args.no_global:
             continue
-        cfg = gsr.config(mode=mode)
+        cfg = gsr.config(mode=mode, sort_prefix=args.sort_prefix if mode == gsr.MODE_HIER else 0)
         passes = (gsr.lib().gsr_group_passes(W, H) if mode == gsr.MODE_HIER else gsr.lib().gsr_sort_passes(W, H))
         r = gsr.Renderer(entries_hint=40 * n)
         emax, consumed = plan(r, ds, cams, cfg)

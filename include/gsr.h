@@ -140,6 +140,11 @@ typedef struct gsr_config {
  *   zd       float2 (view depth, |mu - o|)
  *   rect     int32[4] tile rectangle (x0, y0, x1, y1), inclusive
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
+ *            (GSR_MODE_GLOBAL / GSR_MODE_WINDOW)
+ *   dup_hist uint32 [32][ceil(N / 256)]: GSR_MODE_HIER / GSR_MODE_FULL count the
+ *            kept tiles of each block of 256 Gaussians by the low 5 bits of the
+ *            tile id, then hold their exclusive prefix sum (digit-major): the
+ *            start of each block's bucket in the entries
  *   kmask    uint32 kept-tile bit mask (row-major over rect) of Gaussians whose
  *            rectangle holds at most min(lb_threshold, 32) tiles, else 0
  * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
@@ -149,14 +154,14 @@ typedef struct gsr_config {
  * the fallback, number of such tiles, unused);
  * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb).
  * GSR_MODE_GLOBAL: keys/values are fully sorted.
- * GSR_MODE_HIER: keys/values hold the entries grouped by tile (Gaussian id
- * order inside a tile; the keys of tiles that took the fallback are
- * overwritten), pre_vals uint32[capacity] each tile's sorted ids from its
+ * GSR_MODE_HIER: keys/values hold the entries grouped by tile (in no
+ * particular order inside a tile; the keys of tiles that took the fallback
+ * are overwritten), pre_vals uint32[capacity] each tile's sorted ids from its
  * range start (a prefix, or the whole list for a tile that took the
  * fallback), pre_len uint32[tiles] their number, tile_flag uint32[tiles] the
  * entry count of a tile that took the fallback (else 0). */
 typedef struct gsr_layout {
-    int64_t xy, conic_o, sw, splat, zd, rect, touched, kmask, offsets, grad2d;
+    int64_t xy, conic_o, sw, splat, zd, rect, touched, kmask, offsets, dup_hist, grad2d;
     int64_t keys, values, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag;
     int64_t entry_capacity;
@@ -243,8 +248,9 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
  * digits of at most 9 bits): the global order, and the fallback sort. */
 int gsr_sort_passes(int32_t W, int32_t H);
 
-/* Number of radix passes that group a W x H frame's entries by tile (tile
- * bits only; 0 for a single tile). */
+/* Number of radix passes that group a W x H frame's entries by tile: over the
+ * tile bits above the low 5, which duplication already buckets by (0 for at
+ * most 32 tiles). */
 int gsr_group_passes(int32_t W, int32_t H);
 
 /* ---------------------------------------------------------------------------

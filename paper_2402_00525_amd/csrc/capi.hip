@@ -34,11 +34,13 @@ int bits_for_tiles(int tiles) {
 }
 
 // Radix passes of the sort stage and the buffer duplication writes into.
-// HIER: entries are grouped by tile (tile bits only) and the grouped result
-// lands in buffer 0; buffer 1 is then free scratch for the per-tile fallback
-// sort.  GLOBAL: the full (tile, depth) sort, result in buffer 0.
+// HIER: duplication already places entries in buckets of the low
+// kDupDigitBits tile bits (grouped duplication); stable radix passes over the
+// remaining tile bits finish the grouping by tile, which lands in buffer 0;
+// buffer 1 is then free scratch for the per-tile fallback sort.  GLOBAL: the
+// full (tile, depth) sort, result in buffer 0.
 struct SortPlan {
-    int tile_bits, key_bits, tile_passes, full_passes, dup_buf;
+    int tile_bits, key_bits, group_bits, tile_passes, full_passes, dup_buf;
 };
 
 SortPlan sort_plan(int tiles, int mode) {
@@ -46,10 +48,17 @@ SortPlan sort_plan(int tiles, int mode) {
     p.tile_bits = bits_for_tiles(tiles);
     p.key_bits = 32 + p.tile_bits;
     p.full_passes = gsr::sort_pass_count(p.key_bits);
-    p.tile_passes = p.tile_bits > 0 ? gsr::sort_pass_count(p.tile_bits) : 0;
+    p.group_bits = p.tile_bits > gsr::kDupDigitBits ? p.tile_bits - gsr::kDupDigitBits : 0;
+    p.tile_passes = p.group_bits > 0 ? gsr::sort_pass_count(p.group_bits) : 0;
     p.dup_buf = (mode == GSR_MODE_HIER ? p.tile_passes : p.full_passes) & 1;
     return p;
 }
+
+int64_t dup_workgroups(int64_t n) { return (n + 255) / 256; }
+
+// Records of a batch view start at a multiple of 256 (one preprocessing
+// workgroup), so that workgroups are numbered across the batch.
+int64_t align_records(int64_t n) { return (n + 255) & ~(int64_t)255; }
 
 // Layout for a given entry capacity.
 void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_partial, int64_t* hist,
@@ -69,6 +78,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->touched = take(4 * n);
     L->kmask = take(4 * n);
     L->offsets = take(4 * n);
+    L->dup_hist = take(4 * gsr::kDupBins * dup_workgroups(n));
     L->grad2d = take(36 * n);
     L->ranges = take(8 * (int64_t)tiles);
     L->counters = take(64);
@@ -76,6 +86,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->tile_flag = take(4 * (int64_t)tiles);
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
     const int64_t sp = (int64_t)std::max({gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)tiles),
+                                          gsr::scan_partial_len((size_t)(gsr::kDupBins * dup_workgroups(n))),
                                           gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
                        2;
     *scan_partial = take(4 * sp);
@@ -159,6 +170,7 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.touched = (uint32_t*)(base + L.touched);
     b.kmask = (uint32_t*)(base + L.kmask);
     b.offsets = (uint32_t*)(base + L.offsets);
+    b.dhist = (uint32_t*)(base + L.dup_hist);
     b.scan_partial = (uint32_t*)(base + sp);
     b.hist = (uint32_t*)(base + hist);
     b.keys[0] = (uint64_t*)(base + L.keys);
@@ -190,8 +202,8 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
     if (mode == GSR_MODE_HIER) {
         if ((e = gsr::launch_fill_u32(b.tile_flag, (size_t)tiles, 0u, s)) != hipSuccess) return e;
         if (sp.tile_passes > 0) {
-            if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.tile_bits,
-                                            sp.dup_buf, &res, s, scatter_events, 32)) != hipSuccess)
+            if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.group_bits,
+                                            sp.dup_buf, &res, s, scatter_events, 32 + gsr::kDupDigitBits)) != hipSuccess)
                 return e;
         }
         if ((e = mark(0)) != hipSuccess) return e;
@@ -259,12 +271,22 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     };
     if ((e = mark(0)) != hipSuccess) return fail_hip(e, "event");
     if ((e = gsr::launch_fill_u32(b.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
-    if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, cfg->flags, b, s)) != hipSuccess) return fail_hip(e, "preprocess");
+    // Hierarchical lists use grouped duplication (entries bucketed by their
+    // low tile bits), the global order duplication at per-Gaussian offsets.
+    const gsr::DupGroups grp{b.dhist, (uint32_t)dup_workgroups(scene->n), 0u, 0u};
+    const gsr::DupGroups* groups = mode == GSR_MODE_HIER ? &grp : nullptr;
+    if ((e = gsr::launch_preprocess(sc, dc, mode, cfg->lb_threshold, cfg->flags, b, s, groups)) != hipSuccess)
+        return fail_hip(e, "preprocess");
     if ((e = mark(1)) != hipSuccess) return fail_hip(e, "event");
-    if ((e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
-                              s, b.counters + 3)) != hipSuccess)
-        return fail_hip(e, "scan");
-    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, cfg->flags, b, sp.dup_buf, status_dev, s)) != hipSuccess)
+    if (groups)
+        e = gsr::launch_scan(b.dhist, b.dhist, (size_t)gsr::kDupBins * grp.stride, b.scan_partial, b.counters,
+                             b.capacity, status_dev, s, b.counters + 3);
+    else
+        e = gsr::launch_scan(b.touched, b.offsets, (size_t)scene->n, b.scan_partial, b.counters, b.capacity, status_dev,
+                             s, b.counters + 3);
+    if (e != hipSuccess) return fail_hip(e, "scan");
+    if ((e = gsr::launch_duplicate(scene->n, dc, mode, cfg->lb_threshold, cfg->flags, b, sp.dup_buf, status_dev, s, 0u,
+                                   0u, groups)) != hipSuccess)
         return fail_hip(e, "duplicate");
     if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
     const int n_sort_ev = mode == GSR_MODE_HIER ? sp.tile_passes : sp.full_passes;
@@ -384,7 +406,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
 // Batched rendering: many views of several scenes in one launch sequence.
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-    int64_t views, xy, co, sw, pk, zd, rect, touched, kmask, offsets, ranges, counters;
+    int64_t views, xy, co, sw, pk, zd, rect, touched, kmask, offsets, dhist, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag, flist;
     int64_t keys[2], vals[2], hist, partial;
     int64_t tkeys[2], tvals[2], thist, tpartial;
@@ -408,6 +430,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->touched = take(4 * R);
     L->kmask = take(4 * R);
     L->offsets = take(4 * R);
+    L->dhist = take(4 * gsr::kDupBins * dup_workgroups(R));
     L->ranges = take(8 * tiles);
     L->counters = take(64);
     L->pre_len = take(4 * tiles);
@@ -422,6 +445,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->tpartial = take(4 * ((int64_t)gsr::scan_partial_len((size_t)nbt * gsr::kSortMaxBins) + 2));
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
     L->partial = take(4 * ((int64_t)std::max({gsr::scan_partial_len((size_t)R), gsr::scan_partial_len((size_t)tiles),
+                                              gsr::scan_partial_len((size_t)(gsr::kDupBins * dup_workgroups(R))),
                                               gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
                            2));
     L->hist = take(4 * gsr::kSortMaxBins * nb);
@@ -463,7 +487,7 @@ int validate_batch(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* vi
         if (int rc = check_camera(&views[v].cam)) return rc;
         if (!views[v].rgb || !views[v].depth || !views[v].count || !views[v].T)
             return fail(GSR_EINVAL, "view output is NULL");
-        *R += scenes[views[v].scene].n;
+        *R += align_records(scenes[views[v].scene].n);
         *tiles += tiles_of(views[v].cam.W, views[v].cam.H);
     }
     if (*R >= ((int64_t)1 << 32) - 1 || *tiles >= ((int64_t)1 << 31)) return fail(GSR_EINVAL, "batch too large");
@@ -498,6 +522,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.touched = (uint32_t*)(base + L.touched);
     fb.kmask = (uint32_t*)(base + L.kmask);
     fb.offsets = (uint32_t*)(base + L.offsets);
+    fb.dhist = (uint32_t*)(base + L.dhist);
     fb.scan_partial = (uint32_t*)(base + L.partial);
     fb.hist = (uint32_t*)(base + L.hist);
     fb.keys[0] = (uint64_t*)(base + L.keys[0]);
@@ -530,21 +555,30 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
         v.offsets += r0;
         return v;
     };
+    // Grouped duplication over the whole batch: workgroup w of view v is
+    // number rec_base[v] / 256 + w of the batch (every view's records start
+    // at a multiple of 256, so each column of the counts has one writer).
+    const uint32_t nwg = (uint32_t)dup_workgroups(b->R);
+    auto groups_of = [&](size_t v) {
+        return gsr::DupGroups{fb.dhist, nwg, (uint32_t)(b->rec_base[v] / 256), (uint32_t)b->tile_base[v]};
+    };
     for (size_t v = 0; v < b->views.size(); ++v) {
         const gsr_scene& sc = b->scenes[b->views[v].scene];
         const gsr::SceneArgs sa{sc.n, sc.sh_degree, sc.means, sc.scales, sc.rots, sc.opacities, sc.sh};
-        if ((e = gsr::launch_preprocess(sa, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags, shifted(b->rec_base[v]), s)) !=
-            hipSuccess)
+        const gsr::DupGroups g = groups_of(v);
+        if ((e = gsr::launch_preprocess(sa, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags,
+                                        shifted(b->rec_base[v]), s, &g)) != hipSuccess)
             return fail_hip(e, "preprocess");
     }
-    if ((e = gsr::launch_scan(fb.touched, fb.offsets, (size_t)b->R, fb.scan_partial, fb.counters, fb.capacity,
-                              status_dev, s, fb.counters + 3)) != hipSuccess)
+    if ((e = gsr::launch_scan(fb.dhist, fb.dhist, (size_t)gsr::kDupBins * nwg, fb.scan_partial, fb.counters,
+                              fb.capacity, status_dev, s, fb.counters + 3)) != hipSuccess)
         return fail_hip(e, "scan");
     for (size_t v = 0; v < b->views.size(); ++v) {
         const gsr_scene& sc = b->scenes[b->views[v].scene];
-        if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags, shifted(b->rec_base[v]),
-                                       sp.dup_buf, status_dev, s, (uint32_t)b->tile_base[v],
-                                       (uint32_t)b->rec_base[v])) != hipSuccess)
+        const gsr::DupGroups g = groups_of(v);
+        if ((e = gsr::launch_duplicate(sc.n, make_cam(&b->views[v].cam), GSR_MODE_HIER, lb, b->cfg.flags,
+                                       shifted(b->rec_base[v]), sp.dup_buf, status_dev, s, (uint32_t)b->tile_base[v],
+                                       (uint32_t)b->rec_base[v], &g)) != hipSuccess)
             return fail_hip(e, "duplicate");
     }
     if ((e = sort_stage(fb, tiles, GSR_MODE_HIER, (uint32_t)prefix_len(&b->cfg), s, nullptr)) != hipSuccess)
@@ -670,7 +704,7 @@ int gsr_batch_create(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* 
         vd[v].T = views[v].T;
         vd[v].tile_base = (uint32_t)t;
         vd[v].rec_base = (uint32_t)r;
-        r += scenes[views[v].scene].n;
+        r += align_records(scenes[views[v].scene].n);
         t += tiles_of(views[v].cam.W, views[v].cam.H);
     }
     int dev = 0;

@@ -322,7 +322,25 @@ struct PreArgs {
     PreOut out;
     uint32_t* touched;
     uint32_t* kmask;
+    // Grouped duplication (see launch_preprocess): per-workgroup counts of
+    // kept tiles by the low kDupDigitBits bits of the (batch-global) tile id,
+    // digit-major: dhist[d * dh_stride + wg_base + workgroup].
+    uint32_t* dhist;
+    uint32_t dh_stride, wg_base, tile_base;
 };
+
+__device__ __forceinline__ uint32_t dup_digit(const DevCam& cam, uint32_t tile_base, int tx, int ty) {
+    return ((uint32_t)(ty * cam.tiles_x + tx) + tile_base) & (uint32_t)(kDupBins - 1);
+}
+
+// Column of the counts (and order of the buckets' runs) of workgroup w of a
+// launch of nw workgroups: workgroups go to the 8 XCDs round robin, and the
+// runs of workgroups of one XCD are made adjacent, so that a cache line on the
+// boundary of two runs is written through one L2.  A bijection of [0, nw).
+__device__ __forceinline__ uint32_t xcd_column(uint32_t w, uint32_t nw) {
+    const uint32_t q = nw / 8u, r = nw % 8u, x = w % 8u;
+    return x * q + (x < r ? x : r) + w / 8u;
+}
 
 // Work classes of a visible Gaussian in preprocessing and duplication
 // (load balancing, Sec. 3.4), by the number of tiles of its rectangle:
@@ -354,8 +372,11 @@ static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "stagin
 // over the lanes; the others record which rectangle tiles they keep.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     __shared__ float s_sh[256 * kShStride];
+    __shared__ uint32_t s_dh[kDupBins];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
+    const bool grouped = a.dhist != nullptr;
+    for (int d = threadIdx.x; d < kDupBins; d += blockDim.x) s_dh[d] = 0u;
     // Coalesced load of this workgroup's SH coefficients into LDS.
     const int K = (a.sc.deg + 1) * (a.sc.deg + 1), row = 3 * K;
     const int b0 = blockIdx.x * blockDim.x;
@@ -414,15 +435,22 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             Splat h;
             h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
             h.lt = st.lt[lo];
-            if (no_cull || tile_kept(h, a.cam, st.rx0[lo] + k % rw, st.ry0[lo] + k / rw))
+            const int tx = st.rx0[lo] + k % rw, ty = st.ry0[lo] + k / rw;
+            if (no_cull || tile_kept(h, a.cam, tx, ty)) {
                 atomicOr(&st.mask[lo], 1u << k);
+                if (grouped) atomicAdd(&s_dh[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
+            }
         }
         wave_lds_sync();
         mask = st.mask[lane];
         cnt = (uint32_t)__popc(mask);
         if (serial) {
             for (int k = 0; k < area; ++k) {
-                if (no_cull || tile_kept(g, a.cam, rc.x + k % wdt, rc.y + k / wdt)) ++cnt;
+                const int tx = rc.x + k % wdt, ty = rc.y + k / wdt;
+                if (no_cull || tile_kept(g, a.cam, tx, ty)) {
+                    ++cnt;
+                    if (grouped) atomicAdd(&s_dh[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
+                }
             }
         }
     }
@@ -438,7 +466,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
         uint32_t c = 0;
         for (int k = lane; k < rarea; k += 64) {
-            c += (no_cull || tile_kept(h, a.cam, rx0 + k % rw, ry0 + k / rw)) ? 1u : 0u;
+            const int tx = rx0 + k % rw, ty = ry0 + k / rw;
+            if (no_cull || tile_kept(h, a.cam, tx, ty)) {
+                ++c;
+                if (grouped) atomicAdd(&s_dh[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
+            }
         }
         c = wave_reduce_add(c);
         if (lane == src_lane) cnt = c;
@@ -446,6 +478,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     if (i < a.sc.n) {
         a.touched[i] = cnt;
         a.kmask[i] = mask;
+    }
+    if (grouped) {
+        __syncthreads();
+        const uint32_t col = a.wg_base + xcd_column(blockIdx.x, gridDim.x);
+        for (int d = threadIdx.x; d < kDupBins; d += blockDim.x) a.dhist[(size_t)d * a.dh_stride + col] = s_dh[d];
     }
 }
 
@@ -466,6 +503,11 @@ struct DupArgs {
     uint32_t capacity;
     int32_t* status;
     uint32_t tile_base, id_base;
+    // Grouped duplication: the scanned per-workgroup digit counts of
+    // preprocessing; entries go to their digit's bucket (in no particular
+    // order inside it) instead of their Gaussian's offsets.
+    const uint32_t* dhist;
+    uint32_t dh_stride, wg_base;
 };
 
 __device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32_t tile, uint32_t dbits, uint32_t id) {
@@ -520,9 +562,20 @@ struct DupStage {
 // (App. B.4).
 __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     __shared__ DupStage s_st[4];
+    __shared__ uint32_t s_cur[kDupBins];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     DupStage& st = s_st[wave];
+    const bool grouped = a.dhist != nullptr;
+    if (grouped) {
+        const uint32_t col = a.wg_base + xcd_column(blockIdx.x, gridDim.x);
+        for (int d = threadIdx.x; d < kDupBins; d += blockDim.x) s_cur[d] = a.dhist[(size_t)d * a.dh_stride + col];
+        __syncthreads();
+    }
+    // Slot of the next entry of tile (tx, ty) in its bucket.
+    auto bucket_slot = [&](int tx, int ty) -> uint32_t {
+        return atomicAdd(&s_cur[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
+    };
     uint32_t cnt = 0;
     if (i < a.n) cnt = a.touched[i];
     Splat g;
@@ -532,7 +585,7 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     if (cnt > 0) {
         g = load_packed(a.pk, (uint32_t)i);
         rc = a.rect[i];
-        off = a.offsets[i];
+        off = grouped ? 0u : a.offsets[i];
         const float2 zd = a.zd[i];
         zdepth = a.mode == kModeGlobal ? zd.x : zd.y;
     }
@@ -581,7 +634,8 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         h.s22 = st.s22[lo]; h.w0 = st.w0[lo]; h.w1 = st.w1[lo]; h.w2 = st.w2[lo];
         h.lt = __int_as_float(0x7fc00000);  // no culling here: the mask decided
         const uint32_t dbits = key_depth(a, h, st.z[lo], tx, ty);
-        put_entry(a, st.off[lo] + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits, id_wave + (uint32_t)lo);
+        put_entry(a, grouped ? bucket_slot(tx, ty) : st.off[lo] + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits,
+                  id_wave + (uint32_t)lo);
     }
     if (serial) {
         // No load balancing for this Gaussian: its lane walks its rectangle.
@@ -590,7 +644,8 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
             const int tx = rc.x + k % wdt, ty = rc.y + k / wdt;
             uint32_t dbits;
             if (keep_and_depth(a, g, zdepth, tx, ty, dbits)) {
-                put_entry(a, off + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits, (uint32_t)i);
+                put_entry(a, grouped ? bucket_slot(tx, ty) : off + r, (uint32_t)(ty * a.cam.tiles_x + tx), dbits,
+                          (uint32_t)i);
                 ++r;
             }
         }
@@ -622,7 +677,8 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
                 keep = keep_and_depth(a, h, hz, tx, ty, dbits);
             }
             const uint64_t m = __ballot(keep);
-            if (keep) put_entry(a, base + (uint32_t)__popcll(m & lanemask_lt()), (uint32_t)(ty * a.cam.tiles_x + tx),
+            if (keep) put_entry(a, grouped ? bucket_slot(tx, ty) : base + (uint32_t)__popcll(m & lanemask_lt()),
+                                (uint32_t)(ty * a.cam.tiles_x + tx),
                                 dbits, id);
             base += (uint32_t)__popcll(m);
         }
@@ -931,7 +987,7 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 }
 
 hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b,
-                             hipStream_t s) {
+                             hipStream_t s, const DupGroups* groups) {
     if (sc.n == 0) return hipSuccess;
     PreArgs a;
     a.sc = sc;
@@ -942,6 +998,10 @@ hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, i
     a.out = PreOut{b.xy, b.co, b.sw, b.pk, b.zd, b.rect};
     a.touched = b.touched;
     a.kmask = b.kmask;
+    a.dhist = groups ? groups->hist : nullptr;
+    a.dh_stride = groups ? groups->stride : 0u;
+    a.wg_base = groups ? groups->wg_base : 0u;
+    a.tile_base = groups ? groups->tile_base : 0u;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -961,7 +1021,8 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* pa
 }
 
 hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf,
-                            int32_t* status, hipStream_t s, uint32_t tile_base, uint32_t id_base) {
+                            int32_t* status, hipStream_t s, uint32_t tile_base, uint32_t id_base,
+                            const DupGroups* groups) {
     if (n == 0) return hipSuccess;
     DupArgs a;
     a.cam = cam;
@@ -984,6 +1045,9 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flag
     a.status = status;
     a.tile_base = tile_base;
     a.id_base = id_base;
+    a.dhist = groups ? groups->hist : nullptr;
+    a.dh_stride = groups ? groups->stride : 0u;
+    a.wg_base = groups ? groups->wg_base : 0u;
     hipLaunchKernelGGL(k_duplicate, dim3((unsigned)div_up(n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -26,6 +26,7 @@ struct FrameBufs {
     uint32_t* touched;
     uint32_t* kmask;          // kept-tile bit mask of lane-handled Gaussians
     uint32_t* offsets;
+    uint32_t* dhist;          // grouped duplication counts, kDupBins x workgroups
     uint32_t* scan_partial;   // scan scratch, >= scan_partial_len(max(n, hist)) + 2
     uint64_t* keys[2];
     uint32_t* vals[2];
@@ -67,8 +68,22 @@ int sort_pass_count(int bits);
 constexpr int kSortMaxBins = 512;
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+// Grouped duplication (hierarchical lists): entries are written straight
+// into buckets of the low kDupDigitBits bits of their tile id.  Preprocessing
+// counts each workgroup's kept tiles per bucket into hist[d * stride + wg_base
+// + workgroup]; after an exclusive scan of hist (digit-major, so buckets are in
+// digit order), duplication places every entry at its bucket's next slot.
+// Inside a bucket the order is unspecified; only the tile grouping is used.
+constexpr int kDupDigitBits = 5;
+constexpr int kDupBins = 1 << kDupDigitBits;
+struct DupGroups {
+    uint32_t* hist;
+    uint32_t stride;     // workgroups of the whole batch
+    uint32_t wg_base;    // first workgroup of this launch
+    uint32_t tile_base;  // first tile of this view
+};
 hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b,
-                             hipStream_t s);
+                             hipStream_t s, const DupGroups* groups = nullptr);
 // Exclusive scan of n uint32 values; the total (clamped to `clamp`) goes to
 // *total, and `status` gets the overflow bit if the total exceeds `clamp`;
 // raw_total (optional) receives the unclamped total, saturated at 2^32 - 1.
@@ -76,8 +91,9 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* pa
                        uint32_t clamp, int32_t* status, hipStream_t s, uint32_t* raw_total = nullptr);
 // Writes the unsorted entries into key/value buffer `buf`; tile ids are
 // offset by tile_base and Gaussian ids by id_base (zero for one view).
-hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf, int32_t* status,
-                            hipStream_t s, uint32_t tile_base = 0, uint32_t id_base = 0);
+hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf,
+                            int32_t* status, hipStream_t s, uint32_t tile_base = 0, uint32_t id_base = 0,
+                            const DupGroups* groups = nullptr);
 // Stable LSD radix sort of the first counters[0] (key, value) pairs on the
 // low `bits` key bits; returns the buffer index (0/1) holding the result.
 // `scatter_events` (optional): 2 events per pass recorded right before and

@@ -266,27 +266,28 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     if (tid == 0) len[tile] = C;
 }
 
-// One stable LSD pass of a tile's list over 8 bits of (depth - dlo) from
-// `shift`: src/dst hold (depth << 32 | id) except in the first pass, which
-// reads the grouped (tile << 32 | depth) keys and their ids.  Keys are taken
-// in chunks of 256 in list order; inside a chunk a key's place among equal
-// digits is its wavefront's ballot rank plus the counts of the wavefronts
-// before it.
+// One stable LSD pass of a tile's list over 8 bits, from `shift`, of either
+// (id - lo) (by_id) or (depth - lo): src/dst hold (depth << 32 | id) except in
+// the first pass, which reads the grouped (tile << 32 | depth) keys and their
+// ids.  Keys are taken in chunks of 256 in list order; inside a chunk a key's
+// place among equal digits is its wavefront's ballot rank plus the counts of
+// the wavefronts before it.
 __device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t* __restrict__ src_ids, bool first,
-                                uint64_t* __restrict__ dst, uint32_t n, uint32_t dlo, int shift, uint32_t* hst,
-                                uint32_t* base, uint32_t (*wc)[256], uint32_t* lw) {
+                                uint64_t* __restrict__ dst, uint32_t n, bool by_id, uint32_t lo, int shift,
+                                uint32_t* hst, uint32_t* base, uint32_t (*wc)[256], uint32_t* lw) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     auto load = [&](uint32_t i) -> uint64_t {
         const uint64_t k = src[i];
         return first ? (((uint64_t)depth_of(k) << 32) | src_ids[i]) : k;
     };
+    auto digit = [&](uint64_t x) -> uint32_t {
+        const uint32_t v = by_id ? (uint32_t)x : (uint32_t)(x >> 32);
+        return ((v - lo) >> shift) & 255u;
+    };
     hst[tid] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += kT) {
-        const uint32_t d = (uint32_t)(load(i) >> 32);
-        atomicAdd(&hst[((d - dlo) >> shift) & 255u], 1u);
-    }
+    for (uint32_t i = tid; i < n; i += kT) atomicAdd(&hst[digit(load(i))], 1u);
     __syncthreads();
     uint32_t total;
     base[tid] = wg_scan_excl(hst[tid], lw, total);
@@ -295,7 +296,7 @@ __device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t
         const uint32_t i = c0 + tid;
         const bool valid = i < n;
         const uint64_t x = valid ? load(i) : 0ull;
-        const uint32_t dg = ((uint32_t)((x >> 32) - dlo) >> shift) & 255u;
+        const uint32_t dg = digit(x);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -323,11 +324,47 @@ __device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t
     }
 }
 
+// Minimum and maximum of the ids vals[b, e), returned to every thread.
+__device__ void id_range(const uint32_t* __restrict__ vals, uint32_t b, uint32_t e, uint32_t* red, uint32_t& lo,
+                         uint32_t& hi) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t mn = 0xffffffffu, mx = 0u;
+    for (uint32_t i = b + threadIdx.x; i < e; i += kT) {
+        const uint32_t v = vals[i];
+        mn = umin(mn, v);
+        mx = umax(mx, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = umin(mn, (uint32_t)__shfl_xor((int)mn, o));
+        mx = umax(mx, (uint32_t)__shfl_xor((int)mx, o));
+    }
+    if (lane == 0) {
+        red[wave] = mn;
+        red[kTW + wave] = mx;
+    }
+    __syncthreads();
+    lo = red[0];
+    hi = red[kTW];
+#pragma unroll
+    for (int w = 1; w < kTW; ++w) {
+        lo = umin(lo, red[w]);
+        hi = umax(hi, red[kTW + w]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int bits_of(uint32_t span) {
+    int b = 0;
+    while (b < 32 && (span >> b) != 0u) ++b;
+    return b;
+}
+
 // Grid-stride over tiles; a workgroup takes every tile flagged by the prefix
-// render (flag = its entry count) and sorts its whole list: in LDS when it
-// fits (lds_cap entries), else by stable 8-bit LSD passes over the bits that
-// vary, ping-ponging between scratch (the tile's range of the other key
-// buffer) and the grouped keys, which are no longer needed.  Counts flagged
+// render (flag = its entry count) and sorts its whole list by (depth, id): in
+// LDS when it fits (lds_cap entries), else by stable 8-bit LSD passes over the
+// bits that vary, ping-ponging between scratch (the tile's range of the other
+// key buffer) and the grouped keys, which are no longer needed.  Counts flagged
 // entries into counters[5] and tiles into counters[6]; appends flagged tiles
 // to flist when given.
 __global__ __launch_bounds__(kT) void k_tile_sort_flagged(uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
@@ -359,16 +396,19 @@ __global__ __launch_bounds__(kT) void k_tile_sort_flagged(uint64_t* __restrict__
             __syncthreads();
             continue;
         }
-        uint32_t dlo, dhi;
+        // Entries of a tile come in no particular order: sort by the whole
+        // (depth, id) key, least significant part first.
+        uint32_t dlo, dhi, ilo, ihi;
         depth_range(keys, rb, rb + n, red, dlo, dhi);
-        const uint32_t span = dhi - dlo;
-        int bits = 0;
-        while (bits < 32 && (span >> bits) != 0u) ++bits;
-        const int passes = bits == 0 ? 1 : (bits + 7) / 8;
+        id_range(vals, rb, rb + n, red, ilo, ihi);
+        const int id_passes = (bits_of(ihi - ilo) + 7) / 8;
+        const int passes = max(1, id_passes + (bits_of(dhi - dlo) + 7) / 8);  // at least one pass packs the ids
         uint64_t* a = keys + rb;
         uint64_t* b = scratch + rb;
         for (int p = 0; p < passes; ++p) {
-            tile_radix_pass(a, vals + rb, p == 0, b, n, dlo, 8 * p, hst, base, wc, lw);
+            const bool by_id = p < id_passes;
+            tile_radix_pass(a, vals + rb, p == 0, b, n, by_id, by_id ? ilo : dlo, 8 * (by_id ? p : p - id_passes), hst,
+                            base, wc, lw);
             uint64_t* tmp = a;
             a = b;
             b = tmp;

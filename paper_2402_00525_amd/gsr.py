@@ -49,7 +49,8 @@ class CConfig(C.Structure):
 
 class CLayout(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
-                ("xy", "conic_o", "sw", "splat", "zd", "rect", "touched", "kmask", "offsets", "grad2d", "keys", "values",
+                ("xy", "conic_o", "sw", "splat", "zd", "rect", "touched", "kmask", "offsets", "dup_hist", "grad2d", "keys",
+                 "values",
                  "ranges", "counters", "pre_vals", "pre_len", "tile_flag", "entry_capacity", "total_bytes")]
 
 

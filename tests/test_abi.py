@@ -124,8 +124,10 @@ def test_sort_pass_count(L):
     assert L.lib().gsr_sort_passes(1920, 1080) == 5      # 8160 tiles -> 13 bits -> 45 bits
     assert L.lib().gsr_sort_passes(128, 128) == 5        # 64 tiles -> 38 bits
     assert L.lib().gsr_sort_passes(16, 16) == 4          # 1 tile -> 32 bits
-    # grouping by tile alone
-    assert L.lib().gsr_group_passes(1920, 1080) == 2     # 13 bits
+    # grouping by tile: duplication buckets the low 5 tile bits, radix passes the rest
+    assert L.lib().gsr_group_passes(1920, 1080) == 1     # 13 bits
+    assert L.lib().gsr_group_passes(80, 64) == 0         # 20 tiles, 5 bits
     assert L.lib().gsr_group_passes(128, 128) == 1       # 6 bits
+    assert L.lib().gsr_group_passes(7680, 4320) == 2     # 129600 tiles, 17 bits
     assert L.lib().gsr_group_passes(16, 16) == 0
     assert L.lib().gsr_group_passes(0, 16) < 0

@@ -255,11 +255,18 @@ def test_edge_cases_empty_culled_nan():
 
 
 def test_deterministic_repeat():
+    """Outputs, tile ranges and sorted tile lists repeat exactly (the order of
+    entries inside a tile of the grouped buffer is not specified)."""
     sc, cam = synth.workload_small()
     a = gpu_frame(sc, cam, max_k=16)
     b = gpu_frame(sc, cam, max_k=16)
-    for k in ("rgb", "depth", "T", "count", "blend_ids", "keys", "values"):
+    for k in ("rgb", "depth", "T", "count", "blend_ids", "ranges"):
         np.testing.assert_array_equal(a[k], b[k])
+    oa, ob = np.lexsort((a["values"], a["keys"])), np.lexsort((b["values"], b["keys"]))
+    np.testing.assert_array_equal(a["keys"][oa], b["keys"][ob])
+    np.testing.assert_array_equal(a["values"][oa], b["values"][ob])
+    for k in ("pre_vals", "pre_len"):
+        np.testing.assert_array_equal(a["lists"][k], b["lists"][k])
 
 
 def test_overflow_grows_workspace():
