@@ -244,6 +244,19 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                       int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);
 
+/* As gsr_render, with the render counting the work of its levels (a model of
+ * its arithmetic, for roofline accounting; the result images are the same):
+ * work_dev uint64[GSR_WORK_COUNTS] (device, overwritten) =
+ *   (cull tests at the 4x4 level, entries keyed there by t_opt,
+ *    cull tests at the 2x2 level, entries keyed there,
+ *    alpha tests at the pixels, entries keyed there, blends)
+ * for the pass over the tiles' sorted prefixes.  GSR_MODE_HIER with head 4
+ * only (else GSR_EUNSUPPORTED). */
+#define GSR_WORK_COUNTS 7
+int gsr_render_work(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                    size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
+                    int32_t* status_dev, uint64_t* work_dev, gsr_stream_t stream);
+
 /* Number of radix passes a W x H frame's full keys need (32 + tile bits,
  * digits of at most 9 bits): the global order, and the fallback sort. */
 int gsr_sort_passes(int32_t W, int32_t H);

@@ -235,7 +235,8 @@ void set_prefix_lists(gsr::RenderArgs& ra, const gsr::FrameBufs& b, int list_mod
 
 int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                 float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
-                int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events) {
+                int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events,
+                uint64_t* work = nullptr) {
     int rc = check_scene(scene);
     if (rc) return rc;
     if ((rc = check_camera(cam))) return rc;
@@ -321,6 +322,11 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.bg1 = cfg->bg[1];
     ra.bg2 = cfg->bg[2];
     ra.flags = (int)cfg->flags;
+    if (work) {
+        if ((e = gsr::launch_fill_u32((uint32_t*)work, 2 * GSR_WORK_COUNTS, 0u, s)) != hipSuccess)
+            return fail_hip(e, "clear");
+        ra.work = (unsigned long long*)work;
+    }
     if (cfg->mode == GSR_MODE_FULL) {
         ra.list_mode = gsr::kListFull;  // the grouped lists, in any order
         if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
@@ -332,6 +338,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
         if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
         if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
+        ra.work = nullptr;  // the work of the prefix pass is counted
         ra.list_mode = gsr::kListFlagged;
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
     } else if (cfg->mode == GSR_MODE_WINDOW) {
@@ -875,6 +882,16 @@ int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_c
         if (!events[k]) return fail(GSR_EINVAL, "event is NULL");
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
                        events, n_events);
+}
+
+int gsr_render_work(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
+                    float* rgb, float* depth, int32_t* count, float* T_final, int32_t* status_dev, uint64_t* work_dev,
+                    gsr_stream_t stream) {
+    if (!cfg || !work_dev) return fail(GSR_EINVAL, "config or work is NULL");
+    if (cfg->mode != GSR_MODE_HIER || cfg->head != 4)
+        return fail(GSR_EUNSUPPORTED, "work counts are built for the hierarchical render with head 4");
+    return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
+                       nullptr, 0, work_dev);
 }
 
 int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,

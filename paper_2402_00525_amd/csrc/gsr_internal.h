@@ -167,6 +167,7 @@ struct RenderArgs {
     const uint32_t* pre_len;
     uint32_t* tile_flag;
     int flags;  // kAblateHierCull: no culling at the 4x4 and 2x2 levels
+    unsigned long long* work;  // if set: the hierarchical render counts its evaluations (head 4 only)
 };
 enum { kListFull = 0, kListPrefix = 1, kListFlagged = 2, kListSorted = 3 };
 

@@ -35,8 +35,13 @@ namespace gsr {
 
 namespace {
 
-// Kernel modes: forward, forward writing blend-id lists, backward.
-enum { kFwd = 0, kFwdDebug = 1, kBwd = 2 };
+// Kernel modes: forward, forward writing blend-id lists, backward, and
+// forward counting the evaluations of every level (a work model for the
+// render's arithmetic roofline; the counts do not depend on timing).
+enum { kFwd = 0, kFwdDebug = 1, kBwd = 2, kFwdCount = 3 };
+// Work counters (RenderArgs::work): cull tests and keyed (t_opt) entries at
+// the 4x4 and 2x2 levels, alpha tests and keyed entries at the pixels, blends.
+enum { kWorkTailTest = 0, kWorkTailKey, kWorkMidTest, kWorkMidKey, kWorkHeadTest, kWorkHeadKey, kWorkBlend, kWorkN };
 
 constexpr int kBatch = 32;
 // Backward: per-tile LDS accumulators for the first kAccSlots list entries.
@@ -189,6 +194,42 @@ __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key
     s.hn += 1;
 }
 
+// Push into a head of capacity K, blending the front whenever it would hold
+// more than K (the k-buffer rule of Sec. 3.3): while it is not full the entry
+// is inserted; when it is full the smaller of the entry and the front is
+// blended and the other one stays, in a single pass over the slots.
+template <int K, int MODE>
+__device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MODE>& s, int pix, uint64_t key,
+                                          uint32_t id, float alpha, float* acc) {
+    if (s.hn < K) {
+        head_insert<K, MODE>(s, key, id, alpha);
+        return;
+    }
+    if (key < s.hk[0]) {
+        blend_one<K, MODE>(a, s, pix, id, alpha, depth_from_bits((uint32_t)(key >> 32)), (uint32_t)key, acc);
+        return;
+    }
+    const uint64_t k0 = s.hk[0];
+    const uint32_t i0 = s.hid[0];
+    const float a0 = s.ha[0];
+    int pos = 0;  // the entry's slot once the front has left
+#pragma unroll
+    for (int i = 1; i < K; ++i) pos += s.hk[i] < key ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (i < pos) {
+            s.hk[i] = s.hk[i + 1];
+            s.hid[i] = s.hid[i + 1];
+            s.ha[i] = s.ha[i + 1];
+        } else if (i == pos) {
+            s.hk[i] = key;
+            s.hid[i] = id;
+            s.ha[i] = alpha;
+        }
+    }
+    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
+}
+
 template <int K, int MODE>
 struct HierCtx {
     const RenderArgs& a;
@@ -202,6 +243,7 @@ struct HierCtx {
     int ms, mn;
     PixelState<K, MODE> st;
     float* acc;  // backward: the tile's LDS gradient accumulators
+    uint32_t work[kWorkN];  // kFwdCount only
 
     __device__ HierCtx(const RenderArgs& a_, WaveQueues& q_) : a(a_), q(q_) {}
 
@@ -214,10 +256,12 @@ struct HierCtx {
             if (!st.done && pix_ok) {
                 const Splat g = load_packed(a.pk, id);
                 float alpha;
+                if (MODE == kFwdCount) ++work[kWorkHeadTest];
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
+                    if (MODE == kFwdCount) ++work[kWorkHeadKey];
                     const float t = t_opt(g, dP);
-                    head_insert<K, MODE>(st, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha);
-                    if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix, acc);
+                    head_push<K, MODE>(a, st, pix, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), id, alpha,
+                                       acc);
                 }
             }
         }
@@ -236,8 +280,11 @@ struct HierCtx {
                 id = q.tid[row][cs + idx];
                 id = id < a.n ? id : 0u;
                 const Splat g = load_packed(a.pk, id);
-                if ((a.flags & kAblateHierCull) || block_clears(g, Q0, Q1, Q2, Q3))
+                if (MODE == kFwdCount) ++work[kWorkMidTest];
+                if ((a.flags & kAblateHierCull) || block_clears(g, Q0, Q1, Q2, Q3)) {
+                    if (MODE == kFwdCount) ++work[kWorkMidKey];
                     key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
+                }
             }
             uint64_t qk[4];
 #pragma unroll
@@ -319,6 +366,8 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
     HierCtx<K, MODE> h(a, q);
     h.acc = acc;
+    if (MODE == kFwdCount)
+        for (int w = 0; w < kWorkN; ++w) h.work[w] = 0u;
     h.lane = lane;
     h.row = lane >> 4;
     h.j = lane & 15;
@@ -394,8 +443,11 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
                 const Splat g = load_packed(a.pk, id);
-                if ((a.flags & kAblateHierCull) || block_clears(g, S0, S1, S2, S3))
+                if (MODE == kFwdCount) ++h.work[kWorkTailTest];
+                if ((a.flags & kAblateHierCull) || block_clears(g, S0, S1, S2, S3)) {
+                    if (MODE == kFwdCount) ++h.work[kWorkTailKey];
                     k2[hh] = ((uint64_t)depth_bits(t_opt(g, dS)) << 32) | (uint64_t)(e - begin);
+                }
             }
             q.nkey[row][j + 16 * hh] = k2[hh];
             q.nid[row][j + 16 * hh] = i2[hh];
@@ -493,6 +545,15 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         a.T[p] = h.st.T;
         if (MODE == kFwdDebug)
             for (int k = h.st.n; k < a.max_k; ++k) a.blend_ids[p * a.max_k + k] = -1;
+    }
+    if (MODE == kFwdCount) {
+        h.work[kWorkBlend] = h.pix_ok ? (uint32_t)h.st.n : 0u;
+        for (int w = 0; w < kWorkN; ++w) {
+            uint32_t v = h.work[w];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o);
+            if (lane == 0 && v) atomicAdd(a.work + w, (unsigned long long)v);
+        }
     }
     return (b0 < end ? b0 : end) - begin;
 }
@@ -715,8 +776,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
             float alpha;
             if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
             const uint64_t key = ((uint64_t)depth_bits(t_opt(g, d)) << 32) | (uint64_t)(start - begin + k);
-            head_insert<K, MODE>(st, key, s_id[k], alpha);
-            if (st.hn > K) head_pop_blend<K, MODE>(a, st, pix, nullptr);
+            head_push<K, MODE>(a, st, pix, key, s_id[k], alpha, nullptr);
         }
         __syncthreads();
     }
@@ -849,7 +909,10 @@ hipError_t launch_window_k(const RenderArgs& a, hipStream_t s) {
 template <int K>
 hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
-    if (a.grad2d)
+    if (a.work) {
+        if (K != 4) return hipErrorInvalidValue;  // the counting kernel is built for the default head
+        hipLaunchKernelGGL((k_render_hier<4, kFwdCount>), dim3(tiles), dim3(256), 0, s, a);
+    } else if (a.grad2d)
         hipLaunchKernelGGL((k_render_hier<K, kBwd>), dim3(tiles), dim3(256), 0, s, a);
     else if (a.blend_ids)
         hipLaunchKernelGGL((k_render_hier<K, kFwdDebug>), dim3(tiles), dim3(256), 0, s, a);

@@ -57,7 +57,8 @@ class CLayout(C.Structure):
 _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
-           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_sort_passes", "gsr_group_passes",
+           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_render_work",
+           "gsr_sort_passes", "gsr_group_passes",
            "gsr_probe_math",
            "gsr_last_error", "gsr_version")
 
@@ -86,6 +87,9 @@ def lib():
         L.gsr_render_backward.restype = C.c_int
         L.gsr_render_backward.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                           C.c_size_t] + [C.c_void_p] * 9
+        L.gsr_render_work.restype = C.c_int
+        L.gsr_render_work.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
+                                      C.c_size_t] + [C.c_void_p] * 6 + [C.c_void_p]
         L.gsr_render_staged.restype = C.c_int
         L.gsr_render_staged.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                         C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -233,6 +237,25 @@ class Renderer:
                                   _stream())
         _check(rc)
         return out
+
+    WORK_NAMES = ("tail_tests", "tail_keyed", "mid_tests", "mid_keyed", "head_tests", "head_keyed", "blends")
+
+    def render_work(self, scene: DeviceScene, cam, cfg: CConfig | None = None):
+        """Render once with the render's work counters (gsr_render_work);
+        returns (frame, dict of counts).  Synchronises."""
+        cfg = cfg or config()
+        out = Frame(cam.H, cam.W, self.device)
+        work = torch.zeros(len(self.WORK_NAMES), dtype=torch.int64, device=self.device)
+        if self.ws is None:
+            self.plan(scene.n, cam.W, cam.H, self.entries_hint)
+        sc, cc = scene.c_struct(), camera(cam)
+        _check(lib().gsr_render_work(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
+                                     _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T), _ptr(self.status),
+                                     _ptr(work), _stream()))
+        torch.cuda.synchronize()
+        if int(self.status.item()) != 0:
+            raise GsrError(GSR_ECAPACITY, "tile entries overflowed the workspace")
+        return out, dict(zip(self.WORK_NAMES, work.cpu().tolist()))
 
     def render(self, scene: DeviceScene, cam, cfg: CConfig | None = None, max_k: int = 0) -> Frame:
         cfg = cfg or config()

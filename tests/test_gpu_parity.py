@@ -225,6 +225,28 @@ def test_full_sort_bit_exact(case):
     assert_images_close(g, o, TOL)
 
 
+def test_render_work_counts_are_consistent():
+    """gsr_render_work renders the same image and counts one blend per
+    blended Gaussian, at most one keyed entry per test at every level."""
+    from paper_2402_00525_amd import gsr
+    sc = synth.subsample(synth.mixture_scene(100_000, seed=1), 20_000)
+    cam = synth.orbit_camera(640, 360, view=4)
+    say("case: render work counts")
+    ds = gsr.DeviceScene.from_host(sc)
+    r = gsr.Renderer(entries_hint=64 * sc.n)
+    ref = r.render(ds, cam)
+    ref = {k: getattr(ref, k).cpu().numpy().copy() for k in ("rgb", "count", "T")}
+    fr, w = r.render_work(ds, cam)
+    np.testing.assert_array_equal(fr.rgb.cpu().numpy().view(np.uint32), ref["rgb"].view(np.uint32))
+    np.testing.assert_array_equal(fr.count.cpu().numpy(), ref["count"])
+    assert w["blends"] == int(ref["count"].astype(np.int64).sum())
+    for lvl in ("tail", "mid", "head"):
+        assert 0 < w[lvl + "_keyed"] <= w[lvl + "_tests"], w
+    assert w["mid_tests"] <= 4 * w["tail_keyed"] and w["head_tests"] <= 4 * w["mid_keyed"], w
+    with pytest.raises(gsr.GsrError):
+        r.render_work(ds, cam, gsr.config(head=8))
+
+
 def test_edge_cases_empty_culled_nan():
     from paper_2402_00525_amd import gsr
     cam = synth.front_camera(64, 48)
