@@ -39,6 +39,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Source files that define each timed kernel; a change to any of them voids
+# the HBM byte counts taken for it (the profile stores their hash).
+KERNEL_SOURCES = {
+    "k_preprocess": ("frame.hip", "gsr_device.h", "gsr_internal.h"),
+    "k_duplicate": ("frame.hip", "gsr_device.h", "gsr_internal.h"),
+    "k_radix_scatter": ("sort.hip", "gsr_internal.h"),
+    "k_tile_prefix": ("tile_sort.hip", "gsr_internal.h"),
+    "k_render_hier": ("render.hip", "gsr_device.h", "gsr_internal.h"),
+}
+PROFILE = os.path.join(ROOT, "profiles", "frame_3m_1080p_hier.md")
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2402_00525_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes of one launch from the committed counter profile, or None
+    when there is none or the kernel's sources changed since it was taken."""
+    try:
+        with open(PROFILE) as f:
+            for ln in f:
+                p = ln.split()
+                if len(p) == 5 and p[0] == "traffic" and p[1] == kernel and p[2] == workload:
+                    return int(p[3]) if p[4] == kernel_source_hash(kernel) else None
+    except OSError:
+        pass
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +89,9 @@ def parse():
                     help="skip the batched measurement (128 views of 9 scenes, one HIP-graph launch)")
     ap.add_argument("--no-fwd-bwd", action="store_true",
                     help="skip the forward+backward measurement (500k Gaussians, 1280x720, L1 loss)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the sweep of the other renderers (resort windows, head sizes, ablations, "
+                         "load-balancing thresholds, full per-pixel sort)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -96,6 +134,62 @@ def time_frames(r, ds, cams, cfg, steps, warmup, passes):
         k0 = 5 + 2 * passes    # per-tile ordering launch, then the first render launch
         kernels.append([evs[k0].elapsed_time(evs[k0 + 1]), evs[k0 + 2].elapsed_time(evs[k0 + 3])])
     return total / steps, stages, scatter, kernels
+
+
+def time_simple(r, ds, cams, cfg, steps, warmup):
+    """ms per frame over `steps` frames after `warmup` untimed ones."""
+    import torch
+    from paper_2402_00525_amd import gsr
+    out = gsr.Frame(cams[0].H, cams[0].W, "cuda")
+    for i in range(warmup):
+        r.render_async(ds, cams[i % len(cams)], cfg, out)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r.status.zero_()
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(steps):
+        r.render_async(ds, cams[(warmup + i) % len(cams)], cfg, out)
+    end.record()
+    torch.cuda.synchronize()
+    if int(r.status.item()) != 0:
+        raise RuntimeError("tile entries overflowed the planned workspace during timing")
+    return start.elapsed_time(end) / steps
+
+
+def mode_sweep(ds, cams, n, sort_prefix):
+    """The other renderers on the same scene and views: the per-ray resort
+    window over the 3DGS list (Sec. 3.3), the hierarchical render with larger
+    heads, the ablations of Table performance_ablation -- (B) no tile-depth
+    adjustment, (C) no load balancing, (D) no tile culling, (E) no
+    hierarchical culling --, a load-balancing threshold sweep, and the full
+    per-pixel sort (Sec. 3.2).  Each: plan over the views, 2 untimed frames,
+    then one timed frame per view."""
+    import torch
+    from paper_2402_00525_amd import gsr
+    H = gsr.MODE_HIER
+    cases = [("window_K%d" % k, dict(mode=gsr.MODE_WINDOW, head=k)) for k in (4, 8, 16, 24)]
+    cases += [("hier_K%d" % k, dict(mode=H, head=k)) for k in (4, 8, 16, 24)]
+    cases += [("ablation_B_no_tile_depth", dict(mode=H, flags=gsr.ABLATE_TILE_DEPTH)),
+              ("ablation_C_no_load_balancing", dict(mode=H, lb_threshold=gsr.NO_LOAD_BALANCE)),
+              ("ablation_D_no_tile_culling", dict(mode=H, flags=gsr.ABLATE_TILE_CULL)),
+              ("ablation_E_no_hier_culling", dict(mode=H, flags=gsr.ABLATE_HIER_CULL)),
+              ("ablation_BCDE", dict(mode=H, lb_threshold=gsr.NO_LOAD_BALANCE,
+                                     flags=gsr.ABLATE_TILE_DEPTH | gsr.ABLATE_TILE_CULL | gsr.ABLATE_HIER_CULL))]
+    cases += [("lb_threshold_%d" % t, dict(mode=H, lb_threshold=t)) for t in (1, 4, 16, 32, 128, 256)]
+    cases += [("full_sort", dict(mode=gsr.MODE_FULL))]
+    res = {}
+    for name, kw in cases:
+        if kw["mode"] in (H, gsr.MODE_FULL):
+            kw["sort_prefix"] = sort_prefix
+        cfg = gsr.config(**kw)
+        r = gsr.Renderer(entries_hint=40 * n)
+        emax, _ = plan(r, ds, cams, cfg)
+        ms = time_simple(r, ds, cams, cfg, len(cams), 2)
+        res[name] = {"ms_per_frame": round(ms, 4), "entries_max": int(emax)}
+        log("mode %s: %.3f ms/frame (entries max %d)" % (name, ms, emax))
+        del r
+        torch.cuda.empty_cache()
+    return res
 
 
 def plan(r, ds, cams, cfg):
@@ -312,7 +406,7 @@ def main():
         "k_duplicate": (h["stages"][1], h["stages"][1], dup_bytes),
         "k_radix_scatter": (h["scatter"] * h["passes"], h["scatter"], 24.0 * h["E"]),
         "k_tile_prefix": (h["order_ms"], h["order_ms"], 16.0 * h["E"]),
-        "k_render_hier": (h["render_ms"], h["render_ms"], 76.0 * h["consumed"] + 24.0 * P),
+        "k_render_hier": (h["render_ms"], h["render_ms"], 80.0 * h["consumed"] + 24.0 * P),
     }
     kernels = {k: {"ms_per_frame": round(v[0], 4), "GBs": round(v[2] / (v[1] * 1e-3) / 1e9, 1)}
                for k, v in cands.items() if v[1] > 0}
@@ -323,15 +417,17 @@ def main():
         # On-chip bound (LDS queues, VALU): the roofline is the vector ALU's.
         achieved = render_flops / (dur * 1e-3) / 1e12
         roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                    "traffic": profiled_traffic(dom, args.workload),
                     "algorithmic_flops_per_launch": int(render_flops), "avg_launch_ms": round(dur, 4),
                     "work": work}
     else:
         achieved = nbytes / (dur * 1e-3) / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": profiled_traffic(dom, args.workload),
                     "algorithmic_bytes_per_launch": int(nbytes), "avg_launch_ms": round(dur, 4)}
-    frame_bytes = pre_bytes + dup_bytes + h["passes"] * 32.0 * h["E"] + 16.0 * h["E"] + 76.0 * h["consumed"] \
+    frame_bytes = pre_bytes + dup_bytes + h["passes"] * 32.0 * h["E"] + 16.0 * h["E"] + 80.0 * h["consumed"] \
         + 24.0 * P
     line = {
         "metric": METRIC, "value": round(h["ms"], 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
@@ -351,6 +447,10 @@ def main():
         line["global_order"] = {"ms_per_frame": round(g["ms"], 4), "entries": int(g["E"]),
                                 "stages_ms": {k: round(v, 4) for k, v in
                                               zip(("preprocess", "duplicate", "sort", "render"), g["stages"])}}
+    if not args.no_modes:
+        log("mode sweep ...")
+        line["modes"] = {"views": list(range(0, len(cams), 6)),
+                         "results": mode_sweep(ds, cams[::6], n, args.sort_prefix)}
     if not args.no_batch and args.workload != "small":
         log("batched ...")
         line["batched"] = batched(5)

@@ -115,9 +115,9 @@ typedef struct gsr_camera {
  *   head      per-pixel head capacity K (HIER) or window size (WINDOW),
  *             one of 1, 2, 3, 4, 6, 8, 12, 16, 20, 24 (4)
  * lb_threshold only changes speed (tiles above which preprocessing and
- * duplication share a Gaussian across the wavefront; 32; Gaussians of at most
- * min(lb_threshold, 32) tiles share their tiles with the other lanes, those
- * between 32 and lb_threshold are walked by their own lane, and at
+ * duplication share a Gaussian across the wavefront; 64; Gaussians of at most
+ * min(lb_threshold, 64) tiles share their tiles with the other lanes, those
+ * between 64 and lb_threshold are walked by their own lane, and at
  * GSR_NO_LOAD_BALANCE or above every Gaussian is walked by its own lane).
  * bg is the background colour. */
 typedef struct gsr_config {
@@ -145,8 +145,8 @@ typedef struct gsr_config {
  *            kept tiles of each block of 256 Gaussians by the low 5 bits of the
  *            tile id, then hold their exclusive prefix sum (digit-major): the
  *            start of each block's bucket in the entries
- *   kmask    uint32 kept-tile bit mask (row-major over rect) of Gaussians whose
- *            rectangle holds at most min(lb_threshold, 32) tiles, else 0
+ *   kmask    uint64 kept-tile bit mask (row-major over rect) of Gaussians whose
+ *            rectangle holds at most min(lb_threshold, 64) tiles, else 0
  * Sort: keys uint64 (tile << 32 | order-preserving depth bits), values uint32
  * (Gaussian id), ranges uint32[tiles][2] = [start, end) per tile; counters
  * uint32[8] = (entries, entries consumed by the renderer, unused, entries needed before

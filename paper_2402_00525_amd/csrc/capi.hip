@@ -76,7 +76,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->zd = take(8 * n);
     L->rect = take(16 * n);
     L->touched = take(4 * n);
-    L->kmask = take(4 * n);
+    L->kmask = take(8 * n);
     L->offsets = take(4 * n);
     L->dup_hist = take(4 * gsr::kDupBins * dup_workgroups(n));
     L->grad2d = take(36 * n);
@@ -168,7 +168,7 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.zd = (float2*)(base + L.zd);
     b.rect = (int4*)(base + L.rect);
     b.touched = (uint32_t*)(base + L.touched);
-    b.kmask = (uint32_t*)(base + L.kmask);
+    b.kmask = (uint64_t*)(base + L.kmask);
     b.offsets = (uint32_t*)(base + L.offsets);
     b.dhist = (uint32_t*)(base + L.dup_hist);
     b.scan_partial = (uint32_t*)(base + sp);
@@ -435,7 +435,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->zd = take(8 * R);
     L->rect = take(16 * R);
     L->touched = take(4 * R);
-    L->kmask = take(4 * R);
+    L->kmask = take(8 * R);
     L->offsets = take(4 * R);
     L->dhist = take(4 * gsr::kDupBins * dup_workgroups(R));
     L->ranges = take(8 * tiles);
@@ -527,7 +527,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.zd = (float2*)(base + L.zd);
     fb.rect = (int4*)(base + L.rect);
     fb.touched = (uint32_t*)(base + L.touched);
-    fb.kmask = (uint32_t*)(base + L.kmask);
+    fb.kmask = (uint64_t*)(base + L.kmask);
     fb.offsets = (uint32_t*)(base + L.offsets);
     fb.dhist = (uint32_t*)(base + L.dhist);
     fb.scan_partial = (uint32_t*)(base + L.partial);
@@ -665,7 +665,7 @@ void gsr_default_schedule(gsr_schedule* s) {
     if (!s) return;
     s->wgs_per_cu = 2;
     s->cost_order = 1;
-    s->lb_threshold = 32;
+    s->lb_threshold = 64;
 }
 
 int gsr_batch_create(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
@@ -772,7 +772,7 @@ int gsr_batch_tune(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream, const
     std::vector<gsr_schedule> cands;
     for (int w : {1, 2, 3})
         for (int c : {0, 1})
-            for (int lb : {16, 32, 64}) cands.push_back(gsr_schedule{w, c, lb});
+            for (int lb : {32, 64, 128}) cands.push_back(gsr_schedule{w, c, lb});
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(GSR_EDEVICE, "event");
     float best = 1e30f;
@@ -840,7 +840,7 @@ void gsr_default_config(gsr_config* c) {
     c->mid = 8;
     c->mid_batch = 4;
     c->head = 4;
-    c->lb_threshold = 32;
+    c->lb_threshold = 64;
     c->sort_prefix = 0;
 }
 

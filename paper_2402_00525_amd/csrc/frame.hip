@@ -321,7 +321,7 @@ struct PreArgs {
     int mode, lb, flags;
     PreOut out;
     uint32_t* touched;
-    uint32_t* kmask;
+    uint64_t* kmask;
     // Grouped duplication (see launch_preprocess): per-workgroup counts of
     // kept tiles by the low kDupDigitBits bits of the (batch-global) tile id,
     // digit-major: dhist[d * dh_stride + wg_base + workgroup].
@@ -344,15 +344,63 @@ __device__ __forceinline__ uint32_t xcd_column(uint32_t w, uint32_t nw) {
 
 // Work classes of a visible Gaussian in preprocessing and duplication
 // (load balancing, Sec. 3.4), by the number of tiles of its rectangle:
-//   masked    <= min(lb, 32): its (Gaussian, tile) pairs are spread over the
+//   masked    <= min(lb, 64): its (Gaussian, tile) pairs are spread over the
 //             wavefront as one flat list; preprocessing records its kept
-//             tiles as a bit mask;
+//             tiles as a 64-bit mask;
 //   deferred  > lb: the whole wavefront works on it, one Gaussian at a time;
-//   serial    the rest (32 < tiles <= lb), and every Gaussian when lb is
+//   serial    the rest (64 < tiles <= lb), and every Gaussian when lb is
 //             kNoLoadBalance: its own lane walks its rectangle.
-__device__ __forceinline__ int lane_tile_limit(int lb) { return lb < 32 ? lb : 32; }
+__device__ __forceinline__ int lane_tile_limit(int lb) { return lb < 64 ? lb : 64; }
 __device__ __forceinline__ bool class_masked(int area, int lb) { return lb < kNoLoadBalance && area <= lane_tile_limit(lb); }
 __device__ __forceinline__ bool class_deferred(int area, int lb) { return lb < kNoLoadBalance && area > lb; }
+
+// floor(k / w) for 0 <= k < 64 and 1 <= w <= 64 as (k * r16) >> 16 with
+// r16 = ceil(2^16 / w): the product overshoots k / w by less than k / 2^16 <
+// 1 / w, which never reaches the next integer.
+__device__ __forceinline__ uint32_t small_recip(int w) { return (65536u + (uint32_t)w - 1u) / (uint32_t)w; }
+__device__ __forceinline__ int small_div(int k, uint32_t r16) { return (int)(((uint32_t)k * r16) >> 16); }
+
+// Index of the r-th lowest set bit of m (r < popcount(m)), by halving.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t r) {
+    uint32_t w = (uint32_t)m;
+    int pos = 0;
+    const uint32_t c32 = (uint32_t)__popc(w);
+    if (r >= c32) {
+        r -= c32;
+        w = (uint32_t)(m >> 32);
+        pos = 32;
+    }
+#pragma unroll
+    for (int sh = 16; sh > 0; sh >>= 1) {
+        const uint32_t c = (uint32_t)__popc(w & ((1u << sh) - 1u));
+        if (r >= c) {
+            r -= c;
+            w >>= sh;
+            pos += sh;
+        }
+    }
+    return pos;
+}
+
+// Walks rectangle tiles k = lane, lane + 64, ... of a rectangle of width w
+// without a division per step.
+struct RectWalk {
+    int cx, cy, sx, sy, w;
+    __device__ __forceinline__ RectWalk(int lane, int w_) : w(w_) {
+        cy = lane / w;
+        cx = lane - cy * w;
+        sy = 64 / w;
+        sx = 64 - sy * w;
+    }
+    __device__ __forceinline__ void next() {
+        cx += sx;
+        cy += sy;
+        if (cx >= w) {
+            cx -= w;
+            ++cy;
+        }
+    }
+};
 
 // SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
 // stride so that lanes reading their own rows hit distinct banks.
@@ -362,7 +410,8 @@ constexpr int kShStride = 49;
 struct CountStage {
     float x[64], y[64], ca[64], cb[64], cc[64], op[64], lt[64];
     int rx0[64], ry0[64], rw[64];
-    uint32_t pfx[64], mask[64];
+    uint32_t pfx[64], r16[64];
+    uint64_t mask[64];
 };
 static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "staging fits the SH area");
 
@@ -394,7 +443,8 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
                                        s_sh + threadIdx.x * kShStride, g, rc);
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = (vis && wdt > 0 && hgt > 0) ? wdt * hgt : 0;  // the ellipse box may be empty
-    uint32_t cnt = 0, mask = 0;
+    uint32_t cnt = 0;
+    uint64_t mask = 0;
     const bool no_cull = (a.flags & kAblateTileCull) != 0;
     const bool masked = vis && class_masked(area, a.lb);
     const bool deferred = vis && a.mode == kModeHier && class_deferred(area, a.lb);
@@ -418,8 +468,9 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         st.x[lane] = g.x; st.y[lane] = g.y; st.ca[lane] = g.ca; st.cb[lane] = g.cb; st.cc[lane] = g.cc;
         st.op[lane] = g.op; st.lt[lane] = g.lt;
         st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
+        st.r16[lane] = masked ? small_recip(wdt) : 0u;
         st.pfx[lane] = incl - my;
-        st.mask[lane] = 0u;
+        st.mask[lane] = 0ull;
         wave_lds_sync();
         for (uint32_t q = lane; q < total; q += 64) {
             int lo = 0, hi = 63;
@@ -431,19 +482,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
                     hi = mid - 1;
             }
             const int k = (int)(q - st.pfx[lo]);
-            const int rw = st.rw[lo];
+            const int dy = small_div(k, st.r16[lo]);
             Splat h;
             h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
             h.lt = st.lt[lo];
-            const int tx = st.rx0[lo] + k % rw, ty = st.ry0[lo] + k / rw;
+            const int tx = st.rx0[lo] + (k - dy * st.rw[lo]), ty = st.ry0[lo] + dy;
             if (no_cull || tile_kept(h, a.cam, tx, ty)) {
-                atomicOr(&st.mask[lo], 1u << k);
+                atomicOr((unsigned long long*)&st.mask[lo], 1ull << k);
                 if (grouped) atomicAdd(&s_dh[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
             }
         }
         wave_lds_sync();
         mask = st.mask[lane];
-        cnt = (uint32_t)__popc(mask);
+        cnt = (uint32_t)__popcll(mask);
         if (serial) {
             for (int k = 0; k < area; ++k) {
                 const int tx = rc.x + k % wdt, ty = rc.y + k / wdt;
@@ -465,8 +516,9 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         const int rx0 = __shfl(rc.x, src_lane), ry0 = __shfl(rc.y, src_lane);
         const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
         uint32_t c = 0;
-        for (int k = lane; k < rarea; k += 64) {
-            const int tx = rx0 + k % rw, ty = ry0 + k / rw;
+        RectWalk wk(lane, rw);
+        for (int k = lane; k < rarea; k += 64, wk.next()) {
+            const int tx = rx0 + wk.cx, ty = ry0 + wk.cy;
             if (no_cull || tile_kept(h, a.cam, tx, ty)) {
                 ++c;
                 if (grouped) atomicAdd(&s_dh[dup_digit(a.cam, a.tile_base, tx, ty)], 1u);
@@ -496,7 +548,7 @@ struct DupArgs {
     const float2* zd;
     const int4* rect;
     const uint32_t* touched;
-    const uint32_t* kmask;
+    const uint64_t* kmask;
     const uint32_t* offsets;
     uint64_t* keys;
     uint32_t* vals;
@@ -531,15 +583,26 @@ __device__ __forceinline__ uint32_t key_depth(const DupArgs& a, const Splat& h, 
 }
 
 // Keep test and key depth of one rectangle tile (every tile is kept in the
-// global order and in the ablation without tile-based culling).
+// global order and in the ablation without tile-based culling).  With
+// tile-depth adjustment the exact maximum point x^ decides the culling
+// (o exp(power(x^)) against eps_O) and gives the key's ray.
 __device__ __forceinline__ bool keep_and_depth(const DupArgs& a, const Splat& h, float z, int tx, int ty,
                                                uint32_t& dbits) {
-    if (a.mode == kModeGlobal || (a.flags & kAblateTileCull)) {
-        dbits = key_depth(a, h, z, tx, ty);
+    const bool keep_all = a.mode == kModeGlobal || (a.flags & kAblateTileCull);
+    const bool flat_depth = a.mode == kModeGlobal || (a.flags & kAblateTileDepth);
+    float x0, x1, y0, y1;
+    if (flat_depth) {
+        if (!keep_all) {
+            tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+            if (!block_clears(h, x0, x1, y0, y1)) return false;
+        }
+        dbits = depth_bits(z);
         return true;
     }
-    if (!tile_kept(h, a.cam, tx, ty)) return false;
-    dbits = key_depth(a, h, z, tx, ty);  // exact x^ for the key
+    tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+    const float2 xh = box_max_point(h, x0, x1, y0, y1);
+    if (!keep_all && !clears_eps(h, splat_power(h, xh.x, xh.y))) return false;
+    dbits = depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
     return true;
 }
 
@@ -549,7 +612,8 @@ struct DupStage {
     float s00[64], s01[64], s02[64], s11[64], s12[64], s22[64], w0[64], w1[64], w2[64];
     float z[64];
     int rx0[64], ry0[64], rw[64];
-    uint32_t mask[64], off[64], pfx[64];
+    uint32_t off[64], pfx[64], r16[64];
+    uint64_t mask[64];
 };
 
 // Duplication: every kept tile becomes a key (tile << 32 | depth bits) with
@@ -594,8 +658,8 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     const bool small = cnt > 0 && class_masked(area, a.lb);
     const bool deferred = cnt > 0 && class_deferred(area, a.lb);
     const bool serial = cnt > 0 && !small && !deferred;
-    uint32_t mask = 0;
-    if (small) mask = a.mode == kModeHier ? a.kmask[i] : (area >= 32 ? 0xffffffffu : ((1u << area) - 1u));
+    uint64_t mask = 0;
+    if (small) mask = a.mode == kModeHier ? a.kmask[i] : (area >= 64 ? ~0ull : ((1ull << area) - 1ull));
     const uint32_t my = small ? cnt : 0u;
     uint32_t incl = my;
 #pragma unroll
@@ -610,6 +674,7 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     st.z[lane] = zdepth;
     st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
     st.mask[lane] = mask; st.off[lane] = off; st.pfx[lane] = incl - my;
+    st.r16[lane] = small ? small_recip(wdt) : 0u;
     wave_lds_sync();
     const uint32_t id_wave = (uint32_t)(blockIdx.x * blockDim.x + wave * 64);
     for (uint32_t q = lane; q < total; q += 64) {
@@ -623,11 +688,9 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
                 hi = mid - 1;
         }
         const uint32_t r = q - st.pfx[lo];
-        uint32_t m = st.mask[lo];
-        for (uint32_t c = 0; c < r; ++c) m &= m - 1u;  // drop the r lowest kept tiles
-        const int k = __builtin_ctz(m);
-        const int rw = st.rw[lo];
-        const int tx = st.rx0[lo] + k % rw, ty = st.ry0[lo] + k / rw;
+        const int k = nth_set_bit(st.mask[lo], r);  // the r-th kept tile
+        const int dy = small_div(k, st.r16[lo]);
+        const int tx = st.rx0[lo] + (k - dy * st.rw[lo]), ty = st.ry0[lo] + dy;
         Splat h;
         h.x = st.x[lo]; h.y = st.y[lo]; h.ca = st.ca[lo]; h.cb = st.cb[lo]; h.cc = st.cc[lo]; h.op = st.op[lo];
         h.s00 = st.s00[lo]; h.s01 = st.s01[lo]; h.s02 = st.s02[lo]; h.s11 = st.s11[lo]; h.s12 = st.s12[lo];
@@ -666,16 +729,13 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
         uint32_t base = __shfl(off, src);
         const uint32_t id = (uint32_t)__shfl(i, src);
-        for (int k0 = 0; k0 < rarea; k0 += 64) {
+        RectWalk wk(lane, rw);
+        for (int k0 = 0; k0 < rarea; k0 += 64, wk.next()) {
             const int k = k0 + lane;
             bool keep = false;
             uint32_t dbits = 0;
-            int tx = 0, ty = 0;
-            if (k < rarea) {
-                tx = rx0 + k % rw;
-                ty = ry0 + k / rw;
-                keep = keep_and_depth(a, h, hz, tx, ty, dbits);
-            }
+            const int tx = rx0 + wk.cx, ty = ry0 + wk.cy;
+            if (k < rarea) keep = keep_and_depth(a, h, hz, tx, ty, dbits);
             const uint64_t m = __ballot(keep);
             if (keep) put_entry(a, grouped ? bucket_slot(tx, ty) : base + (uint32_t)__popcll(m & lanemask_lt()),
                                 (uint32_t)(ty * a.cam.tiles_x + tx),

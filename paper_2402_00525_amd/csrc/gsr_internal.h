@@ -24,7 +24,7 @@ struct FrameBufs {
     float2* zd;       // view depth, |mu - o|
     int4* rect;       // tile rectangle, inclusive
     uint32_t* touched;
-    uint32_t* kmask;          // kept-tile bit mask of lane-handled Gaussians
+    uint64_t* kmask;          // kept-tile bit mask of lane-handled Gaussians
     uint32_t* offsets;
     uint32_t* dhist;          // grouped duplication counts, kDupBins x workgroups
     uint32_t* scan_partial;   // scan scratch, >= scan_partial_len(max(n, hist)) + 2

@@ -119,7 +119,7 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def config(mode=MODE_HIER, head=4, lb_threshold=32, bg=(0.0, 0.0, 0.0), sort_prefix=0, flags=0) -> CConfig:
+def config(mode=MODE_HIER, head=4, lb_threshold=64, bg=(0.0, 0.0, 0.0), sort_prefix=0, flags=0) -> CConfig:
     c = CConfig()
     lib().gsr_default_config(C.byref(c))
     c.mode, c.head, c.lb_threshold, c.sort_prefix, c.flags = mode, head, lb_threshold, sort_prefix, flags

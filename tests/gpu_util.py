@@ -12,7 +12,7 @@ def say(*a):
 
 
 def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=None, sort_prefix=0, flags=0,
-              lb_threshold=32):
+              lb_threshold=64):
     from paper_2402_00525_amd import gsr
     ds = gsr.DeviceScene.from_host(scene)
     r = renderer or gsr.Renderer(entries_hint=entries_hint or max(1 << 16, 64 * scene.n))

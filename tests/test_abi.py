@@ -38,7 +38,7 @@ def test_library_exports_every_declared_function(L):
 def test_version_and_default_config(L):
     assert b"gfx950" in L.lib().gsr_version()
     c = L.config()
-    assert (c.mode, c.batch, c.tail, c.pop, c.mid, c.mid_batch, c.head, c.lb_threshold) == (1, 32, 64, 16, 8, 4, 4, 32)
+    assert (c.mode, c.batch, c.tail, c.pop, c.mid, c.mid_batch, c.head, c.lb_threshold) == (1, 32, 64, 16, 8, 4, 4, 64)
     assert c.sort_prefix == 0
     assert L.lib().gsr_check_config(C.byref(c)) == 0
     for m in (1, 100, 4096):
@@ -116,7 +116,7 @@ def test_batch_workspace_planning(L):
     views[1].scene = 5                                    # out-of-range scene index
     assert B.gsr_batch_workspace_bytes(scenes, 2, views, 3, 1000) == 0
     s = gsr.schedule()
-    assert (s.wgs_per_cu, s.cost_order, s.lb_threshold) == (2, 1, 32)
+    assert (s.wgs_per_cu, s.cost_order, s.lb_threshold) == (2, 1, 64)
 
 
 def test_sort_pass_count(L):

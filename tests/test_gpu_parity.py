@@ -186,7 +186,7 @@ def _big_gaussian_scene():
     return sc
 
 
-@pytest.mark.parametrize("lb", [0, 1, 16, 64, 1000, 1 << 30])
+@pytest.mark.parametrize("lb", [0, 1, 16, 32, 48, 64, 65, 100, 1000, 1 << 30])
 def test_load_balancing_threshold_changes_nothing(lb):
     """(C) and the threshold sweep: masked, serial and cooperative work
     classes give the same entries and images."""
