@@ -402,6 +402,40 @@ struct RectWalk {
     }
 };
 
+// Owner lookup for a flat list of the pairs of a wavefront's lanes: lane L
+// owns positions [start_L, start_L + len_L), starts in lane order, every
+// list at most 64 long (so at most 64 x 64 positions).  The owner of
+// position p is the r-th non-empty list, r = (number of list starts <= p) -
+// 1; the starts are kept as one 64-bit word per 64 positions, so a step of
+// 64 positions needs one word and a popcount instead of a search.
+struct FlatStarts {
+    uint64_t bits[64];
+    uint32_t lane_of[64];  // lane of the r-th non-empty list
+};
+
+__device__ __forceinline__ void flat_starts_init(FlatStarts& f, uint32_t start, uint32_t len) {
+    const int lane = __lane_id();
+    f.bits[lane] = 0ull;
+    wave_lds_sync();
+    const uint64_t ne = __ballot(len > 0);
+    if (len > 0) {
+        atomicOr((unsigned long long*)&f.bits[start >> 6], 1ull << (start & 63u));
+        f.lane_of[__popcll(ne & lanemask_lt())] = (uint32_t)lane;
+    }
+    wave_lds_sync();
+}
+
+// Owner lane of position 64 j + lane (valid when that position exists);
+// `seen` counts the starts of the steps before j and is advanced.
+__device__ __forceinline__ int flat_owner(const FlatStarts& f, uint32_t j, uint32_t& seen) {
+    const int lane = __lane_id();
+    const uint64_t m = f.bits[j];
+    const uint32_t upto = (uint32_t)__popcll(m & lanemask_lt()) + (uint32_t)((m >> lane) & 1ull);
+    const uint32_t r = seen + upto;
+    seen += (uint32_t)__popcll(m);
+    return r > 0 ? (int)f.lane_of[(r - 1u) & 63u] : 0;
+}
+
 // SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
 // stride so that lanes reading their own rows hit distinct banks.
 constexpr int kShStride = 49;
@@ -412,6 +446,7 @@ struct CountStage {
     int rx0[64], ry0[64], rw[64];
     uint32_t pfx[64], r16[64];
     uint64_t mask[64];
+    FlatStarts fs;
 };
 static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "staging fits the SH area");
 
@@ -420,7 +455,7 @@ static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "stagin
 // wavefront (Sec. 3.4, load balancing), one Gaussian at a time, tiles spread
 // over the lanes; the others record which rectangle tiles they keep.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
-    __shared__ float s_sh[256 * kShStride];
+    __shared__ __align__(16) float s_sh[256 * kShStride];
     __shared__ uint32_t s_dh[kDupBins];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
@@ -431,9 +466,19 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     const int b0 = blockIdx.x * blockDim.x;
     const int nloc = min((int)blockDim.x, a.sc.n - b0);
     const float* src = a.sc.sh + (size_t)b0 * row;
-    for (int f = threadIdx.x; f < nloc * row; f += blockDim.x) {
-        const int gidx = f / row;
-        s_sh[gidx * kShStride + (f - gidx * row)] = src[f];
+    {
+        // (Gaussian, coefficient) of element f, advanced by blockDim.x per step
+        int gidx = (int)threadIdx.x / row, col = (int)threadIdx.x - gidx * row;
+        const int sq = (int)blockDim.x / row, sr = (int)blockDim.x - sq * row;
+        for (int f = threadIdx.x; f < nloc * row; f += blockDim.x) {
+            s_sh[gidx * kShStride + col] = src[f];
+            gidx += sq;
+            col += sr;
+            if (col >= row) {
+                col -= row;
+                ++gidx;
+            }
+        }
     }
     __syncthreads();
     Splat g;
@@ -471,16 +516,12 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         st.r16[lane] = masked ? small_recip(wdt) : 0u;
         st.pfx[lane] = incl - my;
         st.mask[lane] = 0ull;
-        wave_lds_sync();
-        for (uint32_t q = lane; q < total; q += 64) {
-            int lo = 0, hi = 63;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (st.pfx[mid] <= q)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
+        flat_starts_init(st.fs, incl - my, my);
+        uint32_t seen = 0;
+        for (uint32_t j = 0; 64u * j < total; ++j) {
+            const int lo = flat_owner(st.fs, j, seen);
+            const uint32_t q = 64u * j + (uint32_t)lane;
+            if (q >= total) continue;
             const int k = (int)(q - st.pfx[lo]);
             const int dy = small_div(k, st.r16[lo]);
             Splat h;
@@ -510,11 +551,11 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         const int src_lane = __builtin_ctzll(pend);
         pend &= pend - 1;
         Splat h;
-        h.x = __shfl(g.x, src_lane); h.y = __shfl(g.y, src_lane);
-        h.ca = __shfl(g.ca, src_lane); h.cb = __shfl(g.cb, src_lane); h.cc = __shfl(g.cc, src_lane);
-        h.op = __shfl(g.op, src_lane); h.lt = __shfl(g.lt, src_lane);
-        const int rx0 = __shfl(rc.x, src_lane), ry0 = __shfl(rc.y, src_lane);
-        const int rw = __shfl(wdt, src_lane), rarea = __shfl(area, src_lane);
+        h.x = lane_bcast(g.x, src_lane); h.y = lane_bcast(g.y, src_lane);
+        h.ca = lane_bcast(g.ca, src_lane); h.cb = lane_bcast(g.cb, src_lane); h.cc = lane_bcast(g.cc, src_lane);
+        h.op = lane_bcast(g.op, src_lane); h.lt = lane_bcast(g.lt, src_lane);
+        const int rx0 = lane_bcast(rc.x, src_lane), ry0 = lane_bcast(rc.y, src_lane);
+        const int rw = lane_bcast(wdt, src_lane), rarea = lane_bcast(area, src_lane);
         uint32_t c = 0;
         RectWalk wk(lane, rw);
         for (int k = lane; k < rarea; k += 64, wk.next()) {
@@ -614,6 +655,7 @@ struct DupStage {
     int rx0[64], ry0[64], rw[64];
     uint32_t off[64], pfx[64], r16[64];
     uint64_t mask[64];
+    FlatStarts fs;
 };
 
 // Duplication: every kept tile becomes a key (tile << 32 | depth bits) with
@@ -675,18 +717,13 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
     st.rx0[lane] = rc.x; st.ry0[lane] = rc.y; st.rw[lane] = wdt;
     st.mask[lane] = mask; st.off[lane] = off; st.pfx[lane] = incl - my;
     st.r16[lane] = small ? small_recip(wdt) : 0u;
-    wave_lds_sync();
+    flat_starts_init(st.fs, incl - my, my);  // also orders the stores above
     const uint32_t id_wave = (uint32_t)(blockIdx.x * blockDim.x + wave * 64);
-    for (uint32_t q = lane; q < total; q += 64) {
-        // owner: the last lane whose prefix is <= q
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (st.pfx[mid] <= q)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
+    uint32_t seen = 0;
+    for (uint32_t j = 0; 64u * j < total; ++j) {
+        const int lo = flat_owner(st.fs, j, seen);
+        const uint32_t q = 64u * j + (uint32_t)lane;
+        if (q >= total) continue;
         const uint32_t r = q - st.pfx[lo];
         const int k = nth_set_bit(st.mask[lo], r);  // the r-th kept tile
         const int dy = small_div(k, st.r16[lo]);
@@ -718,17 +755,18 @@ __global__ __launch_bounds__(256) void k_duplicate(DupArgs a) {
         const int src = __builtin_ctzll(pend);
         pend &= pend - 1;
         Splat h;
-        h.x = __shfl(g.x, src); h.y = __shfl(g.y, src);
-        h.ca = __shfl(g.ca, src); h.cb = __shfl(g.cb, src); h.cc = __shfl(g.cc, src); h.op = __shfl(g.op, src);
-        h.s00 = __shfl(g.s00, src); h.s01 = __shfl(g.s01, src); h.s02 = __shfl(g.s02, src);
-        h.s11 = __shfl(g.s11, src); h.s12 = __shfl(g.s12, src); h.s22 = __shfl(g.s22, src);
-        h.w0 = __shfl(g.w0, src); h.w1 = __shfl(g.w1, src); h.w2 = __shfl(g.w2, src);
-        h.lt = __shfl(g.lt, src);
-        const float hz = __shfl(zdepth, src);
-        const int rx0 = __shfl(rc.x, src), ry0 = __shfl(rc.y, src);
-        const int rw = __shfl(wdt, src), rarea = __shfl(area, src);
-        uint32_t base = __shfl(off, src);
-        const uint32_t id = (uint32_t)__shfl(i, src);
+        h.x = lane_bcast(g.x, src); h.y = lane_bcast(g.y, src);
+        h.ca = lane_bcast(g.ca, src); h.cb = lane_bcast(g.cb, src); h.cc = lane_bcast(g.cc, src);
+        h.op = lane_bcast(g.op, src);
+        h.s00 = lane_bcast(g.s00, src); h.s01 = lane_bcast(g.s01, src); h.s02 = lane_bcast(g.s02, src);
+        h.s11 = lane_bcast(g.s11, src); h.s12 = lane_bcast(g.s12, src); h.s22 = lane_bcast(g.s22, src);
+        h.w0 = lane_bcast(g.w0, src); h.w1 = lane_bcast(g.w1, src); h.w2 = lane_bcast(g.w2, src);
+        h.lt = lane_bcast(g.lt, src);
+        const float hz = lane_bcast(zdepth, src);
+        const int rx0 = lane_bcast(rc.x, src), ry0 = lane_bcast(rc.y, src);
+        const int rw = lane_bcast(wdt, src), rarea = lane_bcast(area, src);
+        uint32_t base = lane_bcast(off, src);
+        const uint32_t id = lane_bcast((uint32_t)i, src);
         RectWalk wk(lane, rw);
         for (int k0 = 0; k0 < rarea; k0 += 64, wk.next()) {
             const int k = k0 + lane;

@@ -225,6 +225,16 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Value of lane `src` (the same for every lane of the wavefront) in every
+// lane, read into a scalar register.
+__device__ __forceinline__ int lane_bcast(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ uint32_t lane_bcast(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Orders this lane's LDS accesses against those of the other lanes of the
 // same wavefront (compiler barrier plus wait for outstanding LDS operations).
 __device__ __forceinline__ void wave_lds_sync() {
