@@ -108,11 +108,20 @@ struct PreOut {
     int4* rect;
 };
 
-// Projection and colour of Gaussian i (Sec. 2.1, App. A, App. B.2, App. B.4).
-// Returns false (and writes a zero record) when the Gaussian is culled.
-// `tight`: the tile rectangle is cut down to the box of the alpha ellipse.
-__device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, bool tight, int i, const PreOut& out,
-                            const float* shp, Splat& g, int4& rc) {
+// Per-Gaussian results of projection, kept until the colour is known.
+struct ProjOut {
+    float mx, my, ca, cb, cc, op;
+    float Si[6];     // s00 s01 s02 s11 s12 s22
+    float w[3];
+    float pz, dist;
+    float dir[3];    // unit direction camera -> mean (colour)
+    int4 rc;
+};
+
+// Projection of Gaussian i (Sec. 2.1, App. A, App. B.2, App. B.4), all but
+// the colour.  Returns false when the Gaussian is culled.  `tight`: the tile
+// rectangle is cut down to the box of the alpha ellipse.
+__device__ bool project_geom(const SceneArgs& sc, const DevCam& cam, int mode, bool tight, int i, ProjOut& po) {
     const float mu0 = sc.means[3 * i], mu1 = sc.means[3 * i + 1], mu2 = sc.means[3 * i + 2];
     const float s0 = sc.scales[3 * i], s1 = sc.scales[3 * i + 1], s2 = sc.scales[3 * i + 2];
     const float4 qv = reinterpret_cast<const float4*>(sc.rots)[i];
@@ -120,7 +129,6 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, bo
     bool ok = isfinite(mu0) && isfinite(mu1) && isfinite(mu2) && isfinite(s0) && isfinite(s1) && isfinite(s2) &&
               s0 > 0.0f && s1 > 0.0f && s2 > 0.0f && isfinite(qv.x) && isfinite(qv.y) && isfinite(qv.z) &&
               isfinite(qv.w) && isfinite(op);
-    float rgb[3] = {0.0f, 0.0f, 0.0f};
     float Si[3][3];
     float w[3];
     float pz = 0.0f, dist = 0.0f;
@@ -246,42 +254,46 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, bo
                 }
             }
             if (ok) {
-                // Colour: SH along the direction camera -> mean (App. B.4).
+                // Colour direction: camera -> mean (App. B.4).
                 const float len = sqrtf((dm[0] * dm[0] + dm[1] * dm[1]) + dm[2] * dm[2]);
-                const float x = dm[0] / len, y = dm[1] / len, z = dm[2] / len;
+                po.dir[0] = dm[0] / len;
+                po.dir[1] = dm[1] / len;
+                po.dir[2] = dm[2] / len;
                 dist = len;
                 pz = p[2];
-                float bas[16];
-                const int deg = sc.deg;
-                sh_basis(deg, x, y, z, bas);
-                const int K = (deg + 1) * (deg + 1);
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    float acc = bas[0] * shp[ch];
-                    for (int k = 1; k < K; ++k) acc = acc + bas[k] * shp[3 * k + ch];
-                    acc = acc + 0.5f;
-                    if (!isfinite(acc)) ok = false;
-                    rgb[ch] = acc < 0.0f ? 0.0f : acc;
-                }
             }
         }
     }
     if (ok) {
-        g.x = mx; g.y = my; g.ca = ca; g.cb = cb; g.cc = cc; g.op = op;
-        g.lt = -ln_atanh(op / kEpsO);
-        g.s00 = Si[0][0]; g.s01 = Si[0][1]; g.s02 = Si[0][2]; g.s11 = Si[1][1]; g.s12 = Si[1][2]; g.s22 = Si[2][2];
-        g.w0 = w[0]; g.w1 = w[1]; g.w2 = w[2];
-        rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
-        out.xy[i] = make_float2(mx, my);
-        out.co[i] = make_float4(ca, cb, cc, op);
-        out.sw[3 * i] = make_float4(Si[0][0], Si[0][1], Si[0][2], Si[1][1]);
-        out.sw[3 * i + 1] = make_float4(Si[1][2], Si[2][2], w[0], w[1]);
-        out.sw[3 * i + 2] = make_float4(w[2], rgb[0], rgb[1], rgb[2]);
-        out.pk[4 * i] = make_float4(mx, my, ca, cb);
-        out.pk[4 * i + 1] = make_float4(cc, op, Si[0][0], Si[0][1]);
-        out.pk[4 * i + 2] = make_float4(Si[0][2], Si[1][1], Si[1][2], Si[2][2]);
-        out.pk[4 * i + 3] = make_float4(w[0], w[1], w[2], g.lt);
-        out.zd[i] = make_float2(pz, dist);
+        po.mx = mx; po.my = my; po.ca = ca; po.cb = cb; po.cc = cc; po.op = op;
+        po.Si[0] = Si[0][0]; po.Si[1] = Si[0][1]; po.Si[2] = Si[0][2];
+        po.Si[3] = Si[1][1]; po.Si[4] = Si[1][2]; po.Si[5] = Si[2][2];
+        po.w[0] = w[0]; po.w[1] = w[1]; po.w[2] = w[2];
+        po.pz = pz; po.dist = dist;
+        po.rc = make_int4((int)fx0, (int)fy0, (int)fx1, (int)fy1);
+    }
+    return ok;
+}
+
+// Writes Gaussian i's records (a zero record when culled) and its splat.
+__device__ void write_records(const PreOut& out, int i, bool ok, const ProjOut& po, const float* rgb, Splat& g,
+                              int4& rc) {
+    if (ok) {
+        g.x = po.mx; g.y = po.my; g.ca = po.ca; g.cb = po.cb; g.cc = po.cc; g.op = po.op;
+        g.lt = -ln_atanh(po.op / kEpsO);
+        g.s00 = po.Si[0]; g.s01 = po.Si[1]; g.s02 = po.Si[2]; g.s11 = po.Si[3]; g.s12 = po.Si[4]; g.s22 = po.Si[5];
+        g.w0 = po.w[0]; g.w1 = po.w[1]; g.w2 = po.w[2];
+        rc = po.rc;
+        out.xy[i] = make_float2(po.mx, po.my);
+        out.co[i] = make_float4(po.ca, po.cb, po.cc, po.op);
+        out.sw[3 * i] = make_float4(po.Si[0], po.Si[1], po.Si[2], po.Si[3]);
+        out.sw[3 * i + 1] = make_float4(po.Si[4], po.Si[5], po.w[0], po.w[1]);
+        out.sw[3 * i + 2] = make_float4(po.w[2], rgb[0], rgb[1], rgb[2]);
+        out.pk[4 * i] = make_float4(po.mx, po.my, po.ca, po.cb);
+        out.pk[4 * i + 1] = make_float4(po.cc, po.op, po.Si[0], po.Si[1]);
+        out.pk[4 * i + 2] = make_float4(po.Si[2], po.Si[3], po.Si[4], po.Si[5]);
+        out.pk[4 * i + 3] = make_float4(po.w[0], po.w[1], po.w[2], g.lt);
+        out.zd[i] = make_float2(po.pz, po.dist);
         out.rect[i] = rc;
     } else {
         const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -297,7 +309,6 @@ __device__ bool project_one(const SceneArgs& sc, const DevCam& cam, int mode, bo
         out.zd[i] = make_float2(0.0f, 0.0f);
         out.rect[i] = make_int4(0, 0, 0, 0);
     }
-    return ok;
 }
 
 __device__ __forceinline__ void tile_hull(const DevCam& cam, int tx, int ty, float& x0, float& x1, float& y0,
@@ -438,7 +449,11 @@ __device__ __forceinline__ int flat_owner(const FlatStarts& f, uint32_t j, uint3
 
 // SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
 // stride so that lanes reading their own rows hit distinct banks.
-constexpr int kShStride = 49;
+// SH coefficients are staged in LDS in chunks of kShChunk coefficients
+// (3 kShChunk floats per Gaussian, odd row stride so that lanes reading their
+// own rows hit distinct banks).
+constexpr int kShChunk = 8;
+constexpr int kShStride = 3 * kShChunk + 1;
 
 // Per-wavefront staging for the flat kept-tile test (reuses the SH memory).
 struct CountStage {
@@ -461,31 +476,62 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     const int lane = __lane_id();
     const bool grouped = a.dhist != nullptr;
     for (int d = threadIdx.x; d < kDupBins; d += blockDim.x) s_dh[d] = 0u;
-    // Coalesced load of this workgroup's SH coefficients into LDS.
+    ProjOut po;
+    bool vis = false;
+    if (i < a.sc.n) vis = project_geom(a.sc, a.cam, a.mode, a.mode == kModeHier && !(a.flags & kAblateTileCull), i, po);
+    // Colour: SH along the direction camera -> mean (App. B.4), the
+    // coefficients of the workgroup's Gaussians staged through LDS chunk by
+    // chunk with coalesced loads; each channel sums its terms in order k =
+    // 0, 1, ..., K - 1.
     const int K = (a.sc.deg + 1) * (a.sc.deg + 1), row = 3 * K;
     const int b0 = blockIdx.x * blockDim.x;
     const int nloc = min((int)blockDim.x, a.sc.n - b0);
-    const float* src = a.sc.sh + (size_t)b0 * row;
-    {
-        // (Gaussian, coefficient) of element f, advanced by blockDim.x per step
-        int gidx = (int)threadIdx.x / row, col = (int)threadIdx.x - gidx * row;
-        const int sq = (int)blockDim.x / row, sr = (int)blockDim.x - sq * row;
-        for (int f = threadIdx.x; f < nloc * row; f += blockDim.x) {
-            s_sh[gidx * kShStride + col] = src[f];
-            gidx += sq;
-            col += sr;
-            if (col >= row) {
-                col -= row;
-                ++gidx;
+    float rgb[3] = {0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < K; k0 += kShChunk) {
+        const int kc = min(kShChunk, K - k0), ncol = 3 * kc;
+        {
+            // (Gaussian, column) of element f, advanced by blockDim.x per step
+            const float* src = a.sc.sh + (size_t)b0 * row + 3 * k0;
+            int gidx = (int)threadIdx.x / ncol, col = (int)threadIdx.x - gidx * ncol;
+            const int sq = (int)blockDim.x / ncol, sr = (int)blockDim.x - sq * ncol;
+            for (int f = threadIdx.x; f < nloc * ncol; f += blockDim.x) {
+                s_sh[gidx * kShStride + col] = src[(size_t)gidx * row + col];
+                gidx += sq;
+                col += sr;
+                if (col >= ncol) {
+                    col -= ncol;
+                    ++gidx;
+                }
             }
         }
+        __syncthreads();
+        if (vis) {
+            float bas[16];
+            sh_basis(a.sc.deg, po.dir[0], po.dir[1], po.dir[2], bas);
+            const float* shp = s_sh + threadIdx.x * kShStride;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = rgb[ch];
+                for (int k = 0; k < kc; ++k) {
+                    const float t = bas[k0 + k] * shp[3 * k + ch];
+                    acc = (k0 + k == 0) ? t : acc + t;
+                }
+                rgb[ch] = acc;
+            }
+        }
+        __syncthreads();  // the chunk is consumed before the next is staged
     }
-    __syncthreads();
+    if (vis) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float acc = rgb[ch] + 0.5f;
+            if (!isfinite(acc)) vis = false;
+            rgb[ch] = acc < 0.0f ? 0.0f : acc;
+        }
+    }
     Splat g;
     int4 rc = make_int4(0, 0, -1, -1);
-    bool vis = false;
-    if (i < a.sc.n) vis = project_one(a.sc, a.cam, a.mode, a.mode == kModeHier && !(a.flags & kAblateTileCull), i, a.out,
-                                       s_sh + threadIdx.x * kShStride, g, rc);
+    if (i < a.sc.n) write_records(a.out, i, vis, po, rgb, g, rc);
     const int wdt = rc.z - rc.x + 1, hgt = rc.w - rc.y + 1;
     const int area = (vis && wdt > 0 && hgt > 0) ? wdt * hgt : 0;  // the ellipse box may be empty
     uint32_t cnt = 0;
