@@ -51,10 +51,21 @@ constexpr int kPop = 16;
 constexpr int kMidCap = 8;
 constexpr int kMidBatch = 4;
 
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+// Value of lane M of this lane's quad (all four lanes active), by a DPP
+// quad permutation: a VALU move, no LDS round trip.
+template <int M>
+__device__ __forceinline__ uint64_t quad_bcast(uint64_t v) {
+    constexpr int ctrl = M | (M << 2) | (M << 4) | (M << 6);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, ctrl, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), ctrl, 0xf, 0xf, false);
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void quad_all(uint64_t v, uint64_t (&out)[4]) {
+    out[0] = quad_bcast<0>(v);
+    out[1] = quad_bcast<1>(v);
+    out[2] = quad_bcast<2>(v);
+    out[3] = quad_bcast<3>(v);
 }
 
 // Number of entries of sorted arr[0..n) below key.
@@ -249,12 +260,20 @@ struct HierCtx {
 
     // Head level: the c entries of this quad's mid buffer from position ms0.
     __device__ void push_head(int c, int ms0) {
+        if (st.done || !pix_ok) return;
+        uint32_t idn = q.mid[gq][ms0];
+        idn = idn < a.n ? idn : 0u;
+        Splat gn = load_packed(a.pk, idn);  // the next entry's splat, loaded one entry ahead
         for (int e = 0; e < c; ++e) {
             const uint64_t mk = q.mkey[gq][ms0 + e];
-            uint32_t id = q.mid[gq][ms0 + e];
-            id = id < a.n ? id : 0u;
-            if (!st.done && pix_ok) {
-                const Splat g = load_packed(a.pk, id);
+            const uint32_t id = idn;
+            const Splat g = gn;
+            if (e + 1 < c) {
+                idn = q.mid[gq][ms0 + e + 1];
+                idn = idn < a.n ? idn : 0u;
+                gn = load_packed(a.pk, idn);
+            }
+            if (!st.done) {
                 float alpha;
                 if (MODE == kFwdCount) ++work[kWorkHeadTest];
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
@@ -270,7 +289,6 @@ struct HierCtx {
     // Mid level: a chunk of cl tail entries of row `row`, from position cs.
     __device__ void push_mid(int cs, int cl) {
         if (!quad_ok) return;
-        const int qbase = lane & ~3;
         for (int r0 = 0; r0 < cl; r0 += kMidBatch) {
             const int idx = r0 + pl;
             uint64_t key = kInvalidKey;
@@ -287,8 +305,7 @@ struct HierCtx {
                 }
             }
             uint64_t qk[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) qk[m] = shfl_u64(key, qbase + m);
+            quad_all(key, qk);
             int rnk = 0, nnew = 0;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -303,8 +320,7 @@ struct HierCtx {
                 eid = q.mid[gq][ms + pl];
             }
             uint64_t qe[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) qe[m] = shfl_u64(ek, qbase + m);
+            quad_all(ek, qe);
             wave_lds_sync();
             if (pl < mn) {
                 int c = 0;
@@ -427,9 +443,22 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const bool truncated = tl.truncated;
     const uint32_t begin = 0;
     uint32_t b0 = begin;
+    // ids of the next batch, loaded one batch ahead
+    uint32_t nx[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const uint32_t e = b0 + (uint32_t)(j + 16 * hh);
+        nx[hh] = e < end ? list[e] : 0u;
+    }
     for (; b0 < end; b0 += kBatch) {
         const uint64_t live = __ballot(!h.st.done);
         if (live == 0) break;
+        uint32_t cur[2] = {nx[0], nx[1]};
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const uint32_t e = b0 + kBatch + (uint32_t)(j + 16 * hh);
+            nx[hh] = e < end ? list[e] : 0u;
+        }
         const bool row_live = sub_ok && ((live >> (row * 16)) & 0xffffull) != 0;
         if (!row_live) continue;
         // Cull against the sub-tile and key along its centre ray.
@@ -439,7 +468,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         for (int hh = 0; hh < 2; ++hh) {
             const uint32_t e = b0 + (uint32_t)(j + 16 * hh);
             if (e < end) {
-                uint32_t id = list[e];
+                uint32_t id = cur[hh];
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
                 const Splat g = load_packed(a.pk, id);

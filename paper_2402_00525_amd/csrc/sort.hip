@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
     }
 }
 
+template <int NW>
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* lw, uint32_t& total) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     uint32_t x = v;
@@ -72,7 +73,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* lw, ui
     __syncthreads();
     uint32_t before = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
         const uint32_t sw = lw[w];
         if (w < wave) before += sw;
         tot += sw;
@@ -81,52 +82,59 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* lw, ui
     return before + x - v;
 }
 
+// The scatter of a sort tile runs 8 wavefronts of 8 rounds each: twice the
+// resident wavefronts of 4 x 16 in the same LDS.
+constexpr int kScatterWaves = 8;
+constexpr int kScatterRounds = kSortTile / (64 * kScatterWaves);
+constexpr int kScatterThreads = 64 * kScatterWaves;
+static_assert(kScatterRounds * kScatterThreads == kSortTile, "scatter covers one sort tile");
+
 // One stable counting pass over `width` key bits from `shift`.
-//  1. Each wavefront ranks its 1024 keys (16 rounds of 64, in index order):
+//  1. Each wavefront ranks its 512 keys (8 rounds of 64, in index order):
 //     lanes with equal digits are found by ballots over the digit bits, and
 //     a per-wavefront running count per digit in LDS gives each key its rank
 //     among equal digits -- no workgroup barrier inside the loop.
-//  2. Per digit: offsets of the four wavefronts, the block's local start
+//  2. Per digit: offsets of the eight wavefronts, the block's local start
 //     (exclusive scan over digits) and the distance to the global start.
 //  3. Keys are placed in LDS in (digit, index) order, then written out so
 //     that consecutive lanes write consecutive addresses of a digit's run.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
+__global__ __launch_bounds__(kScatterThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
                                                                 const uint32_t* __restrict__ vin,
                                                                 uint64_t* __restrict__ kout,
                                                                 uint32_t* __restrict__ vout,
                                                                 const uint32_t* __restrict__ n_ptr, int shift,
                                                                 int width, const uint32_t* __restrict__ hist,
                                                                 uint32_t nblocks) {
-    __shared__ uint32_t cnt[kWaves][kMaxBins];
+    __shared__ uint32_t cnt[kScatterWaves][kMaxBins];
     __shared__ uint32_t dstart[kMaxBins];
     __shared__ uint32_t gdelta[kMaxBins];
     __shared__ uint64_t sk[kSortTile];
     __shared__ uint32_t sv[kSortTile];
-    __shared__ uint32_t lw[kWaves];
+    __shared__ uint32_t lw[kScatterWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int bins = 1 << width;
     const uint32_t mask = (uint32_t)bins - 1u;
     const uint32_t n = *n_ptr;
     const size_t base = (size_t)blockIdx.x * kSortTile;
     if (base >= n) return;
-    for (int k = tid; k < kWaves * kMaxBins; k += kSortThreads) (&cnt[0][0])[k] = 0;
+    for (int k = tid; k < kScatterWaves * kMaxBins; k += kScatterThreads) (&cnt[0][0])[k] = 0;
     __syncthreads();
 
     const uint64_t lt = lanemask_lt();
-    uint64_t key[kSortRounds];
-    uint32_t val[kSortRounds];
-    uint32_t pos[kSortRounds];
+    uint64_t key[kScatterRounds];
+    uint32_t val[kScatterRounds];
+    uint32_t pos[kScatterRounds];
     // All loads first, so that they are in flight together.
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const size_t i = base + (size_t)wave * (kSortRounds * 64) + (size_t)r * 64 + lane;
+    for (int r = 0; r < kScatterRounds; ++r) {
+        const size_t i = base + (size_t)wave * (kScatterRounds * 64) + (size_t)r * 64 + lane;
         const bool valid = i < n;
         key[r] = valid ? kin[i] : 0ull;
         val[r] = valid ? vin[i] : 0u;
         pos[r] = valid ? 0u : 0xffffffffu;
     }
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < kScatterRounds; ++r) {
         const bool valid = pos[r] == 0u;
         const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
@@ -151,7 +159,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         if (d < bins) {
             uint32_t acc = 0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < kScatterWaves; ++w) {
                 const uint32_t c = cnt[w][d];
                 cnt[w][d] = acc;
                 acc += c;
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         }
     }
     uint32_t total;
-    const uint32_t ex = block_scan_excl(tot2[0] + tot2[1], lw, total);
+    const uint32_t ex = block_scan_excl<kScatterWaves>(tot2[0] + tot2[1], lw, total);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int d = 2 * tid + h;
@@ -172,7 +180,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < kScatterRounds; ++r) {
         if (pos[r] != 0xffffffffu) {
             const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
             const uint32_t lp = dstart[d] + cnt[wave][d] + pos[r];
@@ -185,8 +193,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     __syncthreads();
     const uint32_t cnt_tile = (n - base) < (size_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        const uint32_t idx = (uint32_t)r * kSortThreads + tid;
+    for (int r = 0; r < kScatterRounds; ++r) {
+        const uint32_t idx = (uint32_t)r * kScatterThreads + tid;
         if (idx < cnt_tile) {
             const uint64_t k = sk[idx];
             const uint32_t d = (uint32_t)(k >> shift) & mask;
@@ -219,7 +227,7 @@ hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], c
         e = launch_scan(hist, hist, nb * ((size_t)1 << width), partial, nullptr, 0xffffffffu, nullptr, s);
         if (e != hipSuccess) return e;
         if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p], s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, (const uint64_t*)keys[cur],
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kScatterThreads), 0, s, (const uint64_t*)keys[cur],
                            (const uint32_t*)vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_ptr, shift, width,
                            (const uint32_t*)hist, (uint32_t)nb);
         if (scatter_events && (e = hipEventRecord((hipEvent_t)scatter_events[2 * p + 1], s)) != hipSuccess) return e;

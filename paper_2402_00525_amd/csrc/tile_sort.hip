@@ -249,16 +249,28 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     }
     __syncthreads();
     const uint32_t C = s_C, limit = s_limit;
-    for (uint32_t i0 = rb; i0 < re; i0 += kT) {
-        const uint32_t i = i0 + tid;
-        uint64_t k = 0;
-        bool take = false;
-        if (i < re) {
-            k = keys[i];
-            take = depth_bin(depth_of(k)) < limit;
+    // Selection, four keys per thread in flight (the order of appends does
+    // not matter: the selected entries are sorted next).
+    for (uint32_t i0 = rb; i0 < re; i0 += 4 * kT) {
+        uint64_t k[4];
+        uint32_t v[4];
+        bool take[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kT + tid;
+            k[u] = i < re ? keys[i] : 0ull;
         }
-        const uint32_t slot = wave_append(take, &s_fill);
-        if (take) sk[slot] = ((uint64_t)depth_of(k) << 32) | vals[i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + (uint32_t)u * kT + tid;
+            take[u] = i < re && depth_bin(depth_of(k[u])) < limit;
+            v[u] = take[u] ? vals[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t slot = wave_append(take[u], &s_fill);
+            if (take[u]) sk[slot] = ((uint64_t)depth_of(k[u]) << 32) | v[u];
+        }
     }
     __syncthreads();
     lds_bitonic(sk, C);
