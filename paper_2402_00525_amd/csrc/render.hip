@@ -99,9 +99,9 @@ struct PixelState {
     float T, C0, C1, C2, D;
     int n;
     bool done;
-    uint64_t hk[K + 1];
-    uint32_t hid[K + 1];
-    float ha[K + 1];
+    uint64_t hk[K];
+    uint32_t hid[K];
+    float ha[K];
     int hn;
     // backward only: dL/dC, final colour without background, final transmittance
     float g0, g1, g2, F0, F1, F2, TN;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
     const uint32_t i0 = s.hid[0];
     const float a0 = s.ha[0];
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
+    for (int i = 0; i + 1 < K; ++i) {
         s.hk[i] = s.hk[i + 1];
         s.hid[i] = s.hid[i + 1];
         s.ha[i] = s.ha[i + 1];
@@ -180,14 +180,14 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
     blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
 }
 
-// Insertion into the sorted head (s.hn < K + 1 on entry).
+// Insertion into the sorted head (s.hn < K on entry).
 template <int K, int MODE>
 __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key, uint32_t id, float alpha) {
     int pos = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) pos += (i < s.hn && s.hk[i] < key) ? 1 : 0;
 #pragma unroll
-    for (int i = K; i >= 1; --i) {
+    for (int i = K - 1; i >= 1; --i) {
         if (i > pos && i <= s.hn) {
             s.hk[i] = s.hk[i - 1];
             s.hid[i] = s.hid[i - 1];
@@ -195,7 +195,7 @@ __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key
         }
     }
 #pragma unroll
-    for (int i = 0; i <= K; ++i) {
+    for (int i = 0; i < K; ++i) {
         if (i == pos) {
             s.hk[i] = key;
             s.hid[i] = id;
@@ -425,7 +425,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         h.st.F2 = a.rgb_in[2 * P + p] - h.st.TN * a.bg2;
     }
 #pragma unroll
-    for (int i = 0; i <= K; ++i) {
+    for (int i = 0; i < K; ++i) {
         h.st.hk[i] = kInvalidKey;
         h.st.hid[i] = 0;
         h.st.ha[i] = 0.0f;
@@ -559,7 +559,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 }
             }
 #pragma unroll
-            for (int i = 0; i <= K; ++i)
+            for (int i = 0; i < K; ++i)
                 if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix, acc);
         }
     }
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     st.done = !inside;
     st.hn = 0;
 #pragma unroll
-    for (int i = 0; i <= K; ++i) {
+    for (int i = 0; i < K; ++i) {
         st.hk[i] = kInvalidKey;
         st.hid[i] = 0;
         st.ha[i] = 0.0f;
@@ -810,7 +810,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i <= K; ++i)
+    for (int i = 0; i < K; ++i)
         if (st.hn > 0) head_pop_blend<K, MODE>(a, st, pix, nullptr);
     if (inside) {
         const size_t P = (size_t)cam.W * cam.H;
@@ -857,7 +857,7 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     while (__syncthreads_or(!st.done && more)) {
         const bool active = !st.done && more;
 #pragma unroll
-        for (int i = 0; i <= K; ++i) {
+        for (int i = 0; i < K; ++i) {
             st.hk[i] = kInvalidKey;
             st.hid[i] = 0;
             st.ha[i] = 0.0f;
