@@ -38,7 +38,13 @@ namespace {
 // Kernel modes: forward, forward writing blend-id lists, backward, and
 // forward counting the evaluations of every level (a work model for the
 // render's arithmetic roofline; the counts do not depend on timing).
-enum { kFwd = 0, kFwdDebug = 1, kBwd = 2, kFwdCount = 3 };
+enum { kFwd = 0, kFwdDebug = 1, kBwd = 2, kFwdCount = 3, kFwdPlain = 4 };
+
+// Whether a blend's colour terms are added at the next blend, so that the
+// colour load overlaps the work in between (forward heads of up to 4; the
+// extra registers would cost occupancy elsewhere, and kFwdPlain is the
+// forward without it).
+constexpr bool defer_colour(int K, int MODE) { return MODE != kBwd && MODE != kFwdPlain && K <= 4; }
 // Work counters (RenderArgs::work): cull tests and keyed (t_opt) entries at
 // the 4x4 and 2x2 levels, alpha tests and keyed entries at the pixels, blends.
 enum { kWorkTailTest = 0, kWorkTailKey, kWorkMidTest, kWorkMidKey, kWorkHeadTest, kWorkHeadKey, kWorkBlend, kWorkN };
@@ -106,7 +112,29 @@ struct PixelState {
     // backward only: dL/dC, final colour without background, final transmittance
     float g0, g1, g2, F0, F1, F2, TN;
     float px, py;
+    // forward: the last blend's colour terms, added at the next blend (or
+    // at the end) so that its colour load is in flight meanwhile
+    float4 pe;
+    float pa, pT;
 };
+
+// Adds the pending blend's colour: C += (c alpha) T, exactly as if done at
+// its blend (the sums stay in blend order).  Zero terms while none is pending.
+template <int K, int MODE>
+__device__ __forceinline__ void flush_colour(PixelState<K, MODE>& s) {
+    if (!defer_colour(K, MODE)) return;
+    s.C0 = s.C0 + (s.pe.y * s.pa) * s.pT;
+    s.C1 = s.C1 + (s.pe.z * s.pa) * s.pT;
+    s.C2 = s.C2 + (s.pe.w * s.pa) * s.pT;
+}
+
+template <int K, int MODE>
+__device__ __forceinline__ void init_colour(PixelState<K, MODE>& s) {
+    s.C0 = s.C1 = s.C2 = 0.0f;
+    s.pe = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    s.pa = 0.0f;
+    s.pT = 0.0f;
+}
 
 // Adds the 9 gradient terms of one blend: into the tile's LDS accumulators
 // (slot = rank in the tile list) when the rank has a slot, else to global memory.
@@ -127,9 +155,16 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         return;
     }
     const float4 e = a.sw[3 * id + 2];
-    s.C0 = s.C0 + (e.y * alpha) * s.T;
-    s.C1 = s.C1 + (e.z * alpha) * s.T;
-    s.C2 = s.C2 + (e.w * alpha) * s.T;
+    if (!defer_colour(K, MODE)) {
+        s.C0 = s.C0 + (e.y * alpha) * s.T;
+        s.C1 = s.C1 + (e.z * alpha) * s.T;
+        s.C2 = s.C2 + (e.w * alpha) * s.T;
+    } else {
+        flush_colour(s);
+        s.pe = e;
+        s.pa = alpha;
+        s.pT = s.T;
+    }
     s.D = s.D + (t * alpha) * s.T;
     if (MODE == kFwdDebug) {
         if (s.n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + s.n] = (int32_t)id;
@@ -408,7 +443,8 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     h.dQ = cam_ray(cam, 0.5f * (h.Q0 + h.Q1), 0.5f * (h.Q2 + h.Q3));
     h.dP = cam_ray(cam, (float)h.px, (float)h.py);
     h.st.T = 1.0f;
-    h.st.C0 = h.st.C1 = h.st.C2 = h.st.D = 0.0f;
+    init_colour(h.st);
+    h.st.D = 0.0f;
     h.st.n = 0;
     h.st.done = !h.pix_ok;
     h.st.hn = 0;
@@ -563,6 +599,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix, acc);
         }
     }
+    flush_colour(h.st);
     if (MODE != kBwd && h.pix_ok) {
         const size_t P = (size_t)cam.W * cam.H;
         const size_t p = (size_t)h.pix;
@@ -682,7 +719,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.pre_len = b.pre_len;
         a.tile_flag = b.tile_flag;
         a.flags = b.flags;
-        render_strip<K, kFwd>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
+        render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
     }
 }
 
@@ -777,7 +814,8 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     const float3 d = cam_ray(cam, (float)px, (float)py);
     PixelState<K, MODE> st;
     st.T = 1.0f;
-    st.C0 = st.C1 = st.C2 = st.D = 0.0f;
+    init_colour(st);
+    st.D = 0.0f;
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
@@ -812,6 +850,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
 #pragma unroll
     for (int i = 0; i < K; ++i)
         if (st.hn > 0) head_pop_blend<K, MODE>(a, st, pix, nullptr);
+    flush_colour(st);
     if (inside) {
         const size_t P = (size_t)cam.W * cam.H;
         a.rgb[pix] = st.C0 + st.T * a.bg0;
@@ -848,7 +887,8 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     const float3 d = cam_ray(cam, (float)px, (float)py);
     PixelState<K, MODE> st;
     st.T = 1.0f;
-    st.C0 = st.C1 = st.C2 = st.D = 0.0f;
+    init_colour(st);
+    st.D = 0.0f;
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
@@ -912,6 +952,7 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
             floor_key = st.hk[K - 1] + 1ull;
         }
     }
+    flush_colour(st);
     if (inside) {
         const size_t P = (size_t)cam.W * cam.H;
         a.rgb[pix] = st.C0 + st.T * a.bg0;
