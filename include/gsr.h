@@ -158,8 +158,9 @@ typedef struct gsr_config {
  * particular order inside a tile; the keys of tiles that took the fallback
  * are overwritten), pre_vals uint32[capacity] each tile's sorted ids from its
  * range start (a prefix, or the whole list for a tile that took the
- * fallback), pre_len uint32[tiles] their number, tile_flag uint32[tiles] the
- * entry count of a tile that took the fallback (else 0). */
+ * fallback), pre_len uint32[tiles] their number, tile_flag uint32[3][tiles]:
+ * the entry count of a tile that took the fallback (else 0), then two rows
+ * of per-tile scratch of the render. */
 typedef struct gsr_layout {
     int64_t xy, conic_o, sw, splat, zd, rect, touched, kmask, offsets, dup_hist, grad2d;
     int64_t keys, values, ranges, counters;

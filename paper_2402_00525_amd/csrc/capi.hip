@@ -83,7 +83,7 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
     L->ranges = take(8 * (int64_t)tiles);
     L->counters = take(64);
     L->pre_len = take(4 * (int64_t)tiles);
-    L->tile_flag = take(4 * (int64_t)tiles);
+    L->tile_flag = take(4 * 3 * (int64_t)tiles);  // flags, then the render's per-tile scratch
     const int64_t nb = (int64_t)gsr::sort_blocks((size_t)cap);
     const int64_t sp = (int64_t)std::max({gsr::scan_partial_len((size_t)n), gsr::scan_partial_len((size_t)tiles),
                                           gsr::scan_partial_len((size_t)(gsr::kDupBins * dup_workgroups(n))),
@@ -200,7 +200,7 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
         return order_events ? hipEventRecord((hipEvent_t)order_events[k], s) : hipSuccess;
     };
     if (mode == GSR_MODE_HIER) {
-        if ((e = gsr::launch_fill_u32(b.tile_flag, (size_t)tiles, 0u, s)) != hipSuccess) return e;
+        if ((e = gsr::launch_fill_u32(b.tile_flag, 3 * (size_t)tiles, 0u, s)) != hipSuccess) return e;
         if (sp.tile_passes > 0) {
             if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.group_bits,
                                             sp.dup_buf, &res, s, scatter_events, 32 + gsr::kDupDigitBits)) != hipSuccess)
@@ -441,7 +441,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->ranges = take(8 * tiles);
     L->counters = take(64);
     L->pre_len = take(4 * tiles);
-    L->tile_flag = take(4 * tiles);
+    L->tile_flag = take(4 * 3 * tiles);
     L->flist = take(4 * tiles);
     const int64_t nbt = (int64_t)gsr::sort_blocks((size_t)tiles);
     L->tkeys[0] = take(8 * tiles);

@@ -661,6 +661,38 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     }
 }
 
+// The forward with one wavefront per workgroup: a strip's queues are its
+// own, so a finished wavefront frees its slot without waiting for the other
+// strips of its tile.  Workgroup b renders strip (b mod 32) / 8 of tile
+// 8 (b / 32) + b mod 8, so that the four strips of a tile run on one XCD
+// (workgroups are dealt to the eight XCDs round robin) and share its L2.
+// The entries a tile consumed (the most any of its strips read) are added
+// to counters[1] by the tile's last strip, through two per-tile words after
+// the flags (zeroed with them); the strips of a tile share an XCD, so their
+// atomics meet in one L2.
+template <int K, int MODE>
+__global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
+    __shared__ WaveQueues s_q;
+    const uint32_t b = blockIdx.x, g = b / 32u, r = b % 32u;
+    const int strip = (int)(r / 8u), tile = (int)(g * 8u + r % 8u);
+    const int n_tiles = a.cam.tiles_x * a.cam.tiles_y;
+    if (tile >= n_tiles) return;
+    const uint32_t c = render_strip<K, MODE>(a, tile, tile, strip, s_q, nullptr);
+    if (threadIdx.x == 0) {
+        uint32_t* used = a.tile_flag + n_tiles;
+        uint32_t* done = used + n_tiles;
+        // The maximum is in place before this strip counts itself done: the
+        // count waits for the returned value (no fence, which would write
+        // back the L2).
+        const uint32_t prev = atomicMax(&used[tile], c);
+        asm volatile("" : : "v"(prev) : "memory");
+        if ((atomicAdd(&done[tile], 1u) & 3u) == 3u) {
+            const uint32_t m = atomicExch(&used[tile], 0u);
+            if (m) atomicAdd(a.counters + 1, m);
+        }
+    }
+}
+
 // Persistent form over many views: every wavefront pulls (tile, strip) work
 // items from one atomic queue until the queue is empty; tiles are taken in
 // the order given by `order` (largest lists first when cost-ordered), so
@@ -985,9 +1017,9 @@ hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
     } else if (a.grad2d)
         hipLaunchKernelGGL((k_render_hier<K, kBwd>), dim3(tiles), dim3(256), 0, s, a);
     else if (a.blend_ids)
-        hipLaunchKernelGGL((k_render_hier<K, kFwdDebug>), dim3(tiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_render_hier1<K, kFwdDebug>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_render_hier<K, kFwd>), dim3(tiles), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_render_hier1<K, kFwd>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
