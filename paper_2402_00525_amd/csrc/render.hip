@@ -51,7 +51,7 @@ enum { kWorkTailTest = 0, kWorkTailKey, kWorkMidTest, kWorkMidKey, kWorkHeadTest
 
 constexpr int kBatch = 32;
 // Backward: per-tile LDS accumulators for the first kAccSlots list entries.
-constexpr int kAccSlots = 256;
+constexpr int kAccSlots = 1024;
 constexpr int kTailCap = 64;
 constexpr int kPop = 16;
 constexpr int kMidCap = 8;
@@ -180,8 +180,10 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         add_grad(a, acc, rank, id, 6, s.g0 * w);
         add_grad(a, acc, rank, id, 7, s.g1 * w);
         add_grad(a, acc, rank, id, 8, s.g2 * w);
-        const float2 m = a.xy[id];
-        const float4 c = a.co[id];
+        // 2D mean, conic and opacity from the packed splat (one cache line)
+        const float4 p0 = a.pk[4 * (size_t)id], p1 = a.pk[4 * (size_t)id + 1];
+        const float2 m = make_float2(p0.x, p0.y);
+        const float4 c = make_float4(p0.z, p0.w, p1.x, p1.y);
         const float dx = m.x - s.px, dy = m.y - s.py;
         const float pw = -0.5f * ((c.x * dx) * dx + (c.z * dy) * dy) - (c.y * dx) * dy;
         const float G = exp_cw(pw);
