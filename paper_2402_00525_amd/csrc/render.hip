@@ -116,6 +116,11 @@ struct PixelState {
     // at the end) so that its colour load is in flight meanwhile
     float4 pe;
     float pa, pT;
+    // backward: the last blend's gradient terms, added when the pixel's quad
+    // next meets (quad_flush), so that equal ranks of a quad add once
+    float gv[9];
+    uint32_t grank, gid;
+    bool gpend;
 };
 
 // Adds the pending blend's colour: C += (c alpha) T, exactly as if done at
@@ -136,6 +141,17 @@ __device__ __forceinline__ void init_colour(PixelState<K, MODE>& s) {
     s.pT = 0.0f;
 }
 
+template <int M>
+__device__ __forceinline__ float quad_bcast_f(float v) {
+    constexpr int ctrl = M | (M << 2) | (M << 4) | (M << 6);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xf, 0xf, false));
+}
+template <int M>
+__device__ __forceinline__ uint32_t quad_bcast_u(uint32_t v) {
+    constexpr int ctrl = M | (M << 2) | (M << 4) | (M << 6);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
+}
+
 // Adds the 9 gradient terms of one blend: into the tile's LDS accumulators
 // (slot = rank in the tile list) when the rank has a slot, else to global memory.
 __device__ __forceinline__ void add_grad(const RenderArgs& a, float* acc, uint32_t rank, uint32_t id, int c, float v) {
@@ -143,6 +159,39 @@ __device__ __forceinline__ void add_grad(const RenderArgs& a, float* acc, uint32
         atomicAdd(acc + c * kAccSlots + rank, v);
     else
         atomicAdd(a.grad2d + 9 * (size_t)id + c, v);
+}
+
+// Adds the pending gradient terms of the four lanes of this quad (all four
+// must be active): lanes with the same list rank are summed by DPP and added
+// once by the lowest of them, so a quad blending one Gaussian costs one set
+// of atomics instead of four.
+template <int K, int MODE>
+__device__ __forceinline__ void quad_flush(const RenderArgs& a, PixelState<K, MODE>& s, float* acc) {
+    if (MODE != kBwd) return;
+    if (__ballot(s.gpend) == 0ull) return;
+    const uint32_t r = s.gpend ? s.grank : 0xffffffffu;
+    const uint32_t rq[4] = {quad_bcast_u<0>(r), quad_bcast_u<1>(r), quad_bcast_u<2>(r), quad_bcast_u<3>(r)};
+    const int pl = (int)(threadIdx.x & 3u);
+    bool leader = s.gpend;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) leader = leader && !(m < pl && rq[m] == r);
+    float sum[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const float v0 = quad_bcast_f<0>(s.gv[c]), v1 = quad_bcast_f<1>(s.gv[c]);
+        const float v2 = quad_bcast_f<2>(s.gv[c]), v3 = quad_bcast_f<3>(s.gv[c]);
+        float t = rq[0] == r ? v0 : 0.0f;
+        t = t + (rq[1] == r ? v1 : 0.0f);
+        t = t + (rq[2] == r ? v2 : 0.0f);
+        t = t + (rq[3] == r ? v3 : 0.0f);
+        sum[c] = t;
+    }
+    if (leader) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c)
+            if (sum[c] != 0.0f) add_grad(a, acc, r, s.gid, c, sum[c]);
+    }
+    s.gpend = false;
 }
 
 template <int K, int MODE>
@@ -177,9 +226,14 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         const float ga = s.g0 * (e.y * s.T - ((s.F0 - s.C0) + s.TN * a.bg0) * inv) +
                          s.g1 * (e.z * s.T - ((s.F1 - s.C1) + s.TN * a.bg1) * inv) +
                          s.g2 * (e.w * s.T - ((s.F2 - s.C2) + s.TN * a.bg2) * inv);
-        add_grad(a, acc, rank, id, 6, s.g0 * w);
-        add_grad(a, acc, rank, id, 7, s.g1 * w);
-        add_grad(a, acc, rank, id, 8, s.g2 * w);
+        if (s.gpend)  // not flushed since the last blend: add those terms directly
+            for (int c = 0; c < 9; ++c) add_grad(a, acc, s.grank, s.gid, c, s.gv[c]);
+        s.gpend = true;
+        s.grank = rank;
+        s.gid = id;
+        s.gv[6] = s.g0 * w;
+        s.gv[7] = s.g1 * w;
+        s.gv[8] = s.g2 * w;
         // 2D mean, conic and opacity from the packed splat (one cache line)
         const float4 p0 = a.pk[4 * (size_t)id], p1 = a.pk[4 * (size_t)id + 1];
         const float2 m = make_float2(p0.x, p0.y);
@@ -187,15 +241,14 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         const float dx = m.x - s.px, dy = m.y - s.py;
         const float pw = -0.5f * ((c.x * dx) * dx + (c.z * dy) * dy) - (c.y * dx) * dy;
         const float G = exp_cw(pw);
-        if (c.w * G < kAlphaMax) {
-            const float gp = ga * alpha;  // d alpha / d power = o G
-            add_grad(a, acc, rank, id, 0, gp * (-c.x * dx - c.y * dy));
-            add_grad(a, acc, rank, id, 1, gp * (-c.z * dy - c.y * dx));
-            add_grad(a, acc, rank, id, 2, gp * (-0.5f * dx * dx));
-            add_grad(a, acc, rank, id, 3, gp * (-dx * dy));
-            add_grad(a, acc, rank, id, 4, gp * (-0.5f * dy * dy));
-            add_grad(a, acc, rank, id, 5, ga * G);
-        }
+        const bool live = c.w * G < kAlphaMax;  // alpha not clamped: it depends on the Gaussian
+        const float gp = ga * alpha;            // d alpha / d power = o G
+        s.gv[0] = live ? gp * (-c.x * dx - c.y * dy) : 0.0f;
+        s.gv[1] = live ? gp * (-c.z * dy - c.y * dx) : 0.0f;
+        s.gv[2] = live ? gp * (-0.5f * dx * dx) : 0.0f;
+        s.gv[3] = live ? gp * (-dx * dy) : 0.0f;
+        s.gv[4] = live ? gp * (-0.5f * dy * dy) : 0.0f;
+        s.gv[5] = live ? ga * G : 0.0f;
     }
     s.n += 1;
     s.T = Tn;
@@ -297,7 +350,9 @@ struct HierCtx {
 
     // Head level: the c entries of this quad's mid buffer from position ms0.
     __device__ void push_head(int c, int ms0) {
-        if (st.done || !pix_ok) return;
+        // The backward keeps the whole quad in the loop: its gradient terms
+        // are combined across the quad after every entry.
+        if (MODE != kBwd && (st.done || !pix_ok)) return;
         uint32_t idn = q.mid[gq][ms0];
         idn = idn < a.n ? idn : 0u;
         Splat gn = load_packed(a.pk, idn);  // the next entry's splat, loaded one entry ahead
@@ -310,7 +365,7 @@ struct HierCtx {
                 idn = idn < a.n ? idn : 0u;
                 gn = load_packed(a.pk, idn);
             }
-            if (!st.done) {
+            if (!st.done && pix_ok) {
                 float alpha;
                 if (MODE == kFwdCount) ++work[kWorkHeadTest];
                 if (pixel_alpha(g, (float)px, (float)py, alpha)) {
@@ -320,6 +375,7 @@ struct HierCtx {
                                        acc);
                 }
             }
+            quad_flush(a, st, acc);
         }
     }
 
@@ -447,6 +503,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     h.st.T = 1.0f;
     init_colour(h.st);
     h.st.D = 0.0f;
+    h.st.gpend = false;
     h.st.n = 0;
     h.st.done = !h.pix_ok;
     h.st.hn = 0;
@@ -597,8 +654,10 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 }
             }
 #pragma unroll
-            for (int i = 0; i < K; ++i)
+            for (int i = 0; i < K; ++i) {
                 if (h.st.hn > 0) head_pop_blend<K, MODE>(a, h.st, h.pix, acc);
+                quad_flush(a, h.st, acc);
+            }
         }
     }
     flush_colour(h.st);
