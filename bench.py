@@ -46,7 +46,7 @@ KERNEL_SOURCES = {
     "k_duplicate": ("frame.hip", "gsr_device.h", "gsr_internal.h"),
     "k_radix_scatter": ("sort.hip", "gsr_internal.h"),
     "k_tile_prefix": ("tile_sort.hip", "gsr_internal.h"),
-    "k_render_hier": ("render.hip", "gsr_device.h", "gsr_internal.h"),
+    "k_render_hier1": ("render.hip", "gsr_device.h", "gsr_internal.h"),
 }
 PROFILE = os.path.join(ROOT, "profiles", "frame_3m_1080p_hier.md")
 
@@ -406,14 +406,14 @@ def main():
         "k_duplicate": (h["stages"][1], h["stages"][1], dup_bytes),
         "k_radix_scatter": (h["scatter"] * h["passes"], h["scatter"], 24.0 * h["E"]),
         "k_tile_prefix": (h["order_ms"], h["order_ms"], 16.0 * h["E"]),
-        "k_render_hier": (h["render_ms"], h["render_ms"], 80.0 * h["consumed"] + 24.0 * P),
+        "k_render_hier1": (h["render_ms"], h["render_ms"], 80.0 * h["consumed"] + 24.0 * P),
     }
     kernels = {k: {"ms_per_frame": round(v[0], 4), "GBs": round(v[2] / (v[1] * 1e-3) / 1e9, 1)}
                for k, v in cands.items() if v[1] > 0}
-    kernels["k_render_hier"]["TFLOPs"] = round(render_flops / (h["render_ms"] * 1e-3) / 1e12, 3)
+    kernels["k_render_hier1"]["TFLOPs"] = round(render_flops / (h["render_ms"] * 1e-3) / 1e12, 3)
     dom = max(cands, key=lambda k: cands[k][0])
     per_frame, dur, nbytes = cands[dom]
-    if dom == "k_render_hier":
+    if dom == "k_render_hier1":
         # On-chip bound (LDS queues, VALU): the roofline is the vector ALU's.
         achieved = render_flops / (dur * 1e-3) / 1e12
         roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS,
