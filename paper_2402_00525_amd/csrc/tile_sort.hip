@@ -216,13 +216,12 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     __syncthreads();
     {
         uint32_t i = rb + tid;
-        for (; i + 3 * kT < re; i += 4 * kT) {
-            const uint32_t d0 = depth_of(keys[i]), d1 = depth_of(keys[i + kT]);
-            const uint32_t d2 = depth_of(keys[i + 2 * kT]), d3 = depth_of(keys[i + 3 * kT]);
-            atomicAdd(&hist[depth_bin(d0)], 1u);
-            atomicAdd(&hist[depth_bin(d1)], 1u);
-            atomicAdd(&hist[depth_bin(d2)], 1u);
-            atomicAdd(&hist[depth_bin(d3)], 1u);
+        for (; i + 7 * kT < re; i += 8 * kT) {
+            uint32_t d[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) d[u] = depth_of(keys[i + u * kT]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) atomicAdd(&hist[depth_bin(d[u])], 1u);
         }
         for (; i < re; i += kT) atomicAdd(&hist[depth_bin(depth_of(keys[i]))], 1u);
     }
@@ -249,25 +248,25 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     }
     __syncthreads();
     const uint32_t C = s_C, limit = s_limit;
-    // Selection, four keys per thread in flight (the order of appends does
+    // Selection, eight keys per thread in flight (the order of appends does
     // not matter: the selected entries are sorted next).
-    for (uint32_t i0 = rb; i0 < re; i0 += 4 * kT) {
-        uint64_t k[4];
-        uint32_t v[4];
-        bool take[4];
+    for (uint32_t i0 = rb; i0 < re; i0 += 8 * kT) {
+        uint64_t k[8];
+        uint32_t v[8];
+        bool take[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint32_t i = i0 + (uint32_t)u * kT + tid;
             k[u] = i < re ? keys[i] : 0ull;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint32_t i = i0 + (uint32_t)u * kT + tid;
             take[u] = i < re && depth_bin(depth_of(k[u])) < limit;
             v[u] = take[u] ? vals[i] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const uint32_t slot = wave_append(take[u], &s_fill);
             if (take[u]) sk[slot] = ((uint64_t)depth_of(k[u]) << 32) | v[u];
         }
