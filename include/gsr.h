@@ -211,6 +211,16 @@ int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_co
                      size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                      int32_t* blend_ids, int32_t max_k, int32_t* status_dev, gsr_stream_t stream);
 
+/* As gsr_render, and also writes each pixel's sort error (Sec. 3.3; the
+ * measure of Table sortcost) to sort_error [H,W] (float32, device): over the
+ * Gaussians the pixel blended, in blend order, the sum of t_k - t_{k+1} over
+ * consecutive pairs with t_k > t_{k+1}, where t is t_opt along the pixel's
+ * ray (Eq. dopt), in every mode (0 for an exact order).  Errors as gsr_render;
+ * GSR_EINVAL when sort_error is NULL. */
+int gsr_render_sort_error(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                          size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
+                          float* sort_error, int32_t* status_dev, gsr_stream_t stream);
+
 /* Backward of gsr_render (Sec. 3.5), for the hierarchical order.  Given
  * dL_drgb [3,H,W] and the forward call's rgb and T_final, re-runs the same
  * per-pixel resorting front to back (nothing per pixel is stored by the

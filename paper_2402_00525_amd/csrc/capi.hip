@@ -236,7 +236,7 @@ void set_prefix_lists(gsr::RenderArgs& ra, const gsr::FrameBufs& b, int list_mod
 int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                 float* rgb, float* depth, int32_t* count, float* T_final, int32_t* blend_ids, int32_t max_k,
                 int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events,
-                uint64_t* work = nullptr) {
+                uint64_t* work = nullptr, float* delta = nullptr) {
     int rc = check_scene(scene);
     if (rc) return rc;
     if ((rc = check_camera(cam))) return rc;
@@ -318,6 +318,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     ra.T = T_final;
     ra.blend_ids = blend_ids;
     ra.max_k = blend_ids ? max_k : 0;
+    ra.delta = delta;
     ra.bg0 = cfg->bg[0];
     ra.bg1 = cfg->bg[1];
     ra.bg2 = cfg->bg[2];
@@ -909,6 +910,14 @@ int gsr_sort_passes(int32_t W, int32_t H) {
 int gsr_group_passes(int32_t W, int32_t H) {
     if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
     return sort_plan(tiles_of(W, H), GSR_MODE_HIER).tile_passes;
+}
+
+int gsr_render_sort_error(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
+                          size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final, float* sort_error,
+                          int32_t* status_dev, gsr_stream_t stream) {
+    if (!sort_error) return fail(GSR_EINVAL, "sort_error is NULL");
+    return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
+                       nullptr, 0, nullptr, sort_error);
 }
 
 int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,

@@ -147,6 +147,7 @@ struct RenderArgs {
     float* T;
     int32_t* blend_ids;
     int max_k;
+    float* delta;  // debug renders: each pixel's sort error (Sec. 3.3) [H,W], or null
     float bg0, bg1, bg2;
     // backward only (grad2d != nullptr): dL/d rgb [3,H,W], the forward image and
     // transmittance, and the per-Gaussian 2D gradients [N][9] =

@@ -121,6 +121,8 @@ struct PixelState {
     float gv[9];
     uint32_t grank, gid;
     bool gpend;
+    // debug: sort error so far and the last blended depth
+    float dl, tl;
 };
 
 // Adds the pending blend's colour: C += (c alpha) T, exactly as if done at
@@ -217,6 +219,10 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
     s.D = s.D + (t * alpha) * s.T;
     if (MODE == kFwdDebug) {
         if (s.n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + s.n] = (int32_t)id;
+        // sort error (Sec. 3.3): consecutive blends out of order add their
+        // difference in t_opt
+        if (s.n > 0 && s.tl > t) s.dl = s.dl + (s.tl - t);
+        s.tl = t;
     }
     if (MODE == kBwd) {
         // Sec. 3.5, front to back: everything behind this Gaussian contributes
@@ -504,6 +510,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     init_colour(h.st);
     h.st.D = 0.0f;
     h.st.gpend = false;
+    h.st.dl = h.st.tl = 0.0f;
     h.st.n = 0;
     h.st.done = !h.pix_ok;
     h.st.hn = 0;
@@ -670,8 +677,10 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         a.depth[p] = h.st.D;
         a.count[p] = h.st.n;
         a.T[p] = h.st.T;
-        if (MODE == kFwdDebug)
+        if (MODE == kFwdDebug) {
             for (int k = h.st.n; k < a.max_k; ++k) a.blend_ids[p * a.max_k + k] = -1;
+            if (a.delta) a.delta[p] = h.st.dl;
+        }
     }
     if (MODE == kFwdCount) {
         h.work[kWorkBlend] = h.pix_ok ? (uint32_t)h.st.n : 0u;
@@ -800,6 +809,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
         a.T = vd.T;
         a.blend_ids = nullptr;
         a.max_k = 0;
+        a.delta = nullptr;
         a.bg0 = b.bg0;
         a.bg1 = b.bg1;
         a.bg2 = b.bg2;
@@ -833,6 +843,9 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
     int n = 0;
     bool done = !inside;
     uint32_t consumed = 0;
+    // debug: sort error along the pixel ray (the blend order is the list's)
+    float dl = 0.0f, tl = 0.0f;
+    const float3 dP = DEBUG ? cam_ray(cam, (float)px, (float)py) : make_float3(0.0f, 0.0f, 0.0f);
     for (uint32_t start = begin; start < end; start += 256) {
         if (__syncthreads_count(done ? 1 : 0) == 256) break;
         const uint32_t idx = start + threadIdx.x;
@@ -871,6 +884,11 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
             C2 = C2 + (cd.z * alpha) * T;
             D = D + (cd.w * alpha) * T;
             if (DEBUG && n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + n] = (int32_t)s_id[k];
+            if (DEBUG && a.delta) {
+                const float t = t_opt(load_packed(a.pk, s_id[k]), dP);
+                if (n > 0 && tl > t) dl = dl + (tl - t);
+                tl = t;
+            }
             n += 1;
             T = Tn;
         }
@@ -884,8 +902,10 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
         a.depth[pix] = D;
         a.count[pix] = n;
         a.T[pix] = T;
-        if (DEBUG)
+        if (DEBUG) {
             for (int k = n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+            if (a.delta) a.delta[pix] = dl;
+        }
     }
     if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
 }
@@ -909,6 +929,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     st.T = 1.0f;
     init_colour(st);
     st.D = 0.0f;
+    st.dl = st.tl = 0.0f;
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
@@ -952,8 +973,10 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
         a.depth[pix] = st.D;
         a.count[pix] = st.n;
         a.T[pix] = st.T;
-        if (MODE == kFwdDebug)
+        if (MODE == kFwdDebug) {
             for (int k = st.n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+            if (a.delta) a.delta[pix] = st.dl;
+        }
     }
     if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
 }
@@ -982,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     st.T = 1.0f;
     init_colour(st);
     st.D = 0.0f;
+    st.dl = st.tl = 0.0f;
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
@@ -1054,15 +1078,17 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
         a.depth[pix] = st.D;
         a.count[pix] = st.n;
         a.T[pix] = st.T;
-        if (MODE == kFwdDebug)
+        if (MODE == kFwdDebug) {
             for (int k = st.n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
+            if (a.delta) a.delta[pix] = st.dl;
+        }
     }
 }
 
 template <int K>
 hipError_t launch_window_k(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
-    if (a.blend_ids)
+    if (a.blend_ids || a.delta)
         hipLaunchKernelGGL((k_render_window<K, kFwdDebug>), dim3(tiles), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((k_render_window<K, kFwd>), dim3(tiles), dim3(256), 0, s, a);
@@ -1077,7 +1103,7 @@ hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((k_render_hier<4, kFwdCount>), dim3(tiles), dim3(256), 0, s, a);
     } else if (a.grad2d)
         hipLaunchKernelGGL((k_render_hier<K, kBwd>), dim3(tiles), dim3(256), 0, s, a);
-    else if (a.blend_ids)
+    else if (a.blend_ids || a.delta)
         hipLaunchKernelGGL((k_render_hier1<K, kFwdDebug>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
     else
         hipLaunchKernelGGL((k_render_hier1<K, kFwd>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
@@ -1151,7 +1177,7 @@ hipError_t launch_render_window(const RenderArgs& a, int head, hipStream_t s) {
 
 hipError_t launch_render_full(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
-    if (a.blend_ids)
+    if (a.blend_ids || a.delta)
         hipLaunchKernelGGL(k_render_full<kFwdDebug>, dim3(tiles), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_render_full<kFwd>, dim3(tiles), dim3(256), 0, s, a);
@@ -1160,7 +1186,7 @@ hipError_t launch_render_full(const RenderArgs& a, hipStream_t s) {
 
 hipError_t launch_render_global(const RenderArgs& a, hipStream_t s) {
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
-    if (a.blend_ids)
+    if (a.blend_ids || a.delta)
         hipLaunchKernelGGL(k_render_global<true>, dim3(tiles), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_render_global<false>, dim3(tiles), dim3(256), 0, s, a);

@@ -57,7 +57,8 @@ class CLayout(C.Structure):
 _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
-           "gsr_render", "gsr_render_debug", "gsr_render_backward", "gsr_render_staged", "gsr_render_work",
+           "gsr_render", "gsr_render_debug", "gsr_render_sort_error", "gsr_render_backward", "gsr_render_staged",
+           "gsr_render_work",
            "gsr_sort_passes", "gsr_group_passes",
            "gsr_probe_math",
            "gsr_last_error", "gsr_version")
@@ -84,6 +85,9 @@ def lib():
         L.gsr_render_debug.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                        C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int32, C.c_void_p, C.c_void_p]
+        L.gsr_render_sort_error.restype = C.c_int
+        L.gsr_render_sort_error.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
+                                            C.c_size_t] + [C.c_void_p] * 7
         L.gsr_render_backward.restype = C.c_int
         L.gsr_render_backward.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                           C.c_size_t] + [C.c_void_p] * 9
@@ -256,6 +260,24 @@ class Renderer:
         if int(self.status.item()) != 0:
             raise GsrError(GSR_ECAPACITY, "tile entries overflowed the workspace")
         return out, dict(zip(self.WORK_NAMES, work.cpu().tolist()))
+
+    def render_sort_error(self, scene: DeviceScene, cam, cfg: CConfig | None = None):
+        """Render once with each pixel's sort error (gsr_render_sort_error);
+        returns (frame, sort_error [H,W] float32 tensor).  Synchronises."""
+        cfg = cfg or config()
+        out = Frame(cam.H, cam.W, self.device)
+        delta = torch.empty((cam.H, cam.W), dtype=torch.float32, device=self.device)
+        if self.ws is None:
+            self.plan(scene.n, cam.W, cam.H, self.entries_hint)
+        sc, cc = scene.c_struct(), camera(cam)
+        self.status.zero_()
+        _check(lib().gsr_render_sort_error(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(self.ws), self.ws.numel(),
+                                           _ptr(out.rgb), _ptr(out.depth), _ptr(out.count), _ptr(out.T),
+                                           _ptr(delta), _ptr(self.status), _stream()))
+        torch.cuda.synchronize()
+        if int(self.status.item()) != 0:
+            raise GsrError(GSR_ECAPACITY, "tile entries overflowed the workspace")
+        return out, delta
 
     def render(self, scene: DeviceScene, cam, cfg: CConfig | None = None, max_k: int = 0) -> Frame:
         cfg = cfg or config()

@@ -151,6 +151,29 @@ def test_window_mode_bit_exact(K):
     np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
 
 
+@pytest.mark.parametrize("mode,K", [(oracle.MODE_HIER, 4), (oracle.MODE_HIER, 1), (oracle.MODE_GLOBAL, 4),
+                                    (oracle.MODE_WINDOW, 4), (oracle.MODE_WINDOW, 16), (oracle.MODE_FULL, 4)])
+def test_sort_error_bit_exact(mode, K):
+    """Per-pixel sort error (Sec. 3.3, Table sortcost) through
+    gsr_render_sort_error equals the oracle's, in every mode; zero for the
+    full per-pixel sort."""
+    from paper_2402_00525_amd import gsr
+    sc = synth.subsample(synth.mixture_scene(100_000, seed=1), 8000)
+    cam = synth.orbit_camera(320, 180, view=3)
+    say("case: sort error mode", mode, "K", K)
+    o = oracle.frame(sc, cam, mode=mode, head=K)
+    ds = gsr.DeviceScene.from_host(sc)
+    r = gsr.Renderer(entries_hint=1 << 18)
+    out, delta = r.render_sort_error(ds, cam, gsr.config(mode=mode, head=K))
+    d = delta.cpu().numpy()
+    np.testing.assert_array_equal(out.count.cpu().numpy(), o.count)
+    np.testing.assert_array_equal(d.view(np.uint32), o.delta.view(np.uint32))
+    if mode == oracle.MODE_FULL:
+        assert d.max() == 0.0
+    else:
+        assert d.max() > 0.0
+
+
 def test_window_mode_mixture_1080p():
     sc = synth.subsample(synth.mixture_scene(200_000, seed=1), 20_000)
     cam = synth.orbit_camera(1920, 1080, view=21)
