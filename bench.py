@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the sweep of the other renderers (resort windows, head sizes, ablations, "
                          "load-balancing thresholds, full per-pixel sort)")
+    ap.add_argument("--no-sort-error", action="store_true",
+                    help="skip the per-ray sort error of every renderer (two orbit views)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -187,6 +189,33 @@ def mode_sweep(ds, cams, n, sort_prefix):
         ms = time_simple(r, ds, cams, cfg, len(cams), 2)
         res[name] = {"ms_per_frame": round(ms, 4), "entries_max": int(emax)}
         log("mode %s: %.3f ms/frame (entries max %d)" % (name, ms, emax))
+        del r
+        torch.cuda.empty_cache()
+    return res
+
+
+def sort_errors(ds, cams, n):
+    """Per-ray sort error (Sec. 3.3, the measure of Table sortcost) of every
+    renderer on the given views: the maximum over pixels and the mean over
+    pixels of each pixel's sum of out-of-order t_opt differences between
+    consecutive blends (0 for the full per-pixel sort)."""
+    import torch
+    from paper_2402_00525_amd import gsr
+    cases = [("global_3dgs", dict(mode=gsr.MODE_GLOBAL))]
+    cases += [("window_K%d" % k, dict(mode=gsr.MODE_WINDOW, head=k)) for k in (4, 8, 16, 24)]
+    cases += [("hier_K%d" % k, dict(mode=gsr.MODE_HIER, head=k)) for k in (4, 8, 16, 24)]
+    cases += [("full_sort", dict(mode=gsr.MODE_FULL))]
+    res = {}
+    for name, kw in cases:
+        r = gsr.Renderer(entries_hint=60 * n)
+        dmax, dsum, pix = 0.0, 0.0, 0
+        for cam in cams:
+            _, d = r.render_sort_error(ds, cam, gsr.config(**kw))
+            dmax = max(dmax, float(d.max()))
+            dsum += float(d.double().sum())
+            pix += d.numel()
+        res[name] = {"delta_max": round(dmax, 4), "delta_avg": round(dsum / pix, 5)}
+        log("sort error %s: %s" % (name, res[name]))
         del r
         torch.cuda.empty_cache()
     return res
@@ -451,6 +480,10 @@ def main():
         log("mode sweep ...")
         line["modes"] = {"views": list(range(0, len(cams), 6)),
                          "results": mode_sweep(ds, cams[::6], n, args.sort_prefix)}
+    if not args.no_sort_error:
+        log("sort error ...")
+        sel = [0, len(cams) // 2] if len(cams) > 1 else [0]
+        line["sort_error"] = {"views": sel, "results": sort_errors(ds, [cams[v] for v in sel], n)}
     if not args.no_batch and args.workload != "small":
         log("batched ...")
         line["batched"] = batched(5)
