@@ -102,6 +102,22 @@ def test_mixture_scene_1080p_subsample_bit_exact():
     np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
 
 
+def test_two_grouping_passes_4k_bit_exact():
+    """3840x2160 has 32400 tiles: after the 5 bits of grouped duplication the
+    remaining 10 tile bits take two radix passes."""
+    from paper_2402_00525_amd import gsr
+    assert gsr.lib().gsr_group_passes(3840, 2160) == 2
+    sc = synth.subsample(synth.mixture_scene(100_000, seed=5), 6000)
+    cam = synth.orbit_camera(3840, 2160, view=12)
+    say("case: 6k mixture at 3840x2160 (two grouping passes)")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=8)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=8)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    assert_images_close(g, o, TOL)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+
+
 @pytest.mark.parametrize("prefix", [1, 16, 100, 4096])
 def test_prefix_fallback_bit_exact(prefix):
     """Short sorted prefixes force many tiles through the fallback sort; the
