@@ -400,7 +400,7 @@ def main():
             r.render(ds, cams[v], cfg)
             E_views.append(r.counter(n, cams[v], 0))
             cons_views.append(r.counter(n, cams[v], 1))
-            fb_views.append(r.counter(n, cams[v], 5) if mode == gsr.MODE_HIER else 0)
+            fb_views.append(r.counter(n, cams[v], 5))
         results[label] = dict(ms=ms, stages=[mean([s[k] for s in stages]) for k in range(4)],
                               scatter=mean([mean(s) for s in scatter]) if passes else 0.0, E=mean(E_views),
                               consumed=mean(cons_views), fallback=mean(fb_views), emax=emax, passes=passes,

@@ -127,7 +127,8 @@ typedef struct gsr_config {
     float bg[3];
     uint32_t flags;      /* GSR_ABLATE_* bits (GSR_MODE_HIER only), else 0 */
     int32_t sort_prefix; /* speed only: entries per tile sorted up front (1..4096;
-                            0 = 1024); see gsr_render */
+                            0 = 4096 for GSR_MODE_GLOBAL and GSR_MODE_WINDOW,
+                            else 1024); see gsr_render */
 } gsr_config;
 
 /* Byte offsets of the regions of a workspace, for inspection and debugging.
@@ -153,8 +154,8 @@ typedef struct gsr_config {
  * clamping to the capacity (saturated at 2^32 - 1), unused, entries of the tiles that took
  * the fallback, number of such tiles, unused);
  * grad2d float[N][9] = backward scratch (d mean_2, d conic, d opacity, d rgb).
- * GSR_MODE_GLOBAL: keys/values are fully sorted.
- * GSR_MODE_HIER: keys/values hold the entries grouped by tile (in no
+ * Every mode (GSR_MODE_GLOBAL and GSR_MODE_WINDOW with view-depth keys):
+ * keys/values hold the entries grouped by tile (in no
  * particular order inside a tile; the keys of tiles that took the fallback
  * are overwritten), pre_vals uint32[capacity] each tile's sorted ids from its
  * range start (a prefix, or the whole list for a tile that took the
@@ -187,7 +188,7 @@ int gsr_check_config(const gsr_config* cfg /* host */);
 
 /* Render one frame: preprocess, count and duplicate (tile, depth) entries,
  * sort them, find tile ranges, and blend every pixel front to back with
- * early termination (Eq. volume_desc).  In GSR_MODE_HIER the entries are
+ * early termination (Eq. volume_desc).  In every mode the entries are
  * grouped by tile, each tile's first (at most sort_prefix) entries in (depth,
  * Gaussian id) order are selected and sorted, and a tile whose pixels are
  * still unfinished when its prefix runs out has its whole list sorted and is
@@ -241,16 +242,16 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 /* As gsr_render, and records caller-created HIP events (hipEvent_t, passed
  * as void*) on the stream at the stage boundaries of the paper's per-stage
  * timing (Sec. 4.3): events[0] before Preprocess, [1] after Preprocess, [2]
- * after Duplicate (prefix sum + key emission), [3] after Sort (radix sort,
- * tile ranges and, in GSR_MODE_HIER, the per-tile sorted prefixes), [4] after
- * Render (in GSR_MODE_HIER including the fallback sort of flagged tiles and
- * their second render).  With n_events >= 5 + 2 * passes (passes =
- * gsr_group_passes(W, H) in GSR_MODE_HIER, gsr_sort_passes(W, H) in
- * GSR_MODE_GLOBAL), events[5 + 2p] and [6 + 2p] also bracket the scatter
+ * after Duplicate (prefix sum + key emission), [3] after Sort (grouping by
+ * tile, tile ranges and the per-tile sorted prefixes), [4] after Render
+ * (including the fallback sort of flagged tiles and their second render).
+ * With n_events >= 5 + 2 * passes (passes = gsr_group_passes(W, H) in
+ * GSR_MODE_HIER and GSR_MODE_FULL, gsr_sort_passes(W, H) in GSR_MODE_GLOBAL
+ * and GSR_MODE_WINDOW), events[5 + 2p] and [6 + 2p] also bracket the scatter
  * launch of radix pass p; with n_events >= 9 + 2 * passes, events[5 + 2 passes]
- * and [6 + 2 passes] bracket the per-tile ordering launch (the tile prefixes in
- * GSR_MODE_HIER, the tile ranges otherwise) and [7 + 2 passes] and
- * [8 + 2 passes] the first render launch.  The caller owns the events. */
+ * and [6 + 2 passes] bracket the per-tile ordering launch (the tile prefixes)
+ * and [7 + 2 passes] and [8 + 2 passes] the first render launch.  The caller
+ * owns the events. */
 int gsr_render_staged(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                       size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                       int32_t* status_dev, gsr_stream_t stream, void* const* events, int32_t n_events);
@@ -268,8 +269,9 @@ int gsr_render_work(const gsr_scene* scene, const gsr_camera* cam, const gsr_con
                     size_t ws_bytes, float* rgb, float* depth, int32_t* count, float* T_final,
                     int32_t* status_dev, uint64_t* work_dev, gsr_stream_t stream);
 
-/* Number of radix passes a W x H frame's full keys need (32 + tile bits,
- * digits of at most 9 bits): the global order, and the fallback sort. */
+/* Number of radix passes that group a W x H frame's entries by tile in
+ * GSR_MODE_GLOBAL and GSR_MODE_WINDOW: every tile bit (their duplication
+ * writes entries at per-Gaussian offsets), digits of at most 9 bits. */
 int gsr_sort_passes(int32_t W, int32_t H);
 
 /* Number of radix passes that group a W x H frame's entries by tile: over the

@@ -40,7 +40,7 @@ int bits_for_tiles(int tiles) {
 // buffer 1 is then free scratch for the per-tile fallback sort.  GLOBAL: the
 // full (tile, depth) sort, result in buffer 0.
 struct SortPlan {
-    int tile_bits, key_bits, group_bits, tile_passes, full_passes, dup_buf;
+    int tile_bits, key_bits, group_bits, group_shift, tile_passes, full_passes, dup_buf;
 };
 
 SortPlan sort_plan(int tiles, int mode) {
@@ -48,9 +48,14 @@ SortPlan sort_plan(int tiles, int mode) {
     p.tile_bits = bits_for_tiles(tiles);
     p.key_bits = 32 + p.tile_bits;
     p.full_passes = gsr::sort_pass_count(p.key_bits);
-    p.group_bits = p.tile_bits > gsr::kDupDigitBits ? p.tile_bits - gsr::kDupDigitBits : 0;
+    // The hierarchical order's duplication already buckets entries by the low
+    // tile bits; the global order's writes them at per-Gaussian offsets, so
+    // its grouping passes cover every tile bit.
+    const int done_bits = mode == GSR_MODE_HIER ? gsr::kDupDigitBits : 0;
+    p.group_shift = 32 + done_bits;
+    p.group_bits = p.tile_bits > done_bits ? p.tile_bits - done_bits : 0;
     p.tile_passes = p.group_bits > 0 ? gsr::sort_pass_count(p.group_bits) : 0;
-    p.dup_buf = (mode == GSR_MODE_HIER ? p.tile_passes : p.full_passes) & 1;
+    p.dup_buf = p.tile_passes & 1;
     return p;
 }
 
@@ -187,10 +192,16 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     return b;
 }
 
-int prefix_len(const gsr_config* cfg) { return cfg->sort_prefix == 0 ? 1024 : cfg->sort_prefix; }
+// Entries per tile sorted up front.  The 3DGS lists (global order, resort
+// window) keep every rectangle tile and reach deeper before their pixels
+// finish, so their default prefix is longer.
+int prefix_len(const gsr_config* cfg) {
+    if (cfg->sort_prefix != 0) return cfg->sort_prefix;
+    return (cfg->mode == GSR_MODE_GLOBAL || cfg->mode == GSR_MODE_WINDOW) ? 4096 : 1024;
+}
 
-// Sort stage of a frame (or a batch).  HIER: group by tile, tile ranges and
-// each tile's sorted prefix.  GLOBAL: full sort and ranges.
+// Sort stage of a frame (or a batch): group by tile, tile ranges and each
+// tile's sorted prefix.
 hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, hipStream_t s,
                       void* const* scatter_events, void* const* order_events = nullptr) {
     const SortPlan sp = sort_plan(tiles, mode);
@@ -199,22 +210,19 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
     auto mark = [&](int k) -> hipError_t {
         return order_events ? hipEventRecord((hipEvent_t)order_events[k], s) : hipSuccess;
     };
-    if (mode == GSR_MODE_HIER) {
-        if ((e = gsr::launch_fill_u32(b.tile_flag, 3 * (size_t)tiles, 0u, s)) != hipSuccess) return e;
-        if (sp.tile_passes > 0) {
-            if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.group_bits,
-                                            sp.dup_buf, &res, s, scatter_events, 32 + gsr::kDupDigitBits)) != hipSuccess)
-                return e;
-        }
-        if ((e = mark(0)) != hipSuccess) return e;
-        if ((e = gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.counters, (uint32_t)tiles, b.ranges, b.pre_vals,
-                                         b.pre_len, M, s)) != hipSuccess)
+    // Both orders: group by tile (stable radix passes over the tile bits not
+    // yet grouped), then order each tile's first M entries by (depth, id).
+    if ((e = gsr::launch_fill_u32(b.tile_flag, 3 * (size_t)tiles, 0u, s)) != hipSuccess) return e;
+    if (sp.tile_passes > 0) {
+        if ((e = gsr::launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, sp.group_bits,
+                                        sp.dup_buf, &res, s, scatter_events, sp.group_shift)) != hipSuccess)
             return e;
-        return mark(1);
     }
-    if ((e = gsr::launch_sort(b, sp.key_bits, &res, s, scatter_events)) != hipSuccess) return e;
     if ((e = mark(0)) != hipSuccess) return e;
-    if ((e = gsr::launch_ranges(b.keys[res], b.counters, b.ranges, b.capacity, tiles, s)) != hipSuccess) return e;
+    if ((e = gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.counters, (uint32_t)tiles, b.ranges, b.pre_vals,
+                                     b.pre_len, M, s)) != hipSuccess)
+        return e;
+    (void)mode;
     return mark(1);
 }
 
@@ -290,7 +298,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
                                    0u, groups)) != hipSuccess)
         return fail_hip(e, "duplicate");
     if ((e = mark(2)) != hipSuccess) return fail_hip(e, "event");
-    const int n_sort_ev = mode == GSR_MODE_HIER ? sp.tile_passes : sp.full_passes;
+    const int n_sort_ev = sp.tile_passes;
     void* const* scatter_ev = (events && n_events >= 5 + 2 * n_sort_ev) ? events + 5 : nullptr;
     // Optional brackets of single launches: the per-tile ordering and the
     // first render pass.
@@ -342,16 +350,19 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
         ra.work = nullptr;  // the work of the prefix pass is counted
         ra.list_mode = gsr::kListFlagged;
         if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
-    } else if (cfg->mode == GSR_MODE_WINDOW) {
-        ra.list_mode = gsr::kListFull;
-        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
-        if ((e = gsr::launch_render_window(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
-        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
     } else {
-        ra.list_mode = gsr::kListFull;
+        // The 3DGS order and the resort window over its lists: the same
+        // prefix pass and fallback as the hierarchical order.
+        const bool window = cfg->mode == GSR_MODE_WINDOW;
+        set_prefix_lists(ra, b, gsr::kListPrefix);
         if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
-        if ((e = gsr::launch_render_global(ra, s)) != hipSuccess) return fail_hip(e, "render");
+        e = window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
+        if (e != hipSuccess) return fail_hip(e, "render");
         if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
+        if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
+        ra.list_mode = gsr::kListFlagged;
+        e = window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
+        if (e != hipSuccess) return fail_hip(e, "render fallback");
     }
     if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
     return GSR_OK;
@@ -904,7 +915,7 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 
 int gsr_sort_passes(int32_t W, int32_t H) {
     if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
-    return gsr::sort_pass_count(32 + bits_for_tiles(tiles_of(W, H)));
+    return sort_plan(tiles_of(W, H), GSR_MODE_GLOBAL).tile_passes;
 }
 
 int gsr_group_passes(int32_t W, int32_t H) {

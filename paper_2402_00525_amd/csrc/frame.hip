@@ -916,15 +916,6 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_ranges(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ n_ptr, uint32_t* ranges) {
-    const uint32_t n = *n_ptr;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = (uint32_t)(keys[i] >> 32);
-    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[2 * (size_t)t] = (uint32_t)i;
-    if (i + 1 == n || (uint32_t)(keys[i + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(i + 1);
-}
-
 struct BwdArgs {
     SceneArgs sc;
     DevCam cam;
@@ -1196,14 +1187,6 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flag
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
-                         hipStream_t s) {
-    hipError_t e = launch_fill_u32(ranges, (size_t)tiles * 2, 0u, s);
-    if (e != hipSuccess) return e;
-    if (cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)div_up(cap, 256)), dim3(256), 0, s, keys, n_ptr, ranges);
-    return hipGetLastError();
-}
 
 hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* co, const float* grad2d,
                                       float* dmeans, float* dscales, float* drots, float* dopac, float* dsh,

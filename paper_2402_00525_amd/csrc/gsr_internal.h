@@ -94,12 +94,6 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* pa
 hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flags, const FrameBufs& b, int buf,
                             int32_t* status, hipStream_t s, uint32_t tile_base = 0, uint32_t id_base = 0,
                             const DupGroups* groups = nullptr);
-// Stable LSD radix sort of the first counters[0] (key, value) pairs on the
-// low `bits` key bits; returns the buffer index (0/1) holding the result.
-// `scatter_events` (optional): 2 events per pass recorded right before and
-// after that pass's scatter launch.
-hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s,
-                       void* const* scatter_events = nullptr);
 // Stable LSD sort of the first *n_ptr pairs of (keys[start], vals[start]) on
 // the low `bits` key bits, for at most `cap` pairs; the result lands in
 // buffer start ^ (passes & 1), returned in *result_buf.  hist holds
@@ -127,8 +121,6 @@ hipError_t launch_tile_sort_flagged(uint64_t* keys, const uint32_t* vals, uint64
 // Cost keys for ordering tiles: key[t] = ~(list length of tile t), val[t] = t.
 hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals,
                                  hipStream_t s);
-hipError_t launch_ranges(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* ranges, size_t cap, int tiles,
-                         hipStream_t s);
 
 struct RenderArgs {
     DevCam cam;

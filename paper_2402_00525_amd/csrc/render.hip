@@ -838,19 +838,21 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
     const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
     const bool inside = px < cam.W && py < cam.H;
     const int pix = py * cam.W + px;
-    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const TileList tl = tile_list(a, tile);
+    if (tl.skip) return;
+    const uint32_t begin = 0, end = tl.len;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
     int n = 0;
     bool done = !inside;
     uint32_t consumed = 0;
     // debug: sort error along the pixel ray (the blend order is the list's)
-    float dl = 0.0f, tl = 0.0f;
+    float se_sum = 0.0f, se_last = 0.0f;
     const float3 dP = DEBUG ? cam_ray(cam, (float)px, (float)py) : make_float3(0.0f, 0.0f, 0.0f);
     for (uint32_t start = begin; start < end; start += 256) {
         if (__syncthreads_count(done ? 1 : 0) == 256) break;
         const uint32_t idx = start + threadIdx.x;
         if (idx < end) {
-            uint32_t id = a.vals[idx];
+            uint32_t id = tl.ids[idx];
             id = id < a.n ? id : 0u;
             s_id[threadIdx.x] = id;
             s_xy[threadIdx.x] = a.xy[id];
@@ -886,14 +888,17 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
             if (DEBUG && n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + n] = (int32_t)s_id[k];
             if (DEBUG && a.delta) {
                 const float t = t_opt(load_packed(a.pk, s_id[k]), dP);
-                if (n > 0 && tl > t) dl = dl + (tl - t);
-                tl = t;
+                if (n > 0 && se_last > t) se_sum = se_sum + (se_last - t);
+                se_last = t;
             }
             n += 1;
             T = Tn;
         }
         __syncthreads();
     }
+    // A prefix that ran out while pixels are still live cannot decide the
+    // tile: flag it for its whole sorted list.
+    if (tl.truncated && __syncthreads_or(done ? 0 : 1) && threadIdx.x == 0) a.tile_flag[tile] = tl.n_all;
     if (inside) {
         const size_t P = (size_t)cam.W * cam.H;
         a.rgb[pix] = C0 + T * a.bg0;
@@ -904,7 +909,7 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
         a.T[pix] = T;
         if (DEBUG) {
             for (int k = n; k < a.max_k; ++k) a.blend_ids[(size_t)pix * a.max_k + k] = -1;
-            if (a.delta) a.delta[pix] = dl;
+            if (a.delta) a.delta[pix] = se_sum;
         }
     }
     if (threadIdx.x == 0 && consumed) atomicAdd(a.counters + 1, consumed);
@@ -923,7 +928,9 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
     const bool inside = px < cam.W && py < cam.H;
     const int pix = py * cam.W + px;
-    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const TileList tl = tile_list(a, tile);
+    if (tl.skip) return;
+    const uint32_t begin = 0, end = tl.len;
     const float3 d = cam_ray(cam, (float)px, (float)py);
     PixelState<K, MODE> st;
     st.T = 1.0f;
@@ -944,7 +951,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
         if (__syncthreads_count(st.done ? 1 : 0) == 256) break;
         const uint32_t idx = start + threadIdx.x;
         if (idx < end) {
-            uint32_t id = a.vals[idx];
+            uint32_t id = tl.ids[idx];
             id = id < a.n ? id : 0u;
             s_id[threadIdx.x] = id;
             s_g[threadIdx.x] = load_packed(a.pk, id);
@@ -961,6 +968,9 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
         }
         __syncthreads();
     }
+    // A prefix that ran out while pixels are still live cannot decide the
+    // tile: flag it for its whole sorted list (this pass's image is redone).
+    if (tl.truncated && __syncthreads_or(st.done ? 0 : 1) && threadIdx.x == 0) a.tile_flag[tile] = tl.n_all;
 #pragma unroll
     for (int i = 0; i < K; ++i)
         if (st.hn > 0) head_pop_blend<K, MODE>(a, st, pix, nullptr);
@@ -999,7 +1009,9 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     const int px = tx * 16 + (threadIdx.x & 15), py = ty * 16 + (threadIdx.x >> 4);
     const bool inside = px < cam.W && py < cam.H;
     const int pix = py * cam.W + px;
-    const uint32_t begin = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const TileList tl = tile_list(a, tile);
+    if (tl.skip) return;
+    const uint32_t begin = 0, end = tl.len;
     const float3 d = cam_ray(cam, (float)px, (float)py);
     PixelState<K, MODE> st;
     st.T = 1.0f;
@@ -1024,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
             const uint32_t idx = start + threadIdx.x;
             __syncthreads();
             if (idx < end) {
-                uint32_t id = a.vals[idx];
+                uint32_t id = tl.ids[idx];
                 id = id < a.n ? id : 0u;
                 s_id[threadIdx.x] = id;
                 s_g[threadIdx.x] = load_packed(a.pk, id);

@@ -237,13 +237,6 @@ hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], c
     return hipGetLastError();
 }
 
-hipError_t launch_sort(const FrameBufs& b, int bits, int* result_buf, hipStream_t s, void* const* scatter_events) {
-    // Duplication writes into buffer (passes & 1) so that the result lands in buffer 0.
-    const int passes = sort_pass_count(bits);
-    return launch_sort_pairs(b.keys, b.vals, b.counters, b.capacity, b.hist, b.scan_partial, bits, passes & 1,
-                             result_buf, s, scatter_events, 0);
-}
-
 namespace {
 __global__ void k_tile_cost_keys(const uint32_t* __restrict__ ranges, uint32_t n_tiles, uint64_t* __restrict__ keys,
                                  uint32_t* __restrict__ vals) {

@@ -331,9 +331,9 @@ class Renderer:
         return keys, vals, ranges
 
     def tile_lists(self, n, cam):
-        """Hierarchical mode: per-tile sorted ids of the last frame (a prefix, or
-        the whole list for tiles that took the fallback) as host numpy arrays;
-        pre_vals is indexed by range start."""
+        """Per-tile sorted ids of the last frame (a prefix, or the whole list
+        for tiles that took the fallback) as host numpy arrays; pre_vals is
+        indexed by range start."""
         E = self.counter(n, cam, 0)
         F = self.counter(n, cam, 5)
         tiles = ((cam.W + 15) // 16) * ((cam.H + 15) // 16)

@@ -27,9 +27,8 @@ def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=N
                ranges=ranges.cpu().numpy().view(np.uint32), consumed=r.counter(n, cam, 1), **rec)
     res["mode"] = mode
     res["flags"] = flags
-    res["sort_prefix"] = sort_prefix or 1024
-    if mode == 1:
-        res["lists"] = r.tile_lists(n, cam)
+    res["sort_prefix"] = sort_prefix or (4096 if mode in (0, 3) else 1024)
+    res["lists"] = r.tile_lists(n, cam)
     if max_k > 0:
         res["blend_ids"] = out.blend_ids.cpu().numpy()
     return res
@@ -63,17 +62,13 @@ def assert_records_equal(g, o):
 
 
 def assert_sorted_equal(g, o):
-    """Global order: the fully sorted keys and values equal the oracle's.
-    Hierarchical order: the entries grouped by tile are the oracle's (as a set
-    per tile, in any order inside a tile), every tile's sorted prefix is
-    the start of the oracle's sorted list, and every tile that took the
-    fallback has the oracle's whole sorted list."""
+    """Every order (its own keys: t_opt through x^ in the hierarchical
+    order, view depth in the global one): the entries grouped by tile are the
+    oracle's (as a set per tile, in any order inside a tile), every tile's
+    sorted prefix is the start of the oracle's sorted list, and every tile
+    that took the fallback has the oracle's whole sorted list."""
     assert len(g["keys"]) == len(o.keys), (len(g["keys"]), len(o.keys))
     np.testing.assert_array_equal(g["ranges"], o.ranges)
-    if g.get("mode", 0) != 1:
-        np.testing.assert_array_equal(g["keys"], o.keys)
-        np.testing.assert_array_equal(g["values"], o.values)
-        return
     L = g["lists"]
     ov = o.values.view(np.uint32)
     flag = L["tile_flag"].view(np.uint32)

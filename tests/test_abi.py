@@ -120,10 +120,10 @@ def test_batch_workspace_planning(L):
 
 
 def test_sort_pass_count(L):
-    # 32 depth bits + tile bits, digits of at most 9 bits
-    assert L.lib().gsr_sort_passes(1920, 1080) == 5      # 8160 tiles -> 13 bits -> 45 bits
-    assert L.lib().gsr_sort_passes(128, 128) == 5        # 64 tiles -> 38 bits
-    assert L.lib().gsr_sort_passes(16, 16) == 4          # 1 tile -> 32 bits
+    # global order: grouping over every tile bit, digits of at most 9 bits
+    assert L.lib().gsr_sort_passes(1920, 1080) == 2      # 8160 tiles -> 13 bits
+    assert L.lib().gsr_sort_passes(128, 128) == 1        # 64 tiles -> 6 bits
+    assert L.lib().gsr_sort_passes(16, 16) == 0          # 1 tile
     # grouping by tile: duplication buckets the low 5 tile bits, radix passes the rest
     assert L.lib().gsr_group_passes(1920, 1080) == 1     # 13 bits
     assert L.lib().gsr_group_passes(80, 64) == 0         # 20 tiles, 5 bits
