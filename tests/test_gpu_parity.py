@@ -134,6 +134,25 @@ def test_prefix_fallback_bit_exact(prefix):
     np.testing.assert_array_equal(g["count"], o.count)
 
 
+@pytest.mark.parametrize("mode,K,prefix", [(oracle.MODE_GLOBAL, 4, 1), (oracle.MODE_GLOBAL, 4, 16),
+                                           (oracle.MODE_GLOBAL, 4, 100), (oracle.MODE_WINDOW, 4, 16),
+                                           (oracle.MODE_WINDOW, 16, 100)])
+def test_prefix_fallback_3dgs_lists_bit_exact(mode, K, prefix):
+    """The 3DGS order and the resort window take the same prefix pass and
+    fallback: short prefixes flag tiles, which are rendered again from their
+    whole sorted lists; blend order and images are those of the full sort."""
+    sc, cam = synth.workload_small()
+    say("case: 3DGS lists, mode", mode, "K", K, "prefix", prefix)
+    o = oracle.frame(sc, cam, mode=mode, head=K, max_k=48)
+    g = gpu_frame(sc, cam, mode=mode, head=K, max_k=48, sort_prefix=prefix)
+    assert_sorted_equal(g, o)
+    if prefix <= 16:
+        assert g["lists"]["fallback_entries"] > 0
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    np.testing.assert_array_equal(g["count"], o.count)
+
+
 def test_prefix_fallback_long_lists():
     """Faint Gaussians keep pixels alive past every prefix, so tiles of more
     than 4096 entries take the fallback's radix path."""
