@@ -424,6 +424,12 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
 // ---------------------------------------------------------------------------
 // Batched rendering: many views of several scenes in one launch sequence.
 // ---------------------------------------------------------------------------
+// Batch counters (uint32 words): [0] entries, [2] tiles, [3] entries needed,
+// [5], [6] flagged entries and tiles, from kBatchQueue0 the work-queue heads
+// of the prefix pass, then those of the flagged pass.
+constexpr int kBatchQueue0 = 16;
+constexpr int kBatchCounters = kBatchQueue0 + 2 * gsr::kBatchQueues;
+
 struct BatchLayout {
     int64_t views, xy, co, sw, pk, zd, rect, touched, kmask, offsets, dhist, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag, flist;
@@ -451,7 +457,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
     L->offsets = take(4 * R);
     L->dhist = take(4 * gsr::kDupBins * dup_workgroups(R));
     L->ranges = take(8 * tiles);
-    L->counters = take(64);
+    L->counters = take(4 * kBatchCounters);
     L->pre_len = take(4 * tiles);
     L->tile_flag = take(4 * 3 * tiles);
     L->flist = take(4 * tiles);
@@ -559,7 +565,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     const SortPlan sp = sort_plan(tiles, GSR_MODE_HIER);
     const int lb = b->sched.lb_threshold;
     hipError_t e;
-    if ((e = gsr::launch_fill_u32(fb.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
+    if ((e = gsr::launch_fill_u32(fb.counters, kBatchCounters, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
     if ((e = gsr::launch_fill_u32(fb.counters + 2, 1, (uint32_t)b->tiles, s)) != hipSuccess) return fail_hip(e, "clear");
     auto shifted = [&](int64_t r0) {
         gsr::FrameBufs v = fb;
@@ -632,8 +638,8 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.pre_len = fb.pre_len;
     ba.tile_flag = fb.tile_flag;
     ba.flags = (int)b->cfg.flags;
-    ba.queue = fb.counters + 1;
-    ba.n_items = (uint32_t)(4 * b->tiles);
+    ba.queue = fb.counters + kBatchQueue0;
+    ba.n_tiles = (uint32_t)b->tiles;
     ba.n_tiles_dev = nullptr;
     ba.bg0 = b->cfg.bg[0];
     ba.bg1 = b->cfg.bg[1];
@@ -645,7 +651,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.list_mode = gsr::kListFlagged;
     ba.order = fb.flist;
     ba.n_tiles_dev = fb.counters + 6;
-    ba.queue = fb.counters + 7;
+    ba.queue = fb.counters + kBatchQueue0 + gsr::kBatchQueues;
     if ((e = gsr::launch_render_hier_batch(ba, b->cfg.head, grid, s)) != hipSuccess)
         return fail_hip(e, "render fallback");
     return GSR_OK;

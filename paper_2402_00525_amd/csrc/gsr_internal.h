@@ -175,6 +175,11 @@ struct ViewDev {
     uint32_t rec_base;   // first record of this view
 };
 
+// Work queues of the batched render: tile slot s of the work order goes to
+// queue s % kBatchQueues, the queue of the XCD that runs workgroups b with
+// b % kBatchQueues == s % kBatchQueues.
+constexpr int kBatchQueues = 8;
+
 struct BatchArgs {
     const ViewDev* views;
     int n_views;
@@ -192,9 +197,9 @@ struct BatchArgs {
     const uint32_t* pre_len;
     uint32_t* tile_flag;
     int flags;                // as RenderArgs::flags
-    uint32_t* queue;          // work-queue head, zero before the launch
-    uint32_t n_items;         // 4 strips per global tile
-    const uint32_t* n_tiles_dev;  // if set, n_items = 4 * *n_tiles_dev (tiles listed in order)
+    uint32_t* queue;          // kBatchQueues work-queue heads (one per XCD), zero before the launch
+    uint32_t n_tiles;         // tiles listed in `order` (4 strips each)
+    const uint32_t* n_tiles_dev;  // if set, the number of tiles is read here instead
     float bg0, bg1, bg2;
 };
 

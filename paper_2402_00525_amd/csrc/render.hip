@@ -763,66 +763,80 @@ __global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
     }
 }
 
-// Persistent form over many views: every wavefront pulls (tile, strip) work
-// items from one atomic queue until the queue is empty; tiles are taken in
-// the order given by `order` (largest lists first when cost-ordered), so
-// views of very different sizes share the machine.  Every wavefront leaves
-// the loop once the queue is exhausted.
+// One (tile, strip) item of the batched render: slot `slot` of the work order.
+template <int K>
+__device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t slot, uint32_t strip, WaveQueues& q) {
+    const uint32_t gt = b.order ? b.order[slot] : slot;
+    // view of global tile gt: the last view whose first tile is <= gt
+    int lo = 0, hi = b.n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.views[mid].tile_base <= gt)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int v = __builtin_amdgcn_readfirstlane(lo);
+    const ViewDev& vd = b.views[v];
+    RenderArgs a;
+    a.cam = vd.cam;
+    a.n = b.n_records;
+    a.xy = b.xy;
+    a.co = b.co;
+    a.sw = b.sw;
+    a.pk = b.pk;
+    a.zd = b.zd;
+    a.vals = b.vals;
+    a.ranges = b.ranges;
+    a.counters = nullptr;
+    a.rgb = vd.rgb;
+    a.depth = vd.depth;
+    a.count = vd.count;
+    a.T = vd.T;
+    a.blend_ids = nullptr;
+    a.max_k = 0;
+    a.delta = nullptr;
+    a.bg0 = b.bg0;
+    a.bg1 = b.bg1;
+    a.bg2 = b.bg2;
+    a.dL = nullptr;
+    a.rgb_in = nullptr;
+    a.T_in = nullptr;
+    a.grad2d = nullptr;
+    a.list_mode = b.list_mode;
+    a.pre_vals = b.pre_vals;
+    a.pre_len = b.pre_len;
+    a.tile_flag = b.tile_flag;
+    a.flags = b.flags;
+    render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)strip, q, nullptr);
+}
+
+// Persistent form over many views: wavefronts pull (tile, strip) work items
+// from atomic queues until every queue is empty; tiles are taken in the order
+// given by `order` (largest lists first when cost-ordered), so views of very
+// different sizes share the machine.  Slot s of that order belongs to queue s
+// % 8, which the workgroups of one XCD (blockIdx.x % 8, as workgroups are
+// dealt to the 8 XCDs in turn) drain first: the four strips of a tile then
+// meet in one L2.  A wavefront whose queue is empty moves on to the next
+// queues in turn, and leaves once it has found all of them empty.
 template <int K>
 __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
     __shared__ WaveQueues s_q[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t n_items = b.n_tiles_dev ? 4u * *b.n_tiles_dev : b.n_items;
-    for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(b.queue, 1u);
-        item = (uint32_t)__shfl((int)item, 0);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= n_items) break;
-        const uint32_t slot = item >> 2;
-        const uint32_t gt = b.order ? b.order[slot] : slot;
-        // view of global tile gt: the last view whose first tile is <= gt
-        int lo = 0, hi = b.n_views - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b.views[mid].tile_base <= gt)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const uint32_t n_slots = b.n_tiles_dev ? *b.n_tiles_dev : b.n_tiles;
+    const uint32_t home = blockIdx.x % (uint32_t)kBatchQueues;
+    for (uint32_t qi = 0; qi < (uint32_t)kBatchQueues; ++qi) {
+        const uint32_t x = (home + qi) % (uint32_t)kBatchQueues;
+        const uint32_t n_x = n_slots > x ? (n_slots - x + kBatchQueues - 1u) / (uint32_t)kBatchQueues : 0u;
+        for (;;) {
+            uint32_t item = 0;
+            if (lane == 0) item = atomicAdd(b.queue + x, 1u);
+            item = (uint32_t)__shfl((int)item, 0);
+            item = __builtin_amdgcn_readfirstlane(item);
+            if (item >= 4u * n_x) break;
+            const uint32_t slot = (item >> 2) * (uint32_t)kBatchQueues + x;
+            render_batch_item<K>(b, slot, item & 3u, s_q[wave]);
         }
-        const int v = __builtin_amdgcn_readfirstlane(lo);
-        const ViewDev& vd = b.views[v];
-        RenderArgs a;
-        a.cam = vd.cam;
-        a.n = b.n_records;
-        a.xy = b.xy;
-        a.co = b.co;
-        a.sw = b.sw;
-        a.pk = b.pk;
-        a.zd = b.zd;
-        a.vals = b.vals;
-        a.ranges = b.ranges;
-        a.counters = nullptr;
-        a.rgb = vd.rgb;
-        a.depth = vd.depth;
-        a.count = vd.count;
-        a.T = vd.T;
-        a.blend_ids = nullptr;
-        a.max_k = 0;
-        a.delta = nullptr;
-        a.bg0 = b.bg0;
-        a.bg1 = b.bg1;
-        a.bg2 = b.bg2;
-        a.dL = nullptr;
-        a.rgb_in = nullptr;
-        a.T_in = nullptr;
-        a.grad2d = nullptr;
-        a.list_mode = b.list_mode;
-        a.pre_vals = b.pre_vals;
-        a.pre_len = b.pre_len;
-        a.tile_flag = b.tile_flag;
-        a.flags = b.flags;
-        render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)(item & 3u), s_q[wave], nullptr);
     }
 }
 

@@ -48,9 +48,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
                 const size_t i = base + (size_t)(r + u) * 64 + lane;
                 k8[u] = i < n ? keys[i] : ~0ull;
             }
+            // Keys with the digit of lane 0 are added as one count (runs of
+            // equal digits would otherwise queue on one LDS address).
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (k8[u] != ~0ull) atomicAdd(&h[j][(uint32_t)(k8[u] >> shift) & mask], 1u);
+            for (int u = 0; u < 8; ++u) {
+                const bool valid = k8[u] != ~0ull;
+                const uint32_t d = (uint32_t)(k8[u] >> shift) & mask;
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                const uint64_t same = __ballot(valid && d == d0);
+                if (valid && d != d0) atomicAdd(&h[j][d], 1u);
+                if (lane == 0 && same) atomicAdd(&h[j][d0], (uint32_t)__popcll(same));
+            }
         }
     }
     __syncthreads();
