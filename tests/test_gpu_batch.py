@@ -142,3 +142,20 @@ def test_batch_overflow_replans():
     got = _frames_np(b.render())
     assert b.capacity() > 1000
     _assert_same(got, _single(scenes, views))
+
+
+def test_batch_fewer_tiles_than_work_queues():
+    # 1 + 6 tiles: most of the eight per-XCD queues hold nothing, and with a
+    # prefix of 16 the flagged pass lists only a few tiles.
+    from paper_2402_00525_amd import gsr
+    scenes = [synth.uniform_scene(2000, seed=0, sh_degree=0), synth.uniform_scene(1500, seed=21, sh_degree=2)]
+    views = [(0, synth.front_camera(16, 16)), (1, synth.orbit_camera(33, 17, 11))]
+    ref = _single(scenes, views)
+    for prefix in (0, 16):
+        say("case: 7-tile batch, prefix %d" % prefix)
+        b, _ = _batch(scenes, views, cfg=gsr.config(sort_prefix=prefix))
+        for w in (1, 8):
+            b.set_schedule(gsr.schedule(w, 1, 64))
+            _assert_same(_frames_np(b.render()), ref)
+        if prefix:
+            assert int(b.counters()[6].item()) > 0
