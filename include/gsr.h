@@ -284,8 +284,10 @@ int gsr_group_passes(int32_t W, int32_t H);
  * rendered by one launch sequence.  All views' Gaussians are preprocessed into
  * one record array, all (view, tile, depth) keys are sorted once, and one
  * persistent render kernel pulls (tile, 16x4 strip) work items of all views
- * from an atomic queue, largest tile lists first.  Each view's pixels equal
- * those of gsr_render for that view (hierarchical order).
+ * from eight atomic queues, one per XCD (tile slot s of the work order, which
+ * is largest tile lists first when cost-ordered, in queue s mod 8; a
+ * wavefront drains its own XCD's queue, then the others).  Each view's pixels
+ * equal those of gsr_render for that view (hierarchical order).
  * ------------------------------------------------------------------------- */
 typedef struct gsr_view {
     int32_t scene;        /* index into the scenes array */
@@ -338,8 +340,10 @@ int gsr_batch_tune(gsr_batch* batch, int32_t* status_dev, gsr_stream_t stream, c
 int64_t gsr_batch_records(const gsr_batch* batch);        /* total Gaussian records */
 int64_t gsr_batch_tiles(const gsr_batch* batch);          /* total 16x16 tiles */
 int64_t gsr_batch_entry_capacity(const gsr_batch* batch); /* entries the workspace holds */
-int64_t gsr_batch_counters_offset(const gsr_batch* batch);/* byte offset of uint32 counters[4] in ws:
-                                                             (entries, queue head, tiles, entries needed) */
+int64_t gsr_batch_counters_offset(const gsr_batch* batch);/* byte offset of uint32 counters[32] in ws:
+                                                             [0] entries, [2] tiles, [3] entries needed,
+                                                             [5] / [6] entries / tiles of the fallback,
+                                                             [16..31] work-queue heads */
 void gsr_batch_destroy(gsr_batch* batch);
 
 /* Element-wise arithmetic probe of the device (diagnostic): for n inputs
