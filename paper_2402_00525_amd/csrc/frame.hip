@@ -114,6 +114,7 @@ struct ProjOut {
     float Si[6];     // s00 s01 s02 s11 s12 s22
     float w[3];
     float pz, dist;
+    float lno;       // ln(opacity / eps_O)
     float dir[3];    // unit direction camera -> mean (colour)
     int4 rc;
 };
@@ -216,7 +217,10 @@ __device__ bool project_geom(const SceneArgs& sc, const DevCam& cam, int mode, b
                 my = cam.fy * tytz + cam.cy;
                 ok = op >= kEpsO;
             }
+            float lno = 0.0f;
             if (ok) {
+                lno = ln_atanh(op / kEpsO);
+                po.lno = lno;
                 const float mid = 0.5f * (a + c);
                 const float disc = mid * mid - det;
                 const float lam = mid + sqrtf(0.1f > disc ? 0.1f : disc);
@@ -226,7 +230,7 @@ __device__ bool project_geom(const SceneArgs& sc, const DevCam& cam, int mode, b
                 } else {
                     // Opacity-aware bound t_O = sqrt(2 ln(o / eps_O)), widened by
                     // 1/256 and a pixel so that only exact culling decides.
-                    const float tO = sqrtf(2.0f * ln_atanh(op / kEpsO));
+                    const float tO = sqrtf(2.0f * lno);
                     const float r = tO * sqrtf(lam);
                     rr = r * 1.00390625f + 1.0f;
                 }
@@ -244,7 +248,7 @@ __device__ bool project_geom(const SceneArgs& sc, const DevCam& cam, int mode, b
                     // q <= t_O^2 has half-widths t_O sqrt(Sigma_2 diagonal), at
                     // most the radius above; widened the same way (the box may
                     // be empty when the square is not).
-                    const float tO = sqrtf(2.0f * ln_atanh(op / kEpsO));
+                    const float tO = sqrtf(2.0f * lno);
                     const float rx = (tO * sqrtf(a)) * 1.00390625f + 1.0f;
                     const float ry = (tO * sqrtf(c)) * 1.00390625f + 1.0f;
                     fx0 = sel_max(fx0, ceilf(((mx - rx) - 15.0f) / 16.0f));
@@ -280,7 +284,7 @@ __device__ void write_records(const PreOut& out, int i, bool ok, const ProjOut& 
                               int4& rc) {
     if (ok) {
         g.x = po.mx; g.y = po.my; g.ca = po.ca; g.cb = po.cb; g.cc = po.cc; g.op = po.op;
-        g.lt = -ln_atanh(po.op / kEpsO);
+        g.lt = -po.lno;
         g.s00 = po.Si[0]; g.s01 = po.Si[1]; g.s02 = po.Si[2]; g.s11 = po.Si[3]; g.s12 = po.Si[4]; g.s22 = po.Si[5];
         g.w0 = po.w[0]; g.w1 = po.w[1]; g.w2 = po.w[2];
         rc = po.rc;
@@ -447,11 +451,9 @@ __device__ __forceinline__ int flat_owner(const FlatStarts& f, uint32_t j, uint3
     return r > 0 ? (int)f.lane_of[(r - 1u) & 63u] : 0;
 }
 
-// SH coefficients of a workgroup's Gaussians, staged in LDS with an odd row
-// stride so that lanes reading their own rows hit distinct banks.
-// SH coefficients are staged in LDS in chunks of kShChunk coefficients
-// (3 kShChunk floats per Gaussian, odd row stride so that lanes reading their
-// own rows hit distinct banks).
+// SH coefficients of a workgroup's Gaussians are staged in LDS in chunks of
+// kShChunk coefficients (3 kShChunk floats per Gaussian, odd row stride so
+// that lanes reading their own rows hit distinct banks).
 constexpr int kShChunk = 8;
 constexpr int kShStride = 3 * kShChunk + 1;
 
