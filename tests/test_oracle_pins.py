@@ -350,17 +350,44 @@ def test_hier_equals_full_sort_when_head_holds_everything():
     np.testing.assert_array_equal(hier.rgb, full.rgb)
 
 
-def test_full_order_invariant_under_180_degree_roll():
-    sc, cam = synth.workload_small()
-    cam = synth.orbit_camera(96, 64, view=7)
-    rolled = synth.roll_180(cam)
-    a = oracle.frame(sc, cam, mode=oracle.MODE_FULL, max_k=64)
-    b = oracle.frame(sc, rolled, mode=oracle.MODE_FULL, max_k=64)
-    bb = b.blend_ids[::-1, ::-1]
-    same = np.all(a.blend_ids == bb, axis=-1)
-    # alpha decisions use the 2D mean, which is mirrored up to one rounding;
-    # orders agree on (almost) every pixel and the per-pixel sets of depths do.
-    assert same.mean() > 0.995, same.mean()
+def _alpha_f64(fr, g, u, v):
+    ca, cb, cc, o = fr.conic_o[g].astype(np.float64)
+    dx, dy = float(fr.xy[g, 0]) - u, float(fr.xy[g, 1]) - v
+    return o * math.exp(-0.5 * (ca * dx * dx + cc * dy * dy) - cb * dx * dy)
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_FULL, oracle.MODE_HIER])
+def test_order_invariant_under_180_degree_roll(mode):
+    # An exact 180-degree roll about the optical axis maps pixel (i, j) to
+    # (W-1-i, H-1-j) with bit-identical world rays, so t_opt along every ray
+    # and hence the full per-pixel order are unchanged (Sec. 3: sorting along
+    # the ray removes popping under rotation).  With W and H multiples of 16
+    # the tiles, sub-tiles and quads map onto each other too, so the
+    # hierarchical order is unchanged as well.  What can change is an alpha
+    # decision: the mirrored 2D mean is rounded once more, so a Gaussian whose
+    # alpha at a pixel lies within rounding of 1/255 may be kept in one frame
+    # and skipped in the other.  Every pixel must agree exactly once such
+    # Gaussians are set aside, and there must be few of them.
+    scenes = [synth.workload_small()[0], synth.subsample(synth.mixture_scene(100_000, seed=1), 5000)]
+    n_pix = n_diff = 0
+    for sc in scenes:
+        for view in (0, 7, 29):
+            cam = synth.orbit_camera(96, 64, view=view)
+            a = oracle.frame(sc, cam, mode=mode, max_k=128)
+            b = oracle.frame(sc, synth.roll_180(cam), mode=mode, max_k=128)
+            assert a.count.max() < 128
+            bb = b.blend_ids[::-1, ::-1]
+            n_pix += cam.W * cam.H
+            for y, x in zip(*np.nonzero(np.any(a.blend_ids != bb, axis=-1))):
+                n_diff += 1
+                sa = [int(i) for i in a.blend_ids[y, x] if i >= 0]
+                sb = [int(i) for i in bb[y, x] if i >= 0]
+                odd = set(sa) ^ set(sb)
+                for g in odd:
+                    for fr, u, v in ((a, x, y), (b, cam.W - 1 - x, cam.H - 1 - y)):
+                        assert abs(_alpha_f64(fr, g, u, v) * 255.0 - 1.0) < 1e-4, (view, y, x, g)
+                assert [g for g in sa if g not in odd] == [g for g in sb if g not in odd], (view, y, x)
+    assert n_diff <= 1e-3 * n_pix, n_diff
 
 
 def test_hier_sorts_better_than_global_and_queue_invariants():
