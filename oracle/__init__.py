@@ -78,6 +78,9 @@ def lib():
         L.oracle_ray_f32.argtypes = [C.c_void_p, C.c_float, C.c_float, C.c_void_p]
         L.oracle_backward_f64.restype = C.c_int
         L.oracle_backward_f32.restype = C.c_int
+        L.oracle_grad2d_f64.restype = C.c_int
+        L.oracle_chain_f64.restype = C.c_int
+        L.oracle_chain_f32.restype = C.c_int
         _lib = L
     return _lib
 
@@ -264,3 +267,41 @@ def backward(scene, cam, dL_drgb, precision="f64", head=4, mode=MODE_HIER, bg=(0
     if rc != 0:
         raise RuntimeError("oracle backward failed: %d" % rc)
     return rgb, g, int(sig[0])
+
+
+GRAD2D_NAMES = ("mean_x", "mean_y", "conic_a", "conic_b", "conic_c", "opacity", "r", "g", "b")
+
+
+def grad2d(scene, cam, dL_drgb, head=4, mode=MODE_HIER, bg=(0.0, 0.0, 0.0)):
+    """Float64 gradients of sum(dL_drgb * rgb) with respect to every
+    Gaussian's 2D quantities [N,9] (GRAD2D_NAMES order), a bound [N,9] on the
+    magnitudes each is summed from, and the number of blends [N]."""
+    L = lib()
+    n = scene.n
+    g2 = np.zeros((n, 9), np.float64)
+    bd = np.zeros((n, 9), np.float64)
+    nt = np.zeros(n, np.int32)
+    dL = np.ascontiguousarray(dL_drgb, dtype=np.float64)
+    oc, of = ocam(cam), ocfg(mode=mode, head=head, bg=bg)
+    rc = L.oracle_grad2d_f64(C.c_int(n), C.c_int(scene.sh_degree), *map(_p, _scene_arrays(scene)), C.byref(oc),
+                             C.byref(of), _p(dL), _p(g2), _p(bd), _p(nt))
+    if rc != 0:
+        raise RuntimeError("oracle grad2d failed: %d" % rc)
+    return g2, bd, nt
+
+
+def chain(scene, cam, g2, mode=MODE_HIER, precision="f64"):
+    """Parameter gradients from given 2D gradients g2 [N,9], computed in
+    float64 (or in float32 arithmetic with ``precision="f32"``)."""
+    L = lib()
+    n, K = scene.n, (scene.sh_degree + 1) ** 2
+    g = dict(means=np.zeros((n, 3)), scales=np.zeros((n, 3)), rots=np.zeros((n, 4)), opacities=np.zeros(n),
+             sh=np.zeros((n, K, 3)))
+    g2 = np.ascontiguousarray(g2, dtype=np.float64)
+    oc, of = ocam(cam), ocfg(mode=mode)
+    fn = L.oracle_chain_f64 if precision == "f64" else L.oracle_chain_f32
+    rc = fn(C.c_int(n), C.c_int(scene.sh_degree), *map(_p, _scene_arrays(scene)), C.byref(oc), C.byref(of),
+            _p(g2), _p(g["means"]), _p(g["scales"]), _p(g["rots"]), _p(g["opacities"]), _p(g["sh"]))
+    if rc != 0:
+        raise RuntimeError("oracle chain failed: %d" % rc)
+    return g

@@ -929,7 +929,14 @@ template <class F> struct G2 {
     F mx = 0, my = 0, ca = 0, cb = 0, cc = 0, op = 0, rgb[3] = {0, 0, 0};
 };
 
-template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const float bg[3], std::vector<G2<F>>& g2) {
+// With `bound` given, each 2D component also accumulates a bound on the
+// magnitudes its terms are computed from (every difference and sum of the
+// term taken with absolute values), and `nterms` counts the Gaussian's blends:
+// a float32 evaluation of the same sums in any order differs from the exact
+// ones by at most about (nterms + ops per term) * 2^-24 * bound (first-order
+// running-error analysis).  The bound carries no gradient information.
+template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const float bg[3], std::vector<G2<F>>& g2,
+                                        std::vector<G2<F>>* bound = nullptr, std::vector<int>* nterms = nullptr) {
     const Cam<F>& cam = fr.cam;
     const size_t P = (size_t)cam.W * cam.H;
     for (int y = 0; y < cam.H; ++y)
@@ -943,12 +950,19 @@ template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const f
                 const F a = px.alphas[k];
                 const Rec<F>& g = fr.recs[id];
                 for (int ch = 0; ch < 3; ++ch) Cacc[ch] = Cacc[ch] + (g.rgb[ch] * a) * T;
-                F ga = 0;
+                F ga = 0, ga_m = 0;
                 for (int ch = 0; ch < 3; ++ch) {
                     const F dl = dL[ch * P + p];
                     g2[id].rgb[ch] += dl * a * T;
                     ga += dl * (g.rgb[ch] * T - (px.C[ch] - Cacc[ch] + TN * (F)bg[ch]) / (F(1) - a));
+                    if (bound) {
+                        (*bound)[id].rgb[ch] += std::abs(dl) * a * T;
+                        ga_m += std::abs(dl) * (std::abs(g.rgb[ch]) * T +
+                                                (std::abs(px.C[ch]) + std::abs(Cacc[ch]) + TN * std::abs((F)bg[ch])) /
+                                                    (F(1) - a));
+                    }
                 }
+                if (nterms) (*nterms)[id] += 1;
                 const F pw = power_at(g, (F)x, (F)y);
                 const F G = expE(pw);
                 if (g.op * G < F(0.99)) {
@@ -960,6 +974,16 @@ template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const f
                     g2[id].ca += gp * (F(-0.5) * dx * dx);
                     g2[id].cb += gp * (-dx * dy);
                     g2[id].cc += gp * (F(-0.5) * dy * dy);
+                    if (bound) {
+                        G2<F>& b = (*bound)[id];
+                        const F gm = ga_m * a, adx = std::abs(dx), ady = std::abs(dy);
+                        b.op += ga_m * G;
+                        b.mx += gm * (std::abs(g.ca) * adx + std::abs(g.cb) * ady);
+                        b.my += gm * (std::abs(g.cc) * ady + std::abs(g.cb) * adx);
+                        b.ca += gm * (F(0.5) * adx * adx);
+                        b.cb += gm * (adx * ady);
+                        b.cc += gm * (F(0.5) * ady * ady);
+                    }
                 }
                 T = T * (F(1) - a);
             }
@@ -1256,6 +1280,34 @@ static int backward_impl(int n, int deg, const float* means, const float* scales
     return 0;
 }
 
+// Chain rule alone: parameter gradients of every Gaussian from given 2D
+// gradients g2_in [N,9] (same component order as oracle_grad2d_f64), in
+// float64 or float32 arithmetic.
+template <class F>
+static int chain_impl(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                      const float* sh, const OCam* cam, const OCfg* cfg, const double* g2_in, double* dmeans,
+                      double* dscales, double* drots, double* dopac, double* dsh) {
+    if (n < 0 || deg < 0 || deg > 3) return -1;
+    const Cam<F> C(*cam);
+    const int K = (deg + 1) * (deg + 1);
+    for (int i = 0; i < n; ++i) {
+        Rec<F> r;
+        preprocess_one<F>(C, cfg->mode, deg, means + 3 * i, scales + 3 * i, rots + 4 * i, opac[i], sh + 3 * K * i, r);
+        G2<F> g;
+        const double* q = g2_in + 9 * i;
+        g.mx = (F)q[0]; g.my = (F)q[1]; g.ca = (F)q[2]; g.cb = (F)q[3]; g.cc = (F)q[4]; g.op = (F)q[5];
+        g.rgb[0] = (F)q[6]; g.rgb[1] = (F)q[7]; g.rgb[2] = (F)q[8];
+        F dm[3], ds[3], dq[4], dop, dsh_[48];
+        backward_gaussian<F>(C, deg, means + 3 * i, scales + 3 * i, rots + 4 * i, sh + 3 * K * i, r, g, dm, ds, dq,
+                             &dop, dsh_);
+        for (int j = 0; j < 3; ++j) { dmeans[3 * i + j] = dm[j]; dscales[3 * i + j] = ds[j]; }
+        for (int j = 0; j < 4; ++j) drots[4 * i + j] = dq[j];
+        dopac[i] = dop;
+        for (int k = 0; k < 3 * K; ++k) dsh[3 * K * i + k] = dsh_[k];
+    }
+    return 0;
+}
+
 extern "C" {
 
 int oracle_frame_f32(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
@@ -1282,6 +1334,44 @@ int oracle_backward_f32(int n, int deg, const float* means, const float* scales,
                         float* dscales, float* drots, float* dopac, float* dsh, float* rgb, uint64_t* sig) {
     return backward_impl<float>(n, deg, means, scales, rots, opac, sh, cam, cfg, dL, dmeans, dscales, drots, dopac, dsh,
                                 rgb, sig);
+}
+
+// 2D gradients of one frame (float64): per Gaussian the 9 components
+// (mean x, mean y, conic a, b, c, opacity, r, g, b) of d(sum dL * rgb), the
+// magnitude bound of each (see backward_blends) and the number of blends.
+int oracle_grad2d_f64(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                      const float* sh, const OCam* cam, const OCfg* cfg, const double* dL, double* g2_out,
+                      double* bound_out, int32_t* nterms_out) {
+    if (n < 0 || deg < 0 || deg > 3) return -1;
+    Frame<double> fr(*cam, *cfg);
+    run_frame<double>(fr, n, deg, means, scales, rots, opac, sh, nullptr);
+    std::vector<G2<double>> g2(n), bd(n);
+    std::vector<int> nt(n, 0);
+    backward_blends(fr, dL, cfg->bg, g2, &bd, &nt);
+    auto put = [](const G2<double>& g, double* o) {
+        o[0] = g.mx; o[1] = g.my; o[2] = g.ca; o[3] = g.cb; o[4] = g.cc; o[5] = g.op;
+        o[6] = g.rgb[0]; o[7] = g.rgb[1]; o[8] = g.rgb[2];
+    };
+    for (int i = 0; i < n; ++i) {
+        put(g2[i], g2_out + 9 * i);
+        put(bd[i], bound_out + 9 * i);
+        nterms_out[i] = nt[i];
+    }
+    return 0;
+}
+
+int oracle_chain_f64(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                     const float* sh, const OCam* cam, const OCfg* cfg, const double* g2_in, double* dmeans,
+                     double* dscales, double* drots, double* dopac, double* dsh) {
+    return chain_impl<double>(n, deg, means, scales, rots, opac, sh, cam, cfg, g2_in, dmeans, dscales, drots, dopac,
+                              dsh);
+}
+
+int oracle_chain_f32(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
+                     const float* sh, const OCam* cam, const OCfg* cfg, const double* g2_in, double* dmeans,
+                     double* dscales, double* drots, double* dopac, double* dsh) {
+    return chain_impl<float>(n, deg, means, scales, rots, opac, sh, cam, cfg, g2_in, dmeans, dscales, drots, dopac,
+                             dsh);
 }
 
 // ----- element functions exposed for the pins -----

@@ -541,7 +541,11 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const TileList tl = tile_list(a, range_tile);
     if (tl.skip) return 0u;
     const uint32_t* list = tl.ids;
-    const uint32_t end = tl.len;
+    // A truncated prefix is walked in whole batches only: the last, partial
+    // batch of a prefix is not the batch the whole list has at that place,
+    // and the pops that follow it could differ.  The strip is then flagged
+    // unless its pixels finished within the whole batches.
+    const uint32_t end = tl.truncated ? (tl.len & ~(uint32_t)(kBatch - 1)) : tl.len;
     const bool truncated = tl.truncated;
     const uint32_t begin = 0;
     uint32_t b0 = begin;

@@ -159,3 +159,20 @@ def test_batch_fewer_tiles_than_work_queues():
             _assert_same(_frames_np(b.render()), ref)
         if prefix:
             assert int(b.counters()[6].item()) > 0
+
+
+def test_batch_truncated_prefix_walks_whole_batches_only():
+    # The constructed tile whose 40-entry prefix ends in a partial batch (see
+    # test_prefix_cases.py), among other views of a batch.
+    from micro_scenes import PREFIX_M, cam16, prefix_partial_batch_scene
+    from paper_2402_00525_amd import gsr
+    sc, _ = prefix_partial_batch_scene()
+    scenes = [sc, synth.uniform_scene(2000, seed=0, sh_degree=0)]
+    views = [(0, cam16()), (1, synth.front_camera(64, 64)), (0, cam16())]
+    say("case: batch, truncated prefix ending in a partial batch")
+    b, _ = _batch(scenes, views, cfg=gsr.config(sort_prefix=PREFIX_M))
+    got = _frames_np(b.render())
+    o = oracle.frame(sc, cam16(), mode=oracle.MODE_HIER)
+    for k in (0, 2):
+        np.testing.assert_array_equal(got[k]["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+        np.testing.assert_array_equal(got[k]["count"], o.count)

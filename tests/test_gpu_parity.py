@@ -63,7 +63,7 @@ def test_small_scene_bit_exact(mode):
     np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
 
 
-@pytest.mark.parametrize("head", [1, 2, 3, 8, 16, 24])
+@pytest.mark.parametrize("head", [1, 2, 3, 6, 8, 12, 16, 20, 24])
 def test_head_sizes_bit_exact(head):
     sc, cam = synth.workload_small()
     cam = synth.orbit_camera(128, 96, view=5)
@@ -358,3 +358,90 @@ def test_overflow_grows_workspace():
     out = r.render(ds, cam, gsr.config(), max_k=8)
     o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=8)
     np.testing.assert_array_equal(out.blend_ids.cpu().numpy(), o.blend_ids)
+
+
+def test_truncated_prefix_walks_whole_batches_only():
+    """A prefix of 40 entries ends in a partial batch.  Rendered as it is, the
+    tail's first pop after that batch would terminate every pixel with blend
+    orders that differ from the whole list's (the premise is checked on the
+    CPU in test_prefix_cases.py), and the tile would not be flagged.  The
+    render must stop at the last whole batch, flag the tile, and give the
+    whole list's result."""
+    from micro_scenes import PREFIX_M, cam16, prefix_partial_batch_scene
+    sc, _ = prefix_partial_batch_scene()
+    cam = cam16()
+    say("case: truncated prefix ending in a partial batch")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=16)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=16, sort_prefix=PREFIX_M)
+    L = g["lists"]
+    assert L["fallback_tiles"] == 1 and int(L["tile_flag"][0]) == 64
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["count"], o.count)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+
+
+def _bench_tile_mask(cam, flag, seed, n_random=24):
+    """Tiles to check on a benchmark frame: every tile the prefix pass
+    flagged, eight tiles of the bottom (partial) tile row, and a seeded
+    random sample."""
+    tx, ty = (cam.W + 15) // 16, (cam.H + 15) // 16
+    rng = np.random.default_rng(seed)
+    mask = np.zeros(tx * ty, np.uint8)
+    mask[np.nonzero(flag)[0]] = 1
+    mask[(ty - 1) * tx + rng.choice(tx, 8, replace=False)] = 1
+    mask[rng.choice(tx * ty, n_random, replace=False)] = 1
+    return mask
+
+
+@pytest.mark.parametrize("n,seed,view", [(3_000_000, 2, 5), (3_000_000, 2, 24), (1_000_000, 1, 0)])
+def test_benchmark_frames_on_sampled_tiles(n, seed, view):
+    """The benchmarked frames themselves (mixture scenes of 3M and 1M
+    Gaussians at 1920x1080, orbit views) in the launch configuration the
+    benchmark times: per-Gaussian records and tile counts of every Gaussian,
+    the ranges of every tile, and on a sample of tiles (all flagged tiles,
+    part of the partial bottom row, random ones) the sorted lists, per-pixel
+    blend order and images, bit for bit against the oracle rendering only
+    those tiles."""
+    from paper_2402_00525_amd import gsr
+    sc = synth.mixture_scene(n, seed=seed)
+    cam = synth.orbit_camera(1920, 1080, view)
+    say("case: benchmark frame, %d Gaussians, seed %d, view %d" % (n, seed, view))
+    ds = gsr.DeviceScene.from_host(sc)
+    r = gsr.Renderer(entries_hint=32 * n)
+    plain = r.render(ds, cam, gsr.config())                 # the benchmarked kernels
+    torch.cuda.synchronize()
+    img = {k: getattr(plain, k).cpu().numpy().copy() for k in ("rgb", "depth", "count", "T")}
+    lists = r.tile_lists(n, cam)
+    rec = {k: v.cpu().numpy() for k, v in r.records(n, cam).items()}
+    dbg = r.render(ds, cam, gsr.config(), max_k=16)         # same frame, with blend-id lists
+    torch.cuda.synchronize()
+    bids = dbg.blend_ids.cpu().numpy()
+    flag = lists["tile_flag"].view(np.uint32)
+    mask = _bench_tile_mask(cam, flag, seed=view)
+    say("  flagged tiles %d, checked tiles %d" % (int((flag > 0).sum()), int(mask.sum())))
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=16, tile_mask=mask)
+    np.testing.assert_array_equal(rec["touched"], o.touched)
+    for k in ("xy", "conic_o", "sw", "zd"):
+        np.testing.assert_array_equal(rec[k].view(np.uint32), getattr(o, k).view(np.uint32))
+    np.testing.assert_array_equal(lists["ranges"].view(np.uint32), o.ranges)
+    ov = o.values.view(np.uint32)
+    pre, plen = lists["pre_vals"].view(np.uint32), lists["pre_len"]
+    tx = (cam.W + 15) // 16
+    pix = np.zeros((cam.H, cam.W), bool)
+    for t in np.nonzero(mask)[0]:
+        rb, re = (int(v) for v in o.ranges[t])
+        c = int(plen[t])
+        if flag[t]:
+            assert c == re - rb
+        else:
+            assert c <= min(re - rb, 1024)
+        np.testing.assert_array_equal(pre[rb:rb + c], ov[rb:rb + c])
+        y0, x0 = (t // tx) * 16, (t % tx) * 16
+        pix[y0:y0 + 16, x0:x0 + 16] = True
+    np.testing.assert_array_equal(bids[pix], o.blend_ids[pix])
+    np.testing.assert_array_equal(img["count"][pix], o.count[pix])
+    np.testing.assert_array_equal(img["rgb"][:, pix].view(np.uint32), o.rgb[:, pix].view(np.uint32))
+    for k in ("depth", "T"):
+        np.testing.assert_array_equal(img[k][pix].view(np.uint32), getattr(o, k)[pix].view(np.uint32))
+    np.testing.assert_array_equal(dbg.rgb.cpu().numpy().view(np.uint32), img["rgb"].view(np.uint32))

@@ -38,7 +38,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2402_00525_amd import synth
+from micro_scenes import cam16, e_of, scene_of
 
 Z0, DZ = 4.0, 0.01
 
@@ -48,32 +48,8 @@ def _built(oracle_lib):
     return oracle_lib
 
 
-def cam16():
-    return synth.Camera(R=np.eye(3, dtype=np.float32), t=np.zeros(3, np.float32), center=np.zeros(3, np.float32),
-                        fx=8.0, fy=8.0, cx=7.5, cy=7.5, W=16, H=16)
-
-
-def a_of(u):
-    return (u - 7.5) / 8.0
-
-
-def e_of(m, u, v):
-    return m[2] + a_of(u) * m[0] + a_of(v) * m[1]
-
-
 def z(k):
     return Z0 + DZ * k
-
-
-def scene_of(gauss):
-    """gauss: list of (mean, scale, opacity); isotropic, SH degree 0, grey."""
-    n = len(gauss)
-    means = np.array([g[0] for g in gauss], np.float32)
-    scales = np.array([[g[1]] * 3 for g in gauss], np.float32)
-    rots = np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1))
-    opac = np.array([g[2] for g in gauss], np.float32)
-    sh = np.zeros((n, 1, 3), np.float32)
-    return synth.Scene(means, scales, rots, opac, sh, 0)
 
 
 def axis(k):
