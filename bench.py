@@ -284,7 +284,7 @@ def fwd_bwd(steps, warmup):
         if evs is not None:
             evs[1].record()
         dL = torch.sign(out.rgb - target) / out.rgb.numel()
-        g = gsr.render_backward(r, ds, cam, cfg, out, dL)
+        g = gsr.render_backward(r, ds, cam, cfg, out, dL, check=False)
         if evs is not None:
             evs[2].record()
         return g
@@ -302,7 +302,7 @@ def fwd_bwd(steps, warmup):
     t1.record()
     torch.cuda.synchronize()
     if int(r.status.item()) != 0:
-        raise RuntimeError("overflow during fwd+bwd timing")
+        raise RuntimeError("overflow or workspace mismatch during fwd+bwd timing")
     fwd = mean([e[0].elapsed_time(e[1]) for e in evs])
     bwd = mean([e[1].elapsed_time(e[2]) for e in evs])
     return {"ms_per_step": round(t0.elapsed_time(t1) / steps, 4), "forward_ms": round(fwd, 4),

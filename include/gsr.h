@@ -63,7 +63,11 @@ enum {
  *                    front whenever the window overflows. */
 enum { GSR_MODE_GLOBAL = 0, GSR_MODE_HIER = 1, GSR_MODE_FULL = 2, GSR_MODE_WINDOW = 3 };
 
-enum { GSR_STATUS_OVERFLOW = 1 };
+/* Bits of *status_dev: GSR_STATUS_OVERFLOW, more tile entries than the
+ * workspace holds (outputs undefined); GSR_STATUS_MISMATCH, a backward call
+ * whose workspace does not hold the forward of the same scene, camera and
+ * configuration (its gradients are then zero). */
+enum { GSR_STATUS_OVERFLOW = 1, GSR_STATUS_MISMATCH = 2 };
 
 /* Ablations of GSR_MODE_HIER (Sec. 4.3, Table performance_ablation), bits of
  * gsr_config.flags:
@@ -229,15 +233,18 @@ int gsr_render_sort_error(const gsr_scene* scene, const gsr_camera* cam, const g
  *   dmeans [N,3], dscales [N,3], drots [N,4] (unnormalised quaternion),
  *   dopacities [N], dsh [N,(d+1)^2,3]   (device, float32, overwritten).
  * scene, cam, cfg and ws must be exactly those of the forward call, and ws
- * unmodified since.  The order of floating-point atomic additions makes the
- * gradients reproducible only to rounding.  No gradient flows through the
- * blend order, culling or early termination (they are piecewise constant),
- * nor through the depth output.  Returns GSR_EUNSUPPORTED for the global
- * order. */
+ * unmodified since: the forward leaves a fingerprint of its scene arrays,
+ * sizes, camera and configuration in ws, and a backward whose arguments do
+ * not match it adds nothing (zero gradients) and sets GSR_STATUS_MISMATCH in
+ * *status_dev (checked on the device; status_dev may be NULL).  The order of
+ * floating-point atomic additions makes the gradients reproducible only to
+ * rounding.  No gradient flows through the blend order, culling or early
+ * termination (they are piecewise constant), nor through the depth output.
+ * Returns GSR_EUNSUPPORTED for the global order. */
 int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                         size_t ws_bytes, const float* dL_drgb, const float* rgb, const float* T_final,
                         float* dmeans, float* dscales, float* drots, float* dopacities, float* dsh,
-                        gsr_stream_t stream);
+                        int32_t* status_dev, gsr_stream_t stream);
 
 /* As gsr_render, and records caller-created HIP events (hipEvent_t, passed
  * as void*) on the stream at the stage boundaries of the paper's per-stage

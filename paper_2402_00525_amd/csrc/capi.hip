@@ -192,6 +192,58 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     return b;
 }
 
+// Fingerprint of a frame: what the workspace's lists and records depend on
+// (scene arrays and sizes, camera, blend order and queue configuration).  The
+// forward writes it to counters[8..11]; the backward compares it with its own
+// arguments on the device (no host synchronisation).
+void frame_fingerprint(const gsr_scene* sc, const gsr_camera* c, const gsr_config* cfg, uint32_t out[4]) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    auto mixf = [&](float f) {
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        mix(u);
+    };
+    mix((uint64_t)(uint32_t)sc->sh_degree);
+    mix((uint64_t)(uintptr_t)sc->means);
+    mix((uint64_t)(uintptr_t)sc->scales);
+    mix((uint64_t)(uintptr_t)sc->rots);
+    mix((uint64_t)(uintptr_t)sc->opacities);
+    mix((uint64_t)(uintptr_t)sc->sh);
+    for (int k = 0; k < 9; ++k) mixf(c->R[k]);
+    for (int k = 0; k < 3; ++k) {
+        mixf(c->t[k]);
+        mixf(c->center[k]);
+    }
+    mixf(c->fx);
+    mixf(c->fy);
+    mixf(c->cx);
+    mixf(c->cy);
+    mixf(c->znear);
+    mix((uint64_t)(uint32_t)cfg->mode);
+    mix((uint64_t)(uint32_t)cfg->head);
+    mix((uint64_t)cfg->flags);
+    mix((uint64_t)(uint32_t)cfg->sort_prefix);
+    out[0] = (uint32_t)sc->n;
+    out[1] = ((uint32_t)c->W & 0xffffu) | ((uint32_t)c->H << 16);
+    out[2] = (uint32_t)h;
+    out[3] = (uint32_t)(h >> 32);
+}
+
+__global__ void k_write_words(uint32_t* dst, uint4 v) {
+    if (threadIdx.x == 0) {
+        dst[0] = v.x;
+        dst[1] = v.y;
+        dst[2] = v.z;
+        dst[3] = v.w;
+    }
+}
+
 // Entries per tile sorted up front.  The 3DGS lists (global order, resort
 // window) keep every rectangle tile and reach deeper before their pixels
 // finish, so their default prefix is longer.
@@ -280,6 +332,13 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     };
     if ((e = mark(0)) != hipSuccess) return fail_hip(e, "event");
     if ((e = gsr::launch_fill_u32(b.counters, 16, 0u, s)) != hipSuccess) return fail_hip(e, "clear");
+    {
+        uint32_t fp[gsr::kFingerprintWords];
+        frame_fingerprint(scene, cam, cfg, fp);
+        hipLaunchKernelGGL(k_write_words, dim3(1), dim3(64), 0, s, b.counters + gsr::kFingerprintOffset,
+                           make_uint4(fp[0], fp[1], fp[2], fp[3]));
+        if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "fingerprint");
+    }
     // Hierarchical lists use grouped duplication (entries bucketed by their
     // low tile bits), the global order duplication at per-Gaussian offsets.
     const gsr::DupGroups grp{b.dhist, (uint32_t)dup_workgroups(scene->n), 0u, 0u};
@@ -371,7 +430,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
 
 int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws, size_t ws_bytes,
                   const float* dL, const float* rgb, const float* T_final, float* dmeans, float* dscales, float* drots,
-                  float* dopac, float* dsh, gsr_stream_t stream) {
+                  float* dopac, float* dsh, int32_t* status_dev, gsr_stream_t stream) {
     int rc = check_scene(scene);
     if (rc) return rc;
     if ((rc = check_camera(cam))) return rc;
@@ -414,6 +473,9 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     ra.T_in = T_final;
     ra.grad2d = g2;
     ra.flags = (int)cfg->flags;
+    ra.fp = b.counters + gsr::kFingerprintOffset;
+    frame_fingerprint(scene, cam, cfg, ra.fp_expect);
+    ra.status = status_dev;
     set_prefix_lists(ra, b, gsr::kListSorted);
     if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render backward");
     if ((e = gsr::launch_preprocess_backward(sc, dc, b.co, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
@@ -666,6 +728,13 @@ std::string batch_key(const gsr_batch* b) {
 
 }  // namespace
 
+namespace {
+// The schedules gsr_batch_set_schedule accepts (and the autotuner may reuse).
+bool schedule_valid(const gsr_schedule& c) {
+    return c.wgs_per_cu >= 1 && c.wgs_per_cu <= 8 && (c.cost_order == 0 || c.cost_order == 1) && c.lb_threshold >= 0;
+}
+}  // namespace
+
 extern "C" {
 
 size_t gsr_batch_workspace_bytes(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
@@ -750,8 +819,7 @@ int gsr_batch_render(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream) {
 }
 
 int gsr_batch_set_schedule(gsr_batch* b, const gsr_schedule* sched) {
-    if (!b || !sched || sched->wgs_per_cu < 1 || sched->wgs_per_cu > 8 || sched->lb_threshold < 0)
-        return fail(GSR_EINVAL, "bad schedule");
+    if (!b || !sched || !schedule_valid(*sched)) return fail(GSR_EINVAL, "bad schedule");
     b->sched = *sched;
     return GSR_OK;
 }
@@ -777,8 +845,10 @@ int gsr_batch_tune(gsr_batch* b, int32_t* status_dev, gsr_stream_t stream, const
         std::string k;
         gsr_schedule c;
         float ms;
+        // A line that does not hold a valid schedule (a stale or damaged
+        // cache) is ignored, and the batch is tuned again.
         while (in >> k >> c.wgs_per_cu >> c.cost_order >> c.lb_threshold >> ms) {
-            if (k == key) {
+            if (k == key && schedule_valid(c) && ms > 0.0f) {
                 b->sched = c;
                 if (best_out) *best_out = c;
                 if (best_ms) *best_ms = ms;
@@ -914,9 +984,10 @@ int gsr_render_work(const gsr_scene* scene, const gsr_camera* cam, const gsr_con
 
 int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, void* ws,
                         size_t ws_bytes, const float* dL_drgb, const float* rgb, const float* T_final, float* dmeans,
-                        float* dscales, float* drots, float* dopacities, float* dsh, gsr_stream_t stream) {
+                        float* dscales, float* drots, float* dopacities, float* dsh, int32_t* status_dev,
+                        gsr_stream_t stream) {
     return backward_impl(scene, cam, cfg, ws, ws_bytes, dL_drgb, rgb, T_final, dmeans, dscales, drots, dopacities, dsh,
-                         stream);
+                         status_dev, stream);
 }
 
 int gsr_sort_passes(int32_t W, int32_t H) {

@@ -32,7 +32,8 @@ struct FrameBufs {
     uint32_t* vals[2];
     uint32_t* hist;           // radix histograms, kSortMaxBins x sort blocks
     uint32_t* ranges;         // [tiles][2]
-    uint32_t* counters;       // [0] entries, [1] consumed, [3] entries needed, [4] fallback flag, [5] gated n
+    uint32_t* counters;       // [0] entries, [1] consumed, [3] entries needed, [5] / [6] fallback entries /
+                              // tiles, [8..11] the frame's fingerprint (checked by the backward)
     uint32_t capacity;
     uint32_t* pre_vals;       // [capacity] sorted prefix ids at each tile's range begin
     uint32_t* pre_len;        // [tiles]
@@ -161,7 +162,16 @@ struct RenderArgs {
     uint32_t* tile_flag;
     int flags;  // kAblateHierCull: no culling at the 4x4 and 2x2 levels
     unsigned long long* work;  // if set: the hierarchical render counts its evaluations (head 4 only)
+    // backward only: the fingerprint the forward left in the workspace (fp,
+    // kFingerprintWords words) and the one this call expects; on a mismatch
+    // the backward render adds nothing and sets kStatusMismatch in *status
+    const uint32_t* fp;
+    uint32_t fp_expect[4];
+    int32_t* status;
 };
+constexpr int kFingerprintWords = 4;
+constexpr int kFingerprintOffset = 8;   // counters[8..11] of a frame's workspace
+constexpr int32_t kStatusMismatch = 2;
 enum { kListFull = 0, kListPrefix = 1, kListFlagged = 2, kListSorted = 3 };
 
 // Per-view descriptor of a batch, in device memory.

@@ -705,6 +705,17 @@ __global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
     __shared__ float s_acc[MODE == kBwd ? 9 * kAccSlots : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (MODE == kBwd) {
+        // The workspace must hold the forward of this scene, camera and
+        // configuration (the same decision for every thread of the grid).
+        if (a.fp) {
+            bool same = true;
+#pragma unroll
+            for (int k = 0; k < kFingerprintWords; ++k) same = same && a.fp[k] == a.fp_expect[k];
+            if (!same) {
+                if (blockIdx.x == 0 && threadIdx.x == 0 && a.status) atomicOr(a.status, kStatusMismatch);
+                return;
+            }
+        }
         for (int k = threadIdx.x; k < 9 * kAccSlots; k += 256) s_acc[k] = 0.0f;
         __syncthreads();
     }
@@ -812,6 +823,9 @@ __device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t s
     a.pre_len = b.pre_len;
     a.tile_flag = b.tile_flag;
     a.flags = b.flags;
+    a.work = nullptr;
+    a.fp = nullptr;
+    a.status = nullptr;
     render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)strip, q, nullptr);
 }
 

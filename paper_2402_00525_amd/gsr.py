@@ -22,6 +22,7 @@ MODE_GLOBAL, MODE_HIER, MODE_FULL, MODE_WINDOW = 0, 1, 2, 3
 ABLATE_TILE_DEPTH, ABLATE_TILE_CULL, ABLATE_HIER_CULL = 1, 2, 4
 NO_LOAD_BALANCE = 1 << 30
 STATUS_OVERFLOW = 1
+STATUS_MISMATCH = 2
 
 
 class GsrError(RuntimeError):
@@ -90,7 +91,7 @@ def lib():
                                             C.c_size_t] + [C.c_void_p] * 7
         L.gsr_render_backward.restype = C.c_int
         L.gsr_render_backward.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
-                                          C.c_size_t] + [C.c_void_p] * 9
+                                          C.c_size_t] + [C.c_void_p] * 10
         L.gsr_render_work.restype = C.c_int
         L.gsr_render_work.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                       C.c_size_t] + [C.c_void_p] * 6 + [C.c_void_p]
@@ -392,9 +393,11 @@ class RenderFunction(torch.autograd.Function):
         dm, dsc, drt = torch.empty_like(ds.means), torch.empty_like(ds.scales), torch.empty_like(ds.rots)
         dop, dsh = torch.empty_like(ds.opacities), torch.empty_like(ds.sh)
         sc, cc = ds.c_struct(), camera(cam)
+        # The workspace is this Function's own, untouched since the forward,
+        # so the fingerprint check cannot fail here; no synchronisation.
         _check(lib().gsr_render_backward(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(r.ws), r.ws.numel(),
                                          _ptr(g_rgb), _ptr(out.rgb), _ptr(out.T), _ptr(dm), _ptr(dsc), _ptr(drt),
-                                         _ptr(dop), _ptr(dsh), _stream()))
+                                         _ptr(dop), _ptr(dsh), _ptr(r.status), _stream()))
         ctx.state = None
         return dm, dsc, drt, dop, dsh, None, None
 
@@ -404,16 +407,26 @@ def render(means, scales, rots, opacities, sh, cam, cfg: CConfig | None = None):
     return RenderFunction.apply(means, scales, rots, opacities, sh, cam, cfg or config())
 
 
-def render_backward(renderer: Renderer, scene: DeviceScene, cam, cfg: CConfig, frame: Frame, dL_drgb):
-    """Gradients of a frame rendered with ``renderer.render`` (direct C-ABI call)."""
+def render_backward(renderer: Renderer, scene: DeviceScene, cam, cfg: CConfig, frame: Frame, dL_drgb,
+                    check: bool = True):
+    """Gradients of a frame rendered with ``renderer.render`` (direct C-ABI
+    call).  With ``check`` the call clears the renderer's status word,
+    synchronises once and raises if the renderer's workspace does not hold
+    the forward of this scene, camera and configuration (the library then
+    returns zero gradients); without it nothing waits and a mismatch only
+    sets bit 1 of the status word."""
     grads = dict(means=torch.empty_like(scene.means), scales=torch.empty_like(scene.scales),
                  rots=torch.empty_like(scene.rots), opacities=torch.empty_like(scene.opacities),
                  sh=torch.empty_like(scene.sh))
     sc, cc = scene.c_struct(), camera(cam)
+    if check:
+        renderer.status.zero_()
     _check(lib().gsr_render_backward(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(renderer.ws), renderer.ws.numel(),
                                      _ptr(dL_drgb.contiguous()), _ptr(frame.rgb), _ptr(frame.T), _ptr(grads["means"]),
                                      _ptr(grads["scales"]), _ptr(grads["rots"]), _ptr(grads["opacities"]),
-                                     _ptr(grads["sh"]), _stream()))
+                                     _ptr(grads["sh"]), _ptr(renderer.status), _stream()))
+    if check and int(renderer.status.item()) & STATUS_MISMATCH:
+        raise GsrError(GSR_EINVAL, "the workspace does not hold the forward of this scene, camera and configuration")
     return grads
 
 

@@ -121,6 +121,15 @@ def test_batch_autotune_and_cache(tmp_path):
     assert (best2.wgs_per_cu, best2.cost_order, best2.lb_threshold) == (best.wgs_per_cu, best.cost_order,
                                                                        best.lb_threshold)
     _assert_same(_frames_np(b.render()), ref)
+    # A damaged cache line for this batch (a schedule set_schedule would
+    # refuse) is ignored: the batch is tuned again and a valid line appended.
+    bad = str(tmp_path / "gsr_tune_bad.txt")
+    with open(bad, "w") as f:
+        f.write("%s 99 1 64 0.5\n%s 2 7 64 0.5\n%s 2 1 -5 0.5\n" % (line[0], line[0], line[0]))
+    best3, ms3 = b.tune(cache_path=bad, repeats=1)
+    assert 1 <= best3.wgs_per_cu <= 3 and best3.cost_order in (0, 1) and best3.lb_threshold in (32, 64, 128)
+    assert len(open(bad).read().splitlines()) == 4
+    _assert_same(_frames_np(b.render()), ref)
 
 
 def test_batch_prefix_fallback_matches():
