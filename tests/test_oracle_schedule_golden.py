@@ -227,3 +227,32 @@ def test_tail_pops_only_above_its_threshold():
     sc = scene_of([axis(k) for k in range(39)] + [(list(mV), 3.0, 0.5)])
     fr = oracle.frame(sc, cam16(), mode=oracle.MODE_HIER, head=4, max_k=48)
     assert blends_at(fr, 1, 1) == [V] + list(range(39))
+
+
+def test_tail_pops_after_every_batch_that_overfills_it():
+    """Scene U, default queues (64/8/4).  A_0..A_71 (ids 0..71) and U (id 72)
+    at m = (1, 1, 4.6), large (scale 3).  Sub-tile (0..3, 0..3); pixel (1, 1)
+    in quad (0..1, 0..1).
+
+    e of U: sub-tile 4.6 - 1.5 = 3.1, quad 4.6 - 1.75 = 2.85, pixel
+    4.6 - 1.625 = 2.975: nearest of all at every level.  List: |m_U| = 4.81 >
+    z_71 = 4.71, so U is the last entry (batch 2).
+    Tail: batch 0 (A0..A31) -> 32, no pop.  Batch 1 (A32..A63) -> 64: pop
+    [A0..A15], pop [A16..A31], 32 left.  Batch 2 (A64..A71, U) -> 41: pop
+    [U, A32..A46], 25 left; the end drains [A47..A62] and [A63..A71].
+    Mid: the first two chunks leave every run in index order; after them
+    A0..A27 have gone to the head and [A28..A31] wait.  The run [U, A32, A33,
+    A34] makes [U, A28..A34]: pop U, A28, A29, A30.  Head arrivals: A0..A27,
+    U, A28..A71.  Head (K = 4): when U arrives it holds [A24..A27] (A0..A23
+    blended); U is inserted at the front and blended at once.
+    Blend order: A0..A23, U, A24..A71.
+    A tail that never popped during the list would drain U first (U, A0..);
+    one that popped already at 32 would send A0..A47 before U.
+    """
+    U = 72
+    mU = (1.0, 1.0, 4.6)
+    assert e_of(mU, 1.5, 1.5) < z(0) - 0.5 and e_of(mU, 0.5, 0.5) < z(0) - 0.5 and e_of(mU, 1, 1) < z(0) - 0.5
+    assert np.linalg.norm(mU) > z(71) + 0.04
+    sc = scene_of([axis(k) for k in range(72)] + [(list(mU), 3.0, 0.5)])
+    fr = oracle.frame(sc, cam16(), mode=oracle.MODE_HIER, head=4, max_k=80)
+    assert blends_at(fr, 1, 1) == list(range(24)) + [U] + list(range(24, 72))
