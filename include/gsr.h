@@ -82,6 +82,14 @@ enum { GSR_STATUS_OVERFLOW = 1, GSR_STATUS_MISMATCH = 2 };
 enum { GSR_ABLATE_TILE_DEPTH = 1, GSR_ABLATE_TILE_CULL = 2, GSR_ABLATE_HIER_CULL = 4 };
 #define GSR_NO_LOAD_BALANCE (1 << 30)
 
+/* Variant of GSR_MODE_GLOBAL (Sec. 3.3, Fig. pertiledepth), a bit of
+ * gsr_config.flags: GSR_TILE_CENTRE_DEPTH keys every tile entry with t_opt
+ * along the ray through the tile's centre (the centre of its pixel-centre
+ * hull) instead of the view-space depth; the 3DGS rectangle and the blend in
+ * list order are unchanged (the naive per-tile depth, without per-pixel
+ * resorting). */
+enum { GSR_TILE_CENTRE_DEPTH = 8 };
+
 /* Gaussians of one scene (Sec. 2.1): N rows per array, row-major, float32.
  *   means     [N,3]  centre mu
  *   scales    [N,3]  activated scales s (> 0)
@@ -129,7 +137,8 @@ typedef struct gsr_config {
     int32_t batch, tail, pop, mid, mid_batch, head;
     int32_t lb_threshold;
     float bg[3];
-    uint32_t flags;      /* GSR_ABLATE_* bits (GSR_MODE_HIER only), else 0 */
+    uint32_t flags;      /* GSR_ABLATE_* bits (GSR_MODE_HIER only), GSR_TILE_CENTRE_DEPTH
+                            (GSR_MODE_GLOBAL only), else 0 */
     int32_t sort_prefix; /* speed only: entries per tile sorted up front (1..4096;
                             0 = 4096 for GSR_MODE_GLOBAL and GSR_MODE_WINDOW,
                             else 1024); see gsr_render */

@@ -104,6 +104,7 @@ def ocam(cam) -> OCam:
 # Ablations of the hierarchical mode (see the C++ source): no tile-depth
 # adjustment, no tile-based culling, no culling at the 4x4 / 2x2 levels.
 ABL_TILE_DEPTH, ABL_TILE_CULL, ABL_HIER_CULL = 1, 2, 4
+TILE_CENTRE_DEPTH = 8  # global order keyed along each tile's centre ray (Sec. 3.3)
 
 
 def ocfg(mode=MODE_HIER, head=4, tail=64, mid=8, batch=32, pop=16, mid_batch=4, bg=(0.0, 0.0, 0.0),

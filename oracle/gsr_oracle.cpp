@@ -215,7 +215,10 @@ struct OCfg {
 //   ABL_TILE_CULL   (D) no tile-based culling: every rectangle tile is kept;
 //   ABL_HIER_CULL   (E) no culling at the 4x4 and 2x2 levels of the render.
 // Load balancing (C) changes no result and has no switch here.
-enum { ABL_TILE_DEPTH = 1, ABL_TILE_CULL = 2, ABL_HIER_CULL = 4 };
+// The global (3DGS) order has one variant (Sec. 3.3, Fig. pertiledepth):
+//   TILE_CENTRE_DEPTH  every entry of a tile is keyed by t_opt along the ray
+//                   through the tile's centre instead of the view depth.
+enum { ABL_TILE_DEPTH = 1, ABL_TILE_CULL = 2, ABL_HIER_CULL = 4, TILE_CENTRE_DEPTH = 8 };
 
 enum { MODE_GLOBAL = 0, MODE_HIER = 1, MODE_FULL = 2, MODE_WINDOW = 3 };
 
@@ -525,9 +528,15 @@ template <class F> void emit_entries(const Cam<F>& cam, int mode, int flags, con
     for (int ty = g.rect[1]; ty <= g.rect[3]; ++ty)
         for (int tx = g.rect[0]; tx <= g.rect[2]; ++tx) {
             u32 tile = (u32)(ty * cam.tiles_x + tx);
-            if (gs_lists(mode)) { out.push_back({tile, ord_key(g.z), id}); continue; }
             F a, b, c, d, hx, hy;
             hull(cam, tx * 16, ty * 16, 16, a, b, c, d);
+            if (gs_lists(mode) && (flags & TILE_CENTRE_DEPTH)) {
+                F dir[3];
+                cam.ray(F(0.5) * (a + b), F(0.5) * (c + d), dir);
+                out.push_back({tile, ord_key(topt(g, dir)), id});
+                continue;
+            }
+            if (gs_lists(mode)) { out.push_back({tile, ord_key(g.z), id}); continue; }
             const bool keep = keep_block(g, a, b, c, d, hx, hy);
             if (!keep && !(flags & ABL_TILE_CULL)) continue;
             if (flags & ABL_TILE_DEPTH) { out.push_back({tile, ord_key(g.dist), id}); continue; }

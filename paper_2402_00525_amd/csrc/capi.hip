@@ -937,9 +937,12 @@ int gsr_check_config(const gsr_config* c) {
     if (c->mode != GSR_MODE_GLOBAL && c->mode != GSR_MODE_HIER && c->mode != GSR_MODE_FULL &&
         c->mode != GSR_MODE_WINDOW)
         return fail(GSR_EINVAL, "unknown mode");
-    if ((c->flags & ~(uint32_t)(GSR_ABLATE_TILE_DEPTH | GSR_ABLATE_TILE_CULL | GSR_ABLATE_HIER_CULL)) != 0)
-        return fail(GSR_EINVAL, "unknown flag");
-    if (c->flags != 0 && c->mode != GSR_MODE_HIER) return fail(GSR_EINVAL, "ablation flags apply to GSR_MODE_HIER");
+    const uint32_t ablate = GSR_ABLATE_TILE_DEPTH | GSR_ABLATE_TILE_CULL | GSR_ABLATE_HIER_CULL;
+    if ((c->flags & ~(ablate | (uint32_t)GSR_TILE_CENTRE_DEPTH)) != 0) return fail(GSR_EINVAL, "unknown flag");
+    if ((c->flags & ablate) != 0 && c->mode != GSR_MODE_HIER)
+        return fail(GSR_EINVAL, "ablation flags apply to GSR_MODE_HIER");
+    if ((c->flags & GSR_TILE_CENTRE_DEPTH) != 0 && c->mode != GSR_MODE_GLOBAL)
+        return fail(GSR_EINVAL, "GSR_TILE_CENTRE_DEPTH applies to GSR_MODE_GLOBAL");
     if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
     if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..4096");
     if (c->mode == GSR_MODE_HIER) {

@@ -660,12 +660,17 @@ __device__ __forceinline__ void put_entry(const DupArgs& a, uint32_t pos, uint32
     }
 }
 
-// Key depth of a kept tile: the view depth z (global order), the Gaussian's
+// Key depth of a kept tile: the view depth z (global order), t_opt along the
+// tile-centre ray (global order with naive per-tile depth, Sec. 3.3), the Gaussian's
 // distance (ablation without tile-depth adjustment), or t_opt along the ray
 // through the tile's maximum point x^ (Sec. 3.4).
 __device__ __forceinline__ uint32_t key_depth(const DupArgs& a, const Splat& h, float z, int tx, int ty) {
-    if (a.mode == kModeGlobal || (a.flags & kAblateTileDepth)) return depth_bits(z);
     float x0, x1, y0, y1;
+    if (a.mode == kModeGlobal && (a.flags & kTileCentreDepth)) {
+        tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+        return depth_bits(t_opt(h, cam_ray(a.cam, 0.5f * (x0 + x1), 0.5f * (y0 + y1))));
+    }
+    if (a.mode == kModeGlobal || (a.flags & kAblateTileDepth)) return depth_bits(z);
     tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
     const float2 xh = box_max_point(h, x0, x1, y0, y1);
     return depth_bits(t_opt(h, cam_ray(a.cam, xh.x, xh.y)));
@@ -685,7 +690,12 @@ __device__ __forceinline__ bool keep_and_depth(const DupArgs& a, const Splat& h,
             tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
             if (!block_clears(h, x0, x1, y0, y1)) return false;
         }
-        dbits = depth_bits(z);
+        if (a.mode == kModeGlobal && (a.flags & kTileCentreDepth)) {
+            tile_hull(a.cam, tx, ty, x0, x1, y0, y1);
+            dbits = depth_bits(t_opt(h, cam_ray(a.cam, 0.5f * (x0 + x1), 0.5f * (y0 + y1))));
+        } else {
+            dbits = depth_bits(z);
+        }
         return true;
     }
     tile_hull(a.cam, tx, ty, x0, x1, y0, y1);

@@ -10,7 +10,7 @@ namespace gsr {
 
 enum { kModeGlobal = 0, kModeHier = 1 };
 // Ablations of the hierarchical mode (bits of gsr_config.flags).
-enum { kAblateTileDepth = 1, kAblateTileCull = 2, kAblateHierCull = 4 };
+enum { kAblateTileDepth = 1, kAblateTileCull = 2, kAblateHierCull = 4, kTileCentreDepth = 8 };
 // lb_threshold at or above this: no load balancing (every lane walks its own
 // Gaussian's rectangle).
 constexpr int kNoLoadBalance = 1 << 30;

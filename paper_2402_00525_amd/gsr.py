@@ -20,6 +20,7 @@ MODE_GLOBAL, MODE_HIER, MODE_FULL, MODE_WINDOW = 0, 1, 2, 3
 # Ablations of the hierarchical mode (gsr_config.flags) and the load-balancing
 # threshold that turns load balancing off.
 ABLATE_TILE_DEPTH, ABLATE_TILE_CULL, ABLATE_HIER_CULL = 1, 2, 4
+TILE_CENTRE_DEPTH = 8
 NO_LOAD_BALANCE = 1 << 30
 STATUS_OVERFLOW = 1
 STATUS_MISMATCH = 2

@@ -50,6 +50,14 @@ def test_version_and_default_config(L):
         assert L.lib().gsr_check_config(C.byref(c)) == 0
     c.mode = L.MODE_GLOBAL
     assert L.lib().gsr_check_config(C.byref(c)) == -1    # ablations need GSR_MODE_HIER
+    c.flags = L.TILE_CENTRE_DEPTH                         # naive per-tile depth of the 3DGS order
+    assert L.lib().gsr_check_config(C.byref(c)) == 0
+    for m in (L.MODE_HIER, L.MODE_WINDOW, L.MODE_FULL):
+        c.mode = m
+        assert L.lib().gsr_check_config(C.byref(c)) == -1
+    c.mode = L.MODE_GLOBAL
+    c.flags = L.TILE_CENTRE_DEPTH | 1
+    assert L.lib().gsr_check_config(C.byref(c)) == -1
     c.flags = 0
     c.mode = L.MODE_WINDOW                                # per-ray window of `head` samples
     for K, code in ((1, 0), (24, 0), (25, -4), (0, -1)):
@@ -59,7 +67,7 @@ def test_version_and_default_config(L):
 
 @pytest.mark.parametrize("field,value,code", [
     ("tail", 48, -1), ("tail", 96, -4), ("mid", 6, -1), ("mid", 12, -4), ("head", 0, -1), ("head", 25, -4),
-    ("mode", 7, -1), ("mode", -1, -1), ("flags", 8, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
+    ("mode", 7, -1), ("mode", -1, -1), ("flags", 8, -1), ("flags", 16, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
     ("sort_prefix", 4097, -1)])
 def test_config_validation(L, field, value, code):
     # Sec. 3.4: tail = 32n+32, mid = 4m+4, head >= 1; only the built sizes run.

@@ -236,6 +236,32 @@ def test_ablations_bit_exact(flags):
     assert_images_close(g, o, TOL)
 
 
+@pytest.mark.parametrize("case", ["small", "mixture"])
+def test_tile_centre_depth_bit_exact(case):
+    """The 3DGS order with naive per-tile depth (Sec. 3.3, Fig. pertiledepth):
+    keys along each tile's centre ray, entries, blend order, image and
+    per-pixel sort error equal the oracle's."""
+    from paper_2402_00525_amd import gsr
+    if case == "small":
+        sc, _ = synth.workload_small()
+        cam = synth.orbit_camera(160, 112, view=13)
+    else:
+        sc = synth.subsample(synth.mixture_scene(100_000, seed=1), 8000)
+        cam = synth.orbit_camera(320, 180, view=3)
+    say("case: tile-centre depth", case)
+    o = oracle.frame(sc, cam, mode=oracle.MODE_GLOBAL, max_k=48, flags=oracle.TILE_CENTRE_DEPTH)
+    g = gpu_frame(sc, cam, mode=oracle.MODE_GLOBAL, max_k=48, flags=gsr.TILE_CENTRE_DEPTH)
+    assert_records_equal(g, o)
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    assert_images_close(g, o, TOL)
+    ds = gsr.DeviceScene.from_host(sc)
+    r = gsr.Renderer(entries_hint=1 << 18)
+    out, delta = r.render_sort_error(ds, cam, gsr.config(mode=oracle.MODE_GLOBAL, flags=gsr.TILE_CENTRE_DEPTH))
+    np.testing.assert_array_equal(delta.cpu().numpy().view(np.uint32), o.delta.view(np.uint32))
+
+
 def _big_gaussian_scene():
     sc = synth.uniform_scene(1500, seed=31, sh_degree=1)
     rng = np.random.default_rng(31)
