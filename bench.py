@@ -94,6 +94,9 @@ def parse():
                          "load-balancing thresholds, full per-pixel sort)")
     ap.add_argument("--no-sort-error", action="store_true",
                     help="skip the per-ray sort error of every renderer (two orbit views)")
+    ap.add_argument("--no-rotation", action="store_true",
+                    help="skip the pure-rotation popping sweep (views 0/15/30/45; yaw, pitch, roll of +-0.5/2/5 "
+                         "degrees and a 180-degree roll)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -163,7 +166,8 @@ def mode_sweep(ds, cams, n, sort_prefix):
     window over the 3DGS list (Sec. 3.3), the hierarchical render with larger
     heads, the ablations of Table performance_ablation -- (B) no tile-depth
     adjustment, (C) no load balancing, (D) no tile culling, (E) no
-    hierarchical culling --, a load-balancing threshold sweep, and the full
+    hierarchical culling --, a load-balancing threshold sweep, the 3DGS order
+    keyed along each tile's centre ray (Fig. pertiledepth), and the full
     per-pixel sort (Sec. 3.2).  Each: plan over the views, 2 untimed frames,
     then one timed frame per view."""
     import torch
@@ -178,6 +182,7 @@ def mode_sweep(ds, cams, n, sort_prefix):
               ("ablation_BCDE", dict(mode=H, lb_threshold=gsr.NO_LOAD_BALANCE,
                                      flags=gsr.ABLATE_TILE_DEPTH | gsr.ABLATE_TILE_CULL | gsr.ABLATE_HIER_CULL))]
     cases += [("lb_threshold_%d" % t, dict(mode=H, lb_threshold=t)) for t in (1, 4, 16, 32, 128, 256)]
+    cases += [("global_tile_centre_depth", dict(mode=gsr.MODE_GLOBAL, flags=gsr.TILE_CENTRE_DEPTH))]
     cases += [("full_sort", dict(mode=gsr.MODE_FULL))]
     res = {}
     for name, kw in cases:
@@ -201,7 +206,8 @@ def sort_errors(ds, cams, n):
     consecutive blends (0 for the full per-pixel sort)."""
     import torch
     from paper_2402_00525_amd import gsr
-    cases = [("global_3dgs", dict(mode=gsr.MODE_GLOBAL))]
+    cases = [("global_3dgs", dict(mode=gsr.MODE_GLOBAL)),
+             ("global_tile_centre_depth", dict(mode=gsr.MODE_GLOBAL, flags=gsr.TILE_CENTRE_DEPTH))]
     cases += [("window_K%d" % k, dict(mode=gsr.MODE_WINDOW, head=k)) for k in (4, 8, 16, 24)]
     cases += [("hier_K%d" % k, dict(mode=gsr.MODE_HIER, head=k)) for k in (4, 8, 16, 24)]
     cases += [("full_sort", dict(mode=gsr.MODE_FULL))]
@@ -219,6 +225,65 @@ def sort_errors(ds, cams, n):
         del r
         torch.cuda.empty_cache()
     return res
+
+
+ROTATION_VIEWS = (0, 15, 30, 45)
+ROTATION_ANGLES = (-5.0, -2.0, -0.5, 0.5, 2.0, 5.0)
+
+
+def rotation_sweep(ds, n, W, H):
+    """Popping under pure camera rotation (Sec. 1 and Sec. 3).  At orbit views
+    0, 15, 30 and 45 the camera turns about its centre by yaw, pitch and roll
+    of +-0.5, +-2 and +-5 degrees, and rolls by 180 degrees.  The full
+    per-pixel sort orders each pixel by t_opt along its own ray, which depends
+    on the ray alone, so an order equal to it cannot pop.  For each renderer
+    and angle this reports, averaged over the four views, the fraction of
+    pixels whose first 16 blends differ from the full sort's and the per-ray
+    sort error; for the 180-degree roll, which maps pixel (i, j) to
+    (W-1-i, H-1-j) with the same world ray, the fraction of pixels whose first
+    16 blends differ between the two views."""
+    import torch
+    from paper_2402_00525_amd import gsr, synth
+    K = 16
+    rend = {"hier_K4": dict(mode=gsr.MODE_HIER), "global_3dgs": dict(mode=gsr.MODE_GLOBAL),
+            "window_K16": dict(mode=gsr.MODE_WINDOW, head=16)}
+    rs = {k: gsr.Renderer(entries_hint=60 * n) for k in list(rend) + ["full_sort"]}
+    cfgs = {k: gsr.config(**v) for k, v in rend.items()}
+    cfgs["full_sort"] = gsr.config(mode=gsr.MODE_FULL)
+    acc = {k: {} for k in rend}
+    flips = {k: [] for k in cfgs}
+    for v in ROTATION_VIEWS:
+        base = synth.orbit_camera(W, H, v)
+        rots = [("%s%+g" % (ax, a), synth.rotate_camera(base, **{ax + "_deg": a}))
+                for ax in ("yaw", "pitch", "roll") for a in ROTATION_ANGLES]
+        for name, cam in [("none", base)] + rots:
+            full = rs["full_sort"].render(ds, cam, cfgs["full_sort"], max_k=K).blend_ids
+            for k, cfg in ((k, cfgs[k]) for k in rend):
+                ids = rs[k].render(ds, cam, cfg, max_k=K).blend_ids
+                mis = float((ids != full).any(dim=-1).float().mean())
+                _, d = rs[k].render_sort_error(ds, cam, cfg)
+                a = acc[k].setdefault(name, [0.0, 0.0, 0.0])
+                a[0] += mis / len(ROTATION_VIEWS)
+                a[1] += float(d.double().mean()) / len(ROTATION_VIEWS)
+                a[2] = max(a[2], float(d.max()))
+        rolled = synth.roll_180(base)
+        for k, cfg in cfgs.items():
+            a = rs[k].render(ds, base, cfg, max_k=K).blend_ids
+            b = rs[k].render(ds, rolled, cfg, max_k=K).blend_ids.flip(0).flip(1)
+            flips[k].append(float((a != b).any(dim=-1).float().mean()))
+        log("rotation sweep: view %d done" % v)
+    res = {}
+    for k in cfgs:
+        e = {"roll180_pixels_changed": round(mean(flips[k]), 6)}
+        if k in acc:
+            e["vs_full_sort"] = {name: {"pixels_differing": round(a[0], 5), "delta_avg": round(a[1], 5),
+                                        "delta_max": round(a[2], 4)} for name, a in acc[k].items()}
+        res[k] = e
+        log("rotation %s: roll180 %.5f" % (k, e["roll180_pixels_changed"]))
+    del rs
+    torch.cuda.empty_cache()
+    return {"views": list(ROTATION_VIEWS), "angles_deg": list(ROTATION_ANGLES), "first_blends_compared": K,
+            "results": res}
 
 
 def plan(r, ds, cams, cfg):
@@ -240,6 +305,17 @@ def mean(x):
     return sum(x) / max(1, len(x))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, cam, E):
     """The oracle on a bounded sample of the same frame: every per-Gaussian
     stage and the full sort, but the render on 1 tile in 256; the render time
@@ -255,6 +331,7 @@ def cpu_baseline(scene, cam, E):
     pre, dup, srt, ren = r.stats["ms"]
     est = pre + dup + srt + ren * tiles / int(mask.sum())
     return {"value": round(est, 1), "unit": "ms/frame", "cores": int(r.stats["threads"]), "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": "one 1920x1080 frame of the same scene: all %d Gaussians preprocessed, duplicated and sorted "
                       "(%d entries), hierarchical render on %d of %d tiles scaled to the full image; %.1f s wall"
                       % (scene.n, r.stats["entries"], int(mask.sum()), tiles, wall),
@@ -311,6 +388,42 @@ def fwd_bwd(steps, warmup):
                         "seeded random target, gradients for means/scales/rotations/opacities/SH"}
 
 
+def single_view_reference(dss, views, steps):
+    """The batch's views rendered one at a time through the plain single-view
+    renderer (gsr_render): ms for all views, mean of `steps` passes after one
+    planning pass."""
+    import torch
+    from paper_2402_00525_amd import gsr
+    cfg = gsr.config()
+    r = gsr.Renderer(entries_hint=1 << 20)
+    outs = [gsr.Frame(c.H, c.W, "cuda") for _, c in views]
+    emax = 0
+    for s, c in views:
+        r.render(dss[s], c, cfg)
+        emax = max(emax, r.counter(dss[s].n, c, 0))
+    nmax = max(d.n for d in dss)
+    Wm, Hm = max(c.W for _, c in views), max(c.H for _, c in views)
+    r.plan(nmax, Wm, Hm, int(emax * 1.05) + 1024)
+    for (s, c), o in zip(views, outs):
+        r.render_async(dss[s], c, cfg, o)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r.status.zero_()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        for (s, c), o in zip(views, outs):
+            r.render_async(dss[s], c, cfg, o)
+    t1.record()
+    torch.cuda.synchronize()
+    if int(r.status.item()) != 0:
+        raise RuntimeError("overflow during the single-view reference of the batch")
+    ms = t0.elapsed_time(t1) / steps
+    log("batch views one at a time: %.2f ms for %d views" % (ms, len(views)))
+    del r, outs
+    torch.cuda.empty_cache()
+    return ms
+
+
 def batched(steps):
     """128 views (64 of the 1M-Gaussian scene, 8 each of 8 scenes with N
     log-uniform in [1e5, 2e6]) at resolutions drawn from 256^2, 512^2,
@@ -342,7 +455,12 @@ def batched(steps):
     if int(b.status.item()) != 0:
         raise RuntimeError("overflow during batched timing")
     ms = t0.elapsed_time(t1) / steps
+    single_ms = single_view_reference(dss, views, steps=2)
     res = {"views_per_s": round(len(views) / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3), "views": len(views),
+           "single_view": {"views_per_s": round(len(views) / (single_ms * 1e-3), 1),
+                           "ms_per_batch": round(single_ms, 3),
+                           "how": "the same views rendered one after another through gsr_render (one workspace, "
+                                  "one stream, no host synchronisation between views)"},
            "scenes": len(scenes), "gaussians": [s.n for s in scenes], "entries": int(E),
            "schedule": {"wgs_per_cu": sched.wgs_per_cu, "cost_order": sched.cost_order,
                         "lb_threshold": sched.lb_threshold},
@@ -484,6 +602,9 @@ def main():
         log("sort error ...")
         sel = [0, len(cams) // 2] if len(cams) > 1 else [0]
         line["sort_error"] = {"views": sel, "results": sort_errors(ds, [cams[v] for v in sel], n)}
+    if not args.no_rotation and args.workload != "small":
+        log("rotation sweep ...")
+        line["rotation"] = rotation_sweep(ds, n, W, H)
     if not args.no_batch and args.workload != "small":
         log("batched ...")
         line["batched"] = batched(5)
