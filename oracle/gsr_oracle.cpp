@@ -944,37 +944,60 @@ template <class F> struct G2 {
 // a float32 evaluation of the same sums in any order differs from the exact
 // ones by at most about (nterms + ops per term) * 2^-24 * bound (first-order
 // running-error analysis).  The bound carries no gradient information.
-template <class F> void backward_blends(const Frame<F>& fr, const F* dL, const float bg[3], std::vector<G2<F>>& g2,
-                                        std::vector<G2<F>>* bound = nullptr, std::vector<int>* nterms = nullptr) {
-    const Cam<F>& cam = fr.cam;
+//
+// The terms are evaluated in F from a frame rendered in FD: the blend
+// sequences, alphas, records, final colours and transmittances are the FD
+// frame's, and so are the decisions (whether the alpha clamp was active), so
+// that F = double over an FD = float frame differentiates exactly the branch
+// that the float32 forward took (the order, culling and termination are
+// piecewise constant, Sec. 3.5); only the arithmetic of the terms is F.
+template <class F, class FD> Rec<F> rec_as(const Rec<FD>& r) {
+    Rec<F> g;
+    g.x = (F)r.x; g.y = (F)r.y;
+    g.ca = (F)r.ca; g.cb = (F)r.cb; g.cc = (F)r.cc; g.op = (F)r.op;
+    for (int k = 0; k < 6; ++k) g.s[k] = (F)r.s[k];
+    for (int k = 0; k < 3; ++k) { g.w[k] = (F)r.w[k]; g.rgb[k] = (F)r.rgb[k]; g.clamp_rgb[k] = r.clamp_rgb[k]; }
+    g.z = (F)r.z; g.dist = (F)r.dist;
+    for (int k = 0; k < 4; ++k) g.rect[k] = r.rect[k];
+    g.vis = r.vis; g.clamp_x = r.clamp_x; g.clamp_y = r.clamp_y;
+    return g;
+}
+
+template <class F, class FD = F>
+void backward_blends(const Frame<FD>& fr, const F* dL, const float bg[3], std::vector<G2<F>>& g2,
+                     std::vector<G2<F>>* bound = nullptr, std::vector<int>* nterms = nullptr) {
+    const Cam<FD>& cam = fr.cam;
     const size_t P = (size_t)cam.W * cam.H;
     for (int y = 0; y < cam.H; ++y)
         for (int x = 0; x < cam.W; ++x) {
             const size_t p = (size_t)y * cam.W + x;
-            const Pixel<F>& px = fr.pix[p];
-            const F TN = px.T;
+            const Pixel<FD>& px = fr.pix[p];
+            const F TN = (F)px.T;
+            const F Cfin[3] = {(F)px.C[0], (F)px.C[1], (F)px.C[2]};
             F T = 1, Cacc[3] = {0, 0, 0};
             for (size_t k = 0; k < px.ids.size(); ++k) {
                 const int id = px.ids[k];
-                const F a = px.alphas[k];
-                const Rec<F>& g = fr.recs[id];
+                const F a = (F)px.alphas[k];
+                const Rec<FD>& gd = fr.recs[id];
+                const Rec<F> g = rec_as<F>(gd);
                 for (int ch = 0; ch < 3; ++ch) Cacc[ch] = Cacc[ch] + (g.rgb[ch] * a) * T;
                 F ga = 0, ga_m = 0;
                 for (int ch = 0; ch < 3; ++ch) {
                     const F dl = dL[ch * P + p];
                     g2[id].rgb[ch] += dl * a * T;
-                    ga += dl * (g.rgb[ch] * T - (px.C[ch] - Cacc[ch] + TN * (F)bg[ch]) / (F(1) - a));
+                    ga += dl * (g.rgb[ch] * T - (Cfin[ch] - Cacc[ch] + TN * (F)bg[ch]) / (F(1) - a));
                     if (bound) {
                         (*bound)[id].rgb[ch] += std::abs(dl) * a * T;
                         ga_m += std::abs(dl) * (std::abs(g.rgb[ch]) * T +
-                                                (std::abs(px.C[ch]) + std::abs(Cacc[ch]) + TN * std::abs((F)bg[ch])) /
+                                                (std::abs(Cfin[ch]) + std::abs(Cacc[ch]) + TN * std::abs((F)bg[ch])) /
                                                     (F(1) - a));
                     }
                 }
                 if (nterms) (*nterms)[id] += 1;
                 const F pw = power_at(g, (F)x, (F)y);
                 const F G = expE(pw);
-                if (g.op * G < F(0.99)) {
+                // the clamp decision of the forward's arithmetic
+                if (gd.op * expE(power_at(gd, (FD)x, (FD)y)) < FD(0.99)) {
                     g2[id].op += ga * G;
                     const F gp = ga * a;  // d alpha / d power = o G = alpha
                     const F dx = g.x - (F)x, dy = g.y - (F)y;
@@ -1345,18 +1368,20 @@ int oracle_backward_f32(int n, int deg, const float* means, const float* scales,
                                 rgb, sig);
 }
 
-// 2D gradients of one frame (float64): per Gaussian the 9 components
+// 2D gradients of one frame, float64 terms over the float32 forward's blend
+// sequences and decisions: per Gaussian the 9 components
 // (mean x, mean y, conic a, b, c, opacity, r, g, b) of d(sum dL * rgb), the
 // magnitude bound of each (see backward_blends) and the number of blends.
 int oracle_grad2d_f64(int n, int deg, const float* means, const float* scales, const float* rots, const float* opac,
                       const float* sh, const OCam* cam, const OCfg* cfg, const double* dL, double* g2_out,
                       double* bound_out, int32_t* nterms_out) {
     if (n < 0 || deg < 0 || deg > 3) return -1;
-    Frame<double> fr(*cam, *cfg);
-    run_frame<double>(fr, n, deg, means, scales, rots, opac, sh, nullptr);
+    // the float32 forward's blends and decisions, terms in float64
+    Frame<float> fr(*cam, *cfg);
+    run_frame<float>(fr, n, deg, means, scales, rots, opac, sh, nullptr);
     std::vector<G2<double>> g2(n), bd(n);
     std::vector<int> nt(n, 0);
-    backward_blends(fr, dL, cfg->bg, g2, &bd, &nt);
+    backward_blends<double, float>(fr, dL, cfg->bg, g2, &bd, &nt);
     auto put = [](const G2<double>& g, double* o) {
         o[0] = g.mx; o[1] = g.my; o[2] = g.ca; o[3] = g.cb; o[4] = g.cc; o[5] = g.op;
         o[6] = g.rgb[0]; o[7] = g.rgb[1]; o[8] = g.rgb[2];

@@ -15,7 +15,10 @@ Two levels, each with its own tolerance per element:
   GPU's own 2D gradients, so only the chain's float32 rounding is left.  Its
   size per element is estimated by Monte-Carlo arithmetic (Parker, 1997):
   float32 evaluations of the same chain with inputs moved by one ulp; the
-  tolerance is a multiple of their spread.
+  tolerance is a multiple of their spread.  Sixteen such evaluations: a
+  chain element near a branch of the chain (a clamp) spreads in two modes,
+  which four evaluations can miss (a simulated float32 evaluation then
+  exceeded 9x the tolerance; with sixteen, the worst of six was 0.4x).
 """
 import numpy as np
 
@@ -41,7 +44,7 @@ def _ulp_jitter(a, rng):
     return out.astype(np.float32)
 
 
-def chain_tolerance(scene, cam, g2, runs=4, seed=0):
+def chain_tolerance(scene, cam, g2, runs=16, seed=0):
     """Per-element spread of float32 chain-rule evaluations under one-ulp
     perturbations of the scene and the 2D gradients."""
     import copy

@@ -103,3 +103,54 @@ def test_backward_single_gaussian_closed_form():
     alpha = r.rgb[1, 15, 16] / col
     np.testing.assert_allclose(g["opacities"][0], alpha / 0.5 * col, rtol=1e-10)
     np.testing.assert_allclose(g["sh"][0, 0, 1], alpha * 0.5 / np.sqrt(np.pi), rtol=1e-10)
+
+
+def _alpha32(fr, i, x, y):
+    """alpha of Gaussian i at pixel (x, y) in float32 arithmetic from the
+    frame's float32 records (Eq. volume_desc: opacity times the 2D Gaussian,
+    clamped to 0.99)."""
+    f = np.float32
+    mx, my = fr.xy[i]
+    ca, cb, cc, op = fr.conic_o[i]
+    dx, dy = f(mx) - f(x), f(my) - f(y)
+    p = f(-0.5) * ((ca * dx) * dx + (cc * dy) * dy) - (cb * dx) * dy
+    a = f(op) * f(oracle.exp32(f(p)))
+    return min(a, f(0.99))
+
+
+def test_grad2d_reference_follows_the_float32_forward():
+    """oracle.grad2d differentiates the float32 forward's blend sequences in
+    float64.  Where the float32 and float64 forwards take the same decisions
+    (checked through the decision signatures), the chain rule applied to it
+    gives the float64 backward's parameter gradients to float32 rounding of
+    the forward's records; and its colour components are the closed form
+    sum over blends of dL * alpha * T of the float32 forward."""
+    scene, cam = fd_scene()
+    target = synth.random_target(cam.H, cam.W, seed=4)
+    rgb0, _, _ = oracle.backward(scene, cam, np.zeros((3, cam.H, cam.W)), "f64")
+    dL = (np.sign(rgb0 - target) / rgb0.size).astype(np.float32)
+    _, g64, s64 = oracle.backward(scene, cam, dL.astype(np.float64), "f64")
+    _, _, s32 = oracle.backward(scene, cam, dL, "f32")
+    assert s32 == s64
+    g2, bound, nt = oracle.grad2d(scene, cam, dL)
+    assert np.all(np.abs(g2) <= bound * (1 + 1e-12) + 1e-300)
+    chained = oracle.chain(scene, cam, g2)
+    for name in PARAMS:
+        b = g64[name]
+        assert np.abs(chained[name] - b).max() <= 1e-4 * np.abs(b).max() + 1e-12, name
+    # colour: sum of dL alpha T over the float32 forward's blends
+    fr = oracle.frame(scene, cam, max_k=64)
+    assert fr.count.max() < 64
+    ref = np.zeros((scene.n, 3))
+    nblend = np.zeros(scene.n, np.int64)
+    for y in range(cam.H):
+        for x in range(cam.W):
+            T = 1.0
+            for k in range(int(fr.count[y, x])):
+                i = int(fr.blend_ids[y, x, k])
+                a = float(_alpha32(fr, i, x, y))
+                ref[i] += dL[:, y, x].astype(np.float64) * a * T
+                nblend[i] += 1
+                T *= 1.0 - a
+    np.testing.assert_array_equal(nt, nblend)
+    np.testing.assert_allclose(g2[:, 6:9], ref, rtol=1e-12, atol=1e-18)
