@@ -155,9 +155,10 @@ __device__ __forceinline__ uint32_t quad_bcast_u(uint32_t v) {
 }
 
 // Adds the 9 gradient terms of one blend: into the tile's LDS accumulators
-// (slot = rank in the tile list) when the rank has a slot, else to global memory.
+// (slot = rank in the tile list; the backward always has them) when the rank
+// has a slot, else to global memory.
 __device__ __forceinline__ void add_grad(const RenderArgs& a, float* acc, uint32_t rank, uint32_t id, int c, float v) {
-    if (acc && rank < (uint32_t)kAccSlots)
+    if (rank < (uint32_t)kAccSlots)
         atomicAdd(acc + c * kAccSlots + rank, v);
     else
         atomicAdd(a.grad2d + 9 * (size_t)id + c, v);
@@ -276,27 +277,25 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
     blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
 }
 
-// Insertion into the sorted head (s.hn < K on entry).
+// Insertion into the sorted head (s.hn < K on entry).  Every slot takes its
+// new value by selects, never by a store at a computed slot, so the head
+// stays in registers at every K.
 template <int K, int MODE>
 __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key, uint32_t id, float alpha) {
     int pos = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) pos += (i < s.hn && s.hk[i] < key) ? 1 : 0;
+    // from the back, so that slot i - 1 still holds its old entry
 #pragma unroll
-    for (int i = K - 1; i >= 1; --i) {
-        if (i > pos && i <= s.hn) {
-            s.hk[i] = s.hk[i - 1];
-            s.hid[i] = s.hid[i - 1];
-            s.ha[i] = s.ha[i - 1];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        if (i == pos) {
-            s.hk[i] = key;
-            s.hid[i] = id;
-            s.ha[i] = alpha;
-        }
+    for (int i = K - 1; i >= 0; --i) {
+        const bool here = i == pos;
+        const bool moved = i > pos && i <= s.hn;
+        const uint64_t pk = i > 0 ? s.hk[i - 1] : 0ull;
+        const uint32_t pi = i > 0 ? s.hid[i - 1] : 0u;
+        const float pa = i > 0 ? s.ha[i - 1] : 0.0f;
+        s.hk[i] = here ? key : (moved ? pk : s.hk[i]);
+        s.hid[i] = here ? id : (moved ? pi : s.hid[i]);
+        s.ha[i] = here ? alpha : (moved ? pa : s.ha[i]);
     }
     s.hn += 1;
 }
@@ -322,17 +321,17 @@ __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MOD
     int pos = 0;  // the entry's slot once the front has left
 #pragma unroll
     for (int i = 1; i < K; ++i) pos += s.hk[i] < key ? 1 : 0;
+    // from the front, so that slot i + 1 still holds its old entry
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        if (i < pos) {
-            s.hk[i] = s.hk[i + 1];
-            s.hid[i] = s.hid[i + 1];
-            s.ha[i] = s.ha[i + 1];
-        } else if (i == pos) {
-            s.hk[i] = key;
-            s.hid[i] = id;
-            s.ha[i] = alpha;
-        }
+        const bool moved = i < pos;
+        const bool here = i == pos;
+        const uint64_t nk = i + 1 < K ? s.hk[i + 1] : 0ull;
+        const uint32_t ni = i + 1 < K ? s.hid[i + 1] : 0u;
+        const float na = i + 1 < K ? s.ha[i + 1] : 0.0f;
+        s.hk[i] = moved ? nk : (here ? key : s.hk[i]);
+        s.hid[i] = moved ? ni : (here ? id : s.hid[i]);
+        s.ha[i] = moved ? na : (here ? alpha : s.ha[i]);
     }
     blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
 }
