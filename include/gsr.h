@@ -362,6 +362,31 @@ int64_t gsr_batch_counters_offset(const gsr_batch* batch);/* byte offset of uint
                                                              [16..31] work-queue heads */
 void gsr_batch_destroy(gsr_batch* batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gsr_render
+ * with a fixed workspace of GSR_NOALLOC_BYTES that the library holds in a
+ * static device array, one per GPU, from the first call on that GPU until the
+ * process ends.  The call allocates nothing (no hipMalloc, no allocating
+ * library routine); the caller still owns scene, outputs and status_dev, as
+ * for gsr_render.  The device current on the calling thread must be the
+ * stream's device.
+ *   - Sizes: the per-Gaussian and per-tile regions (about 213 B per Gaussian
+ *     and 32 B per 16x16 tile) plus 28 B per tile entry must fit in
+ *     GSR_NOALLOC_BYTES; a scene and image too large for even one entry is
+ *     refused with GSR_ECAPACITY before anything is enqueued.  More entries
+ *     than the rest holds is the data-dependent overflow of gsr_render
+ *     (GSR_STATUS_OVERFLOW in *status_dev, outputs undefined); it cannot be
+ *     cured by a larger workspace here, only by the workspace entry points.
+ *   - The array keeps the last call's contents; every call clears what it
+ *     needs.  Calls that overlap on one GPU (other streams, other threads)
+ *     share that GPU's array and race: serialise them.
+ *   - Results equal gsr_render's with the same scene, camera and
+ *     configuration (the same kernels run).  A backward is not offered: the
+ *     next call overwrites the forward's workspace. */
+#define GSR_NOALLOC_BYTES ((size_t)64 << 20)
+int gsr_render_noalloc(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, float* rgb,
+                       float* depth, int32_t* count, float* T_final, int32_t* status_dev, gsr_stream_t stream);
+
 /* Element-wise arithmetic probe of the device (diagnostic): for n inputs
  * a[i], b[i] writes out[k*n + i] for k = 0..5:
  *   a/b, sqrt(a), project exp(a), project ln(a) (a >= 1), rint(a), a*b+a. */

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -735,6 +736,36 @@ bool schedule_valid(const gsr_schedule& c) {
 }
 }  // namespace
 
+// The workspace of gsr_render_noalloc: a static device array, one copy per
+// GPU at its own address.  In host code `scratch` names a host-side stand-in,
+// not device memory, so kernels get the address hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+constexpr size_t kNoAllocBytes = GSR_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_workspace(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GSR_EUNSUPPORTED, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255) != 0) return fail(GSR_EDEVICE, "static workspace is not 256-byte aligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GSR_OK;
+}
+}  // namespace
+
 extern "C" {
 
 size_t gsr_batch_workspace_bytes(const gsr_scene* scenes, int32_t n_scenes, const gsr_view* views, int32_t n_views,
@@ -1016,6 +1047,22 @@ int gsr_render_debug(const gsr_scene* scene, const gsr_camera* cam, const gsr_co
                      int32_t* status_dev, gsr_stream_t stream) {
     if (!blend_ids) return fail(GSR_EINVAL, "blend_ids is NULL");
     return render_impl(scene, cam, cfg, ws, ws_bytes, rgb, depth, count, T_final, blend_ids, max_k, status_dev, stream,
+                       nullptr, 0);
+}
+
+int gsr_render_noalloc(const gsr_scene* scene, const gsr_camera* cam, const gsr_config* cfg, float* rgb,
+                       float* depth, int32_t* count, float* T_final, int32_t* status_dev, gsr_stream_t stream) {
+    if (!scene || !cam) return fail(GSR_EINVAL, "scene or camera is NULL");
+    {
+        gsr_layout L;
+        int64_t sp, hist, k1, v1;
+        if (compute_layout(scene->n, cam->W, cam->H, kNoAllocBytes, &L, &sp, &hist, &k1, &v1) != GSR_OK)
+            return fail(GSR_ECAPACITY, "scene and image do not fit the fixed workspace of GSR_NOALLOC_BYTES");
+    }
+    void* ws = nullptr;
+    const int rc = noalloc_workspace(&ws);
+    if (rc) return rc;
+    return render_impl(scene, cam, cfg, ws, kNoAllocBytes, rgb, depth, count, T_final, nullptr, 0, status_dev, stream,
                        nullptr, 0);
 }
 

@@ -60,7 +60,7 @@ _lib = None
 
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
            "gsr_render", "gsr_render_debug", "gsr_render_sort_error", "gsr_render_backward", "gsr_render_staged",
-           "gsr_render_work",
+           "gsr_render_work", "gsr_render_noalloc",
            "gsr_sort_passes", "gsr_group_passes",
            "gsr_probe_math",
            "gsr_last_error", "gsr_version")
@@ -100,6 +100,8 @@ def lib():
         L.gsr_render_staged.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig), C.c_void_p,
                                         C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_int32]
+        L.gsr_render_noalloc.restype = C.c_int
+        L.gsr_render_noalloc.argtypes = [C.POINTER(CScene), C.POINTER(CCamera), C.POINTER(CConfig)] + [C.c_void_p] * 6
         L.gsr_sort_passes.restype = C.c_int
         L.gsr_sort_passes.argtypes = [C.c_int32, C.c_int32]
         L.gsr_group_passes.restype = C.c_int
@@ -344,6 +346,25 @@ class Renderer:
                     pre_vals=get("pre_vals", torch.int32, E), pre_len=get("pre_len", torch.int32, tiles),
                     tile_flag=get("tile_flag", torch.int32, tiles), fallback_entries=F,
                     fallback_tiles=self.counter(n, cam, 6))
+
+
+NOALLOC_BYTES = 64 << 20  # GSR_NOALLOC_BYTES
+
+
+def render_noalloc(scene: DeviceScene, cam, cfg: CConfig | None = None, out: Frame | None = None,
+                   status: torch.Tensor | None = None) -> Frame:
+    """gsr_render_noalloc: one frame in the library's fixed per-GPU workspace
+    (no device allocation by the library).  Enqueues only; the caller reads
+    ``status`` (bit 0: entries overflowed the fixed workspace)."""
+    cfg = cfg or config()
+    dev = scene.means.device
+    out = out or Frame(cam.H, cam.W, dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    sc, cc = scene.c_struct(), camera(cam)
+    _check(lib().gsr_render_noalloc(C.byref(sc), C.byref(cc), C.byref(cfg), _ptr(out.rgb), _ptr(out.depth),
+                                    _ptr(out.count), _ptr(out.T), _ptr(status), _stream()))
+    return out
 
 
 def probe_math(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
