@@ -100,15 +100,25 @@ struct WaveQueues {
     uint32_t mid[16][kMidCap];
 };
 
+constexpr bool head_keeps_ids(int K) { return K <= 8; }
+
 template <int K, int MODE>
 struct PixelState {
     float T, C0, C1, C2, D;
     int n;
     bool done;
+    // head: keys (t_opt bits << 32 | low word) and alphas, sorted; empty
+    // slots hold kInvalidKey, above every real key.  The low word of a key is
+    // the entry's rank in the tile list `ids` (its Gaussian is ids[rank]), or
+    // the Gaussian id itself when `ids` is null.  Small heads also keep each
+    // slot's Gaussian, so that a blend needs no dependent load before its
+    // colour load; large heads save those registers and read ids[rank].
     uint64_t hk[K];
-    uint32_t hid[K];
     float ha[K];
+    uint32_t hid[head_keeps_ids(K) ? K : 1];  // the slots' Gaussians (small heads only)
     int hn;
+    const uint32_t* ids;
+    uint32_t n_ids;  // Gaussians: ids at or above are read as 0
     // backward only: dL/dC, final colour without background, final transmittance
     float g0, g1, g2, F0, F1, F2, TN;
     float px, py;
@@ -261,49 +271,73 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
     s.T = Tn;
 }
 
+// Gaussian of a head key (see PixelState::hk).
+template <int K, int MODE>
+__device__ __forceinline__ uint32_t head_id(const PixelState<K, MODE>& s, uint64_t key) {
+    const uint32_t lo = (uint32_t)key;
+    const uint32_t id = s.ids ? s.ids[lo] : lo;
+    return id < s.n_ids ? id : 0u;
+}
+
+// Gaussian of the front slot.
+template <int K, int MODE>
+__device__ __forceinline__ uint32_t front_id(const PixelState<K, MODE>& s) {
+    if (head_keeps_ids(K)) return s.hid[0];
+    return head_id(s, s.hk[0]);
+}
+
 // Remove the front of the head and blend it.
 template <int K, int MODE>
 __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, MODE>& s, int pix, float* acc) {
     const uint64_t k0 = s.hk[0];
-    const uint32_t i0 = s.hid[0];
     const float a0 = s.ha[0];
+    const uint32_t i0 = front_id(s);
 #pragma unroll
     for (int i = 0; i + 1 < K; ++i) {
         s.hk[i] = s.hk[i + 1];
-        s.hid[i] = s.hid[i + 1];
         s.ha[i] = s.ha[i + 1];
+        if (head_keeps_ids(K)) s.hid[i] = s.hid[i + 1];
     }
+    s.hk[K - 1] = kInvalidKey;
+    s.ha[K - 1] = 0.0f;
     s.hn -= 1;
     blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
 }
 
-// Insertion into the sorted head (s.hn < K on entry).  Every slot takes its
-// new value by selects, never by a store at a computed slot, so the head
-// stays in registers at every K.
+// Insertion into the sorted head (s.hn < K on entry, so the last slot is
+// empty).  With c_i = (slot i holds a key below the entry), true exactly for
+// the slots before the entry's place, slot i keeps its key if c_i, takes the
+// entry if c_(i-1) (or i = 0) and not c_i, and else its predecessor's.  Every
+// slot takes its new value by selects, never by a store at a computed slot,
+// so the head stays in registers at every K.
 template <int K, int MODE>
 __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key, uint32_t id, float alpha) {
-    int pos = 0;
+    bool c[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) pos += (i < s.hn && s.hk[i] < key) ? 1 : 0;
+    for (int i = 0; i < K; ++i) c[i] = s.hk[i] < key;
     // from the back, so that slot i - 1 still holds its old entry
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) {
-        const bool here = i == pos;
-        const bool moved = i > pos && i <= s.hn;
+        const bool take = i == 0 || c[i - 1];
         const uint64_t pk = i > 0 ? s.hk[i - 1] : 0ull;
-        const uint32_t pi = i > 0 ? s.hid[i - 1] : 0u;
         const float pa = i > 0 ? s.ha[i - 1] : 0.0f;
-        s.hk[i] = here ? key : (moved ? pk : s.hk[i]);
-        s.hid[i] = here ? id : (moved ? pi : s.hid[i]);
-        s.ha[i] = here ? alpha : (moved ? pa : s.ha[i]);
+        s.hk[i] = c[i] ? s.hk[i] : (take ? key : pk);
+        s.ha[i] = c[i] ? s.ha[i] : (take ? alpha : pa);
+        if (head_keeps_ids(K)) {
+            const uint32_t pi = i > 0 ? s.hid[i - 1] : 0u;
+            s.hid[i] = c[i] ? s.hid[i] : (take ? id : pi);
+        }
     }
     s.hn += 1;
 }
 
 // Push into a head of capacity K, blending the front whenever it would hold
 // more than K (the k-buffer rule of Sec. 3.3): while it is not full the entry
-// is inserted; when it is full the smaller of the entry and the front is
-// blended and the other one stays, in a single pass over the slots.
+// is inserted; when it is full the smallest of the K + 1 (the entry or the
+// front) is blended and the other K stay sorted, in one pass of selects:
+// with c_i = (slot i + 1 holds a key below the entry) and c_(-1) = (the front
+// is below the entry), slot i takes slot i + 1's key if c_i, the entry if
+// c_(i-1) and not c_i, and else keeps its own.
 template <int K, int MODE>
 __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MODE>& s, int pix, uint64_t key,
                                           uint32_t id, float alpha, float* acc) {
@@ -311,29 +345,30 @@ __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MOD
         head_insert<K, MODE>(s, key, id, alpha);
         return;
     }
-    if (key < s.hk[0]) {
-        blend_one<K, MODE>(a, s, pix, id, alpha, depth_from_bits((uint32_t)(key >> 32)), (uint32_t)key, acc);
-        return;
-    }
     const uint64_t k0 = s.hk[0];
-    const uint32_t i0 = s.hid[0];
     const float a0 = s.ha[0];
-    int pos = 0;  // the entry's slot once the front has left
+    const bool front_goes = k0 < key;
+    const uint32_t bid = front_goes ? front_id(s) : id;
+    bool c[K];
 #pragma unroll
-    for (int i = 1; i < K; ++i) pos += s.hk[i] < key ? 1 : 0;
+    for (int i = 0; i + 1 < K; ++i) c[i] = s.hk[i + 1] < key;
+    c[K - 1] = false;
     // from the front, so that slot i + 1 still holds its old entry
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const bool moved = i < pos;
-        const bool here = i == pos;
+        const bool take = i == 0 ? front_goes : c[i - 1];
         const uint64_t nk = i + 1 < K ? s.hk[i + 1] : 0ull;
-        const uint32_t ni = i + 1 < K ? s.hid[i + 1] : 0u;
         const float na = i + 1 < K ? s.ha[i + 1] : 0.0f;
-        s.hk[i] = moved ? nk : (here ? key : s.hk[i]);
-        s.hid[i] = moved ? ni : (here ? id : s.hid[i]);
-        s.ha[i] = moved ? na : (here ? alpha : s.ha[i]);
+        s.hk[i] = c[i] ? nk : (take ? key : s.hk[i]);
+        s.ha[i] = c[i] ? na : (take ? alpha : s.ha[i]);
+        if (head_keeps_ids(K)) {
+            const uint32_t ni = i + 1 < K ? s.hid[i + 1] : 0u;
+            s.hid[i] = c[i] ? ni : (take ? id : s.hid[i]);
+        }
     }
-    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
+    const uint64_t bk = front_goes ? k0 : key;
+    blend_one<K, MODE>(a, s, pix, bid, front_goes ? a0 : alpha, depth_from_bits((uint32_t)(bk >> 32)), (uint32_t)bk,
+                       acc);
 }
 
 template <int K, int MODE>
@@ -528,8 +563,8 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         h.st.hk[i] = kInvalidKey;
-        h.st.hid[i] = 0;
         h.st.ha[i] = 0.0f;
+        if (head_keeps_ids(K)) h.st.hid[i] = 0u;
     }
     h.ms = 0;
     h.mn = 0;
@@ -540,6 +575,8 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const TileList tl = tile_list(a, range_tile);
     if (tl.skip) return 0u;
     const uint32_t* list = tl.ids;
+    h.st.ids = list;
+    h.st.n_ids = a.n;
     // A truncated prefix is walked in whole batches only: the last, partial
     // batch of a prefix is not the batch the whole list has at that place,
     // and the pops that follow it could differ.  The strip is then flagged
@@ -971,11 +1008,13 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
+    st.ids = tl.ids;
+    st.n_ids = a.n;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         st.hk[i] = kInvalidKey;
-        st.hid[i] = 0;
         st.ha[i] = 0.0f;
+        if (head_keeps_ids(K)) st.hid[i] = 0u;
     }
     uint32_t consumed = 0;
     for (uint32_t start = begin; start < end; start += 256) {
@@ -1052,6 +1091,8 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
+    st.ids = nullptr;  // keys carry the Gaussian id itself
+    st.n_ids = a.n;
     bool more = true;
     uint64_t floor_key = 0;  // keys below this were blended in earlier rounds
     while (__syncthreads_or(!st.done && more)) {
@@ -1059,7 +1100,6 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             st.hk[i] = kInvalidKey;
-            st.hid[i] = 0;
             st.ha[i] = 0.0f;
         }
         int found = 0;
@@ -1086,17 +1126,14 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
                 for (int i = K - 1; i >= 1; --i) {
                     if (st.hk[i - 1] > key) {
                         st.hk[i] = st.hk[i - 1];
-                        st.hid[i] = st.hid[i - 1];
                         st.ha[i] = st.ha[i - 1];
                     } else if (st.hk[i] > key) {
                         st.hk[i] = key;
-                        st.hid[i] = s_id[k];
                         st.ha[i] = alpha;
                     }
                 }
                 if (st.hk[0] > key) {
                     st.hk[0] = key;
-                    st.hid[0] = s_id[k];
                     st.ha[0] = alpha;
                 }
                 found = found < K ? found + 1 : K;
@@ -1106,8 +1143,8 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 if (i < found)
-                    blend_one<K, MODE>(a, st, pix, st.hid[i], st.ha[i], depth_from_bits((uint32_t)(st.hk[i] >> 32)),
-                                       0u, nullptr);
+                    blend_one<K, MODE>(a, st, pix, head_id(st, st.hk[i]), st.ha[i],
+                                       depth_from_bits((uint32_t)(st.hk[i] >> 32)), 0u, nullptr);
             more = found == K;
             floor_key = st.hk[K - 1] + 1ull;
         }
