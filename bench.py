@@ -99,6 +99,9 @@ def parse():
                          "degrees and a 180-degree roll)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM byte counters)")
+    ap.add_argument("--gather-calibration-mib", type=int, default=0,
+                    help="run one gather of this many MiB of 64-byte rows at random row indices first (reference "
+                         "for HBM byte counters of gather-heavy kernels)")
     return ap.parse_args()
 
 
@@ -497,6 +500,19 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
         del src, dst
+    if args.gather_calibration_mib:
+        # rows of 16 float32 (64 bytes, the size of a packed splat) from a table
+        # four times larger, at seeded random indices: reads the index array
+        # and the gathered rows, writes the rows
+        rows = args.gather_calibration_mib << 14
+        table = torch.ones((4 * rows, 16), dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cpu").manual_seed(0)
+        idx = torch.randint(0, 4 * rows, (rows,), generator=g).cuda()
+        out = torch.index_select(table, 0, idx)
+        torch.cuda.synchronize()
+        log("gather calibration: %d MiB of 64-byte rows gathered (+ %d MiB of int64 indices), %d MiB written" %
+            (args.gather_calibration_mib, args.gather_calibration_mib // 8, args.gather_calibration_mib))
+        del table, idx, out
     ds = gsr.DeviceScene.from_host(scene)
     n, W, H = scene.n, cams[0].W, cams[0].H
     P = W * H
@@ -546,7 +562,8 @@ def main():
     render_flops = (49.0 * (work["tail_tests"] + work["mid_tests"]) + 26.0 * (work["tail_keyed"] + work["mid_keyed"])
                     + 31.0 * work["head_tests"] + 26.0 * work["head_keyed"] + 14.0 * work["blends"])
     # Kernels of a hierarchical frame: (ms per frame, ms per launch, algorithmic HBM bytes per launch).
-    pre_bytes = n * (44 + 12 * ksh) + n * 168          # inputs; records incl. the packed splat
+    pre_bytes = n * (44 + 12 * ksh) + n * 116          # inputs; records: splat 64, colour 16, zd 8, rect 16,
+                                                       # kept-tile count 4 and mask 8
     dup_bytes = n * 108 + 12.0 * h["E"]                # records of every Gaussian; one key + id per entry
     cands = {
         "k_preprocess": (h["stages"][0], h["stages"][0], pre_bytes),

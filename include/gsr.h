@@ -145,12 +145,11 @@ typedef struct gsr_config {
 } gsr_config;
 
 /* Byte offsets of the regions of a workspace, for inspection and debugging.
- * Records (App. B.4), one row per Gaussian:
- *   xy       float2 2D mean            conic_o  float4 (a, b, c, opacity)
- *   sw       float[12] Sigma^-1 (s00 s01 s02 s11 s12 s22), w = Sigma^-1 (mu - o), rgb
- *   splat    float[16] the renderer's packed copy: x y a b | c opacity s00 s01 |
- *            s02 s11 s12 s22 | w0 w1 w2 ln(eps_O / opacity) (one 64-byte line
- *            per Gaussian; zero when culled)
+ * Records (App. B.4), one row per Gaussian, zero when culled:
+ *   splat    float[16]: 2D mean x y, conic a b | conic c, opacity, Sigma^-1 s00 s01 |
+ *            s02 s11 s12 s22 | w = Sigma^-1 (mu - o) w0 w1 w2, ln(eps_O / opacity)
+ *            (one 64-byte line per Gaussian, the record every render level reads)
+ *   colour   float4 (r, g, b, |mu - o|)
  *   zd       float2 (view depth, |mu - o|)
  *   rect     int32[4] tile rectangle (x0, y0, x1, y1), inclusive
  *   touched  uint32 kept tiles          offsets uint32 exclusive prefix sum of touched
@@ -176,7 +175,7 @@ typedef struct gsr_config {
  * the entry count of a tile that took the fallback (else 0), then two rows
  * of per-tile scratch of the render. */
 typedef struct gsr_layout {
-    int64_t xy, conic_o, sw, splat, zd, rect, touched, kmask, offsets, dup_hist, grad2d;
+    int64_t splat, colour, zd, rect, touched, kmask, offsets, dup_hist, grad2d;
     int64_t keys, values, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag;
     int64_t entry_capacity;
@@ -370,7 +369,7 @@ void gsr_batch_destroy(gsr_batch* batch);
  * library routine); the caller still owns scene, outputs and status_dev, as
  * for gsr_render.  The device current on the calling thread must be the
  * stream's device.
- *   - Sizes: the per-Gaussian and per-tile regions (about 213 B per Gaussian
+ *   - Sizes: the per-Gaussian and per-tile regions (about 157 B per Gaussian
  *     and 32 B per 16x16 tile) plus 28 B per tile entry must fit in
  *     GSR_NOALLOC_BYTES; a scene and image too large for even one entry is
  *     refused with GSR_ECAPACITY before anything is enqueued.  More entries

@@ -75,10 +75,8 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
         off = align256(off + bytes);
         return o;
     };
-    L->xy = take(8 * n);
-    L->conic_o = take(16 * n);
-    L->sw = take(48 * n);
     L->splat = take(64 * n);
+    L->colour = take(16 * n);
     L->zd = take(8 * n);
     L->rect = take(16 * n);
     L->touched = take(4 * n);
@@ -167,10 +165,8 @@ int check_camera(const gsr_camera* c) {
 
 gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t hist, int64_t k1, int64_t v1) {
     gsr::FrameBufs b;
-    b.xy = (float2*)(base + L.xy);
-    b.co = (float4*)(base + L.conic_o);
-    b.sw = (float4*)(base + L.sw);
     b.pk = (float4*)(base + L.splat);
+    b.col = (float4*)(base + L.colour);
     b.zd = (float2*)(base + L.zd);
     b.rect = (int4*)(base + L.rect);
     b.touched = (uint32_t*)(base + L.touched);
@@ -372,10 +368,8 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     std::memset(&ra, 0, sizeof(ra));
     ra.cam = dc;
     ra.n = (uint32_t)scene->n;
-    ra.xy = b.xy;
-    ra.co = b.co;
-    ra.sw = b.sw;
     ra.pk = b.pk;
+    ra.col = b.col;
     ra.zd = b.zd;
     ra.vals = b.vals[0];
     ra.ranges = b.ranges;
@@ -458,10 +452,8 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     std::memset(&ra, 0, sizeof(ra));
     ra.cam = dc;
     ra.n = (uint32_t)scene->n;
-    ra.xy = b.xy;
-    ra.co = b.co;
-    ra.sw = b.sw;
     ra.pk = b.pk;
+    ra.col = b.col;
     ra.zd = b.zd;
     ra.vals = b.vals[0];
     ra.ranges = b.ranges;
@@ -479,7 +471,7 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     ra.status = status_dev;
     set_prefix_lists(ra, b, gsr::kListSorted);
     if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render backward");
-    if ((e = gsr::launch_preprocess_backward(sc, dc, b.co, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
+    if ((e = gsr::launch_preprocess_backward(sc, dc, b.pk, g2, dmeans, dscales, drots, dopac, dsh, s)) != hipSuccess)
         return fail_hip(e, "preprocess backward");
     return GSR_OK;
 }
@@ -494,7 +486,7 @@ constexpr int kBatchQueue0 = 16;
 constexpr int kBatchCounters = kBatchQueue0 + 2 * gsr::kBatchQueues;
 
 struct BatchLayout {
-    int64_t views, xy, co, sw, pk, zd, rect, touched, kmask, offsets, dhist, ranges, counters;
+    int64_t views, pk, col, zd, rect, touched, kmask, offsets, dhist, ranges, counters;
     int64_t pre_vals, pre_len, tile_flag, flist;
     int64_t keys[2], vals[2], hist, partial;
     int64_t tkeys[2], tvals[2], thist, tpartial;
@@ -509,10 +501,8 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
         return o;
     };
     L->views = take((int64_t)sizeof(gsr::ViewDev) * n_views);
-    L->xy = take(8 * R);
-    L->co = take(16 * R);
-    L->sw = take(48 * R);
     L->pk = take(64 * R);
+    L->col = take(16 * R);
     L->zd = take(8 * R);
     L->rect = take(16 * R);
     L->touched = take(4 * R);
@@ -601,10 +591,8 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     char* base = b->ws;
     const BatchLayout& L = b->L;
     gsr::FrameBufs fb;
-    fb.xy = (float2*)(base + L.xy);
-    fb.co = (float4*)(base + L.co);
-    fb.sw = (float4*)(base + L.sw);
     fb.pk = (float4*)(base + L.pk);
+    fb.col = (float4*)(base + L.col);
     fb.zd = (float2*)(base + L.zd);
     fb.rect = (int4*)(base + L.rect);
     fb.touched = (uint32_t*)(base + L.touched);
@@ -632,10 +620,8 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     if ((e = gsr::launch_fill_u32(fb.counters + 2, 1, (uint32_t)b->tiles, s)) != hipSuccess) return fail_hip(e, "clear");
     auto shifted = [&](int64_t r0) {
         gsr::FrameBufs v = fb;
-        v.xy += r0;
-        v.co += r0;
-        v.sw += 3 * r0;
         v.pk += 4 * r0;
+        v.col += r0;
         v.zd += r0;
         v.rect += r0;
         v.touched += r0;
@@ -688,10 +674,8 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     ba.views = (const gsr::ViewDev*)(base + L.views);
     ba.n_views = (int)b->views.size();
     ba.n_records = (uint32_t)b->R;
-    ba.xy = fb.xy;
-    ba.co = fb.co;
-    ba.sw = fb.sw;
     ba.pk = fb.pk;
+    ba.col = fb.col;
     ba.zd = fb.zd;
     ba.vals = fb.vals[0];
     ba.ranges = fb.ranges;

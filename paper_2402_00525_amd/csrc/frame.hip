@@ -100,10 +100,8 @@ __device__ __forceinline__ uint32_t wave_reduce_add(uint32_t v) {
 }
 
 struct PreOut {
-    float2* xy;
-    float4* co;
-    float4* sw;
     float4* pk;
+    float4* col;
     float2* zd;
     int4* rect;
 };
@@ -288,28 +286,20 @@ __device__ void write_records(const PreOut& out, int i, bool ok, const ProjOut& 
         g.s00 = po.Si[0]; g.s01 = po.Si[1]; g.s02 = po.Si[2]; g.s11 = po.Si[3]; g.s12 = po.Si[4]; g.s22 = po.Si[5];
         g.w0 = po.w[0]; g.w1 = po.w[1]; g.w2 = po.w[2];
         rc = po.rc;
-        out.xy[i] = make_float2(po.mx, po.my);
-        out.co[i] = make_float4(po.ca, po.cb, po.cc, po.op);
-        out.sw[3 * i] = make_float4(po.Si[0], po.Si[1], po.Si[2], po.Si[3]);
-        out.sw[3 * i + 1] = make_float4(po.Si[4], po.Si[5], po.w[0], po.w[1]);
-        out.sw[3 * i + 2] = make_float4(po.w[2], rgb[0], rgb[1], rgb[2]);
         out.pk[4 * i] = make_float4(po.mx, po.my, po.ca, po.cb);
         out.pk[4 * i + 1] = make_float4(po.cc, po.op, po.Si[0], po.Si[1]);
         out.pk[4 * i + 2] = make_float4(po.Si[2], po.Si[3], po.Si[4], po.Si[5]);
         out.pk[4 * i + 3] = make_float4(po.w[0], po.w[1], po.w[2], g.lt);
+        out.col[i] = make_float4(rgb[0], rgb[1], rgb[2], po.dist);
         out.zd[i] = make_float2(po.pz, po.dist);
         out.rect[i] = rc;
     } else {
         const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        out.xy[i] = make_float2(0.0f, 0.0f);
-        out.co[i] = z4;
-        out.sw[3 * i] = z4;
-        out.sw[3 * i + 1] = z4;
-        out.sw[3 * i + 2] = z4;
         out.pk[4 * i] = z4;
         out.pk[4 * i + 1] = z4;
         out.pk[4 * i + 2] = z4;
         out.pk[4 * i + 3] = z4;
+        out.col[i] = z4;
         out.zd[i] = make_float2(0.0f, 0.0f);
         out.rect[i] = make_int4(0, 0, 0, 0);
     }
@@ -630,9 +620,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
 struct DupArgs {
     DevCam cam;
     int n, mode, lb, flags;
-    const float2* xy;
-    const float4* co;
-    const float4* sw;
     const float4* pk;
     const float2* zd;
     const int4* rect;
@@ -931,7 +918,7 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
 struct BwdArgs {
     SceneArgs sc;
     DevCam cam;
-    const float4* co;
+    const float4* pk;
     const float* g2;
     float* dmeans;
     float* dscales;
@@ -950,7 +937,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
     if (i >= a.sc.n) return;
     const int deg = a.sc.deg, K = (deg + 1) * (deg + 1);
     float* dsh = a.dsh + (size_t)i * 3 * K;
-    const bool vis = a.co[i].w > 0.0f;
+    const bool vis = a.pk[4 * (size_t)i + 1].y > 0.0f;  // opacity; zero when culled
     if (!vis) {
         for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.0f;
         for (int j = 0; j < 3; ++j) a.dmeans[3 * i + j] = a.dscales[3 * i + j] = 0.0f;
@@ -1142,7 +1129,7 @@ hipError_t launch_preprocess(const SceneArgs& sc, const DevCam& cam, int mode, i
     a.mode = mode;
     a.lb = lb;
     a.flags = flags;
-    a.out = PreOut{b.xy, b.co, b.sw, b.pk, b.zd, b.rect};
+    a.out = PreOut{b.pk, b.col, b.zd, b.rect};
     a.touched = b.touched;
     a.kmask = b.kmask;
     a.dhist = groups ? groups->hist : nullptr;
@@ -1177,9 +1164,6 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flag
     a.mode = mode;
     a.lb = lb;
     a.flags = flags;
-    a.xy = b.xy;
-    a.co = b.co;
-    a.sw = b.sw;
     a.pk = b.pk;
     a.zd = b.zd;
     a.rect = b.rect;
@@ -1200,11 +1184,11 @@ hipError_t launch_duplicate(int n, const DevCam& cam, int mode, int lb, int flag
 }
 
 
-hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* co, const float* grad2d,
+hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* pk, const float* grad2d,
                                       float* dmeans, float* dscales, float* drots, float* dopac, float* dsh,
                                       hipStream_t s) {
     if (sc.n == 0) return hipSuccess;
-    BwdArgs a{sc, cam, co, grad2d, dmeans, dscales, drots, dopac, dsh};
+    BwdArgs a{sc, cam, pk, grad2d, dmeans, dscales, drots, dopac, dsh};
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)div_up(sc.n, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -17,10 +17,8 @@ constexpr int kNoLoadBalance = 1 << 30;
 
 // Device regions of one frame inside the caller's workspace.
 struct FrameBufs {
-    float2* xy;
-    float4* co;       // conic (a, b, c) + opacity
-    float4* sw;       // 3 float4 per Gaussian: Sigma^-1 (6), w (3), rgb (3)
     float4* pk;       // 4 float4 per Gaussian: the splat as the renderer reads it
+    float4* col;      // colour (r, g, b) and |mu - o|
     float2* zd;       // view depth, |mu - o|
     int4* rect;       // tile rectangle, inclusive
     uint32_t* touched;
@@ -126,10 +124,8 @@ hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint6
 struct RenderArgs {
     DevCam cam;
     uint32_t n;   // number of Gaussians (ids are checked against it)
-    const float2* xy;
-    const float4* co;
-    const float4* sw;
     const float4* pk;
+    const float4* col;
     const float2* zd;
     const uint32_t* vals;
     const uint32_t* ranges;
@@ -194,10 +190,8 @@ struct BatchArgs {
     const ViewDev* views;
     int n_views;
     uint32_t n_records;
-    const float2* xy;
-    const float4* co;
-    const float4* sw;
     const float4* pk;
+    const float4* col;
     const float2* zd;
     const uint32_t* vals;
     const uint32_t* ranges;   // per global tile
@@ -224,7 +218,7 @@ bool hier_head_supported(int head);
 hipError_t launch_render_hier(const RenderArgs& a, int head, hipStream_t s);
 
 // Per-Gaussian chain from the 2D gradients to the parameters.
-hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* co, const float* grad2d,
+hipError_t launch_preprocess_backward(const SceneArgs& sc, const DevCam& cam, const float4* pk, const float* grad2d,
                                       float* dmeans, float* dscales, float* drots, float* dopac, float* dsh,
                                       hipStream_t s);
 

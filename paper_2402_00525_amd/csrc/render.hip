@@ -51,7 +51,7 @@ enum { kWorkTailTest = 0, kWorkTailKey, kWorkMidTest, kWorkMidKey, kWorkHeadTest
 
 constexpr int kBatch = 32;
 // Backward: per-tile LDS accumulators for the first kAccSlots list entries.
-constexpr int kAccSlots = 1024;
+constexpr int kAccSlots = 512;
 constexpr int kTailCap = 64;
 constexpr int kPop = 16;
 constexpr int kMidCap = 8;
@@ -100,7 +100,7 @@ struct WaveQueues {
     uint32_t mid[16][kMidCap];
 };
 
-constexpr bool head_keeps_ids(int K) { return K <= 8; }
+constexpr bool head_keeps_ids(int K, int MODE) { return K <= 8 && MODE != kBwd; }
 
 template <int K, int MODE>
 struct PixelState {
@@ -115,12 +115,12 @@ struct PixelState {
     // colour load; large heads save those registers and read ids[rank].
     uint64_t hk[K];
     float ha[K];
-    uint32_t hid[head_keeps_ids(K) ? K : 1];  // the slots' Gaussians (small heads only)
+    uint32_t hid[head_keeps_ids(K, MODE) ? K : 1];  // the slots' Gaussians (small heads only)
     int hn;
     const uint32_t* ids;
     uint32_t n_ids;  // Gaussians: ids at or above are read as 0
-    // backward only: dL/dC, final colour without background, final transmittance
-    float g0, g1, g2, F0, F1, F2, TN;
+    // backward only: dL/dC and the forward's final colour (background included)
+    float g0, g1, g2, R0, R1, R2;
     float px, py;
     // forward: the last blend's colour terms, added at the next blend (or
     // at the end) so that its colour load is in flight meanwhile
@@ -140,9 +140,9 @@ struct PixelState {
 template <int K, int MODE>
 __device__ __forceinline__ void flush_colour(PixelState<K, MODE>& s) {
     if (!defer_colour(K, MODE)) return;
-    s.C0 = s.C0 + (s.pe.y * s.pa) * s.pT;
-    s.C1 = s.C1 + (s.pe.z * s.pa) * s.pT;
-    s.C2 = s.C2 + (s.pe.w * s.pa) * s.pT;
+    s.C0 = s.C0 + (s.pe.x * s.pa) * s.pT;
+    s.C1 = s.C1 + (s.pe.y * s.pa) * s.pT;
+    s.C2 = s.C2 + (s.pe.z * s.pa) * s.pT;
 }
 
 template <int K, int MODE>
@@ -216,11 +216,11 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         s.done = true;
         return;
     }
-    const float4 e = a.sw[3 * id + 2];
+    const float4 e = a.col[id];
     if (!defer_colour(K, MODE)) {
-        s.C0 = s.C0 + (e.y * alpha) * s.T;
-        s.C1 = s.C1 + (e.z * alpha) * s.T;
-        s.C2 = s.C2 + (e.w * alpha) * s.T;
+        s.C0 = s.C0 + (e.x * alpha) * s.T;
+        s.C1 = s.C1 + (e.y * alpha) * s.T;
+        s.C2 = s.C2 + (e.z * alpha) * s.T;
     } else {
         flush_colour(s);
         s.pe = e;
@@ -237,12 +237,12 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
     }
     if (MODE == kBwd) {
         // Sec. 3.5, front to back: everything behind this Gaussian contributes
-        // C - C_i (C_i includes it), and dC/dalpha = c T - (C - C_i + T_N bg) / (1 - alpha).
+        // C - C_i (C_i includes it), and dC/dalpha = c T - (C - C_i + T_N bg) / (1 - alpha),
+        // where C + T_N bg is the forward's output R.
         const float w = alpha * s.T;
         const float inv = 1.0f / (1.0f - alpha);
-        const float ga = s.g0 * (e.y * s.T - ((s.F0 - s.C0) + s.TN * a.bg0) * inv) +
-                         s.g1 * (e.z * s.T - ((s.F1 - s.C1) + s.TN * a.bg1) * inv) +
-                         s.g2 * (e.w * s.T - ((s.F2 - s.C2) + s.TN * a.bg2) * inv);
+        const float ga = s.g0 * (e.x * s.T - (s.R0 - s.C0) * inv) + s.g1 * (e.y * s.T - (s.R1 - s.C1) * inv) +
+                         s.g2 * (e.z * s.T - (s.R2 - s.C2) * inv);
         if (s.gpend)  // not flushed since the last blend: add those terms directly
             for (int c = 0; c < 9; ++c) add_grad(a, acc, s.grank, s.gid, c, s.gv[c]);
         s.gpend = true;
@@ -282,7 +282,7 @@ __device__ __forceinline__ uint32_t head_id(const PixelState<K, MODE>& s, uint64
 // Gaussian of the front slot.
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t front_id(const PixelState<K, MODE>& s) {
-    if (head_keeps_ids(K)) return s.hid[0];
+    if (head_keeps_ids(K, MODE)) return s.hid[0];
     return head_id(s, s.hk[0]);
 }
 
@@ -296,7 +296,7 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
     for (int i = 0; i + 1 < K; ++i) {
         s.hk[i] = s.hk[i + 1];
         s.ha[i] = s.ha[i + 1];
-        if (head_keeps_ids(K)) s.hid[i] = s.hid[i + 1];
+        if (head_keeps_ids(K, MODE)) s.hid[i] = s.hid[i + 1];
     }
     s.hk[K - 1] = kInvalidKey;
     s.ha[K - 1] = 0.0f;
@@ -323,7 +323,7 @@ __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key
         const float pa = i > 0 ? s.ha[i - 1] : 0.0f;
         s.hk[i] = c[i] ? s.hk[i] : (take ? key : pk);
         s.ha[i] = c[i] ? s.ha[i] : (take ? alpha : pa);
-        if (head_keeps_ids(K)) {
+        if (head_keeps_ids(K, MODE)) {
             const uint32_t pi = i > 0 ? s.hid[i - 1] : 0u;
             s.hid[i] = c[i] ? s.hid[i] : (take ? id : pi);
         }
@@ -361,7 +361,7 @@ __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MOD
         const float na = i + 1 < K ? s.ha[i + 1] : 0.0f;
         s.hk[i] = c[i] ? nk : (take ? key : s.hk[i]);
         s.ha[i] = c[i] ? na : (take ? alpha : s.ha[i]);
-        if (head_keeps_ids(K)) {
+        if (head_keeps_ids(K, MODE)) {
             const uint32_t ni = i + 1 < K ? s.hid[i + 1] : 0u;
             s.hid[i] = c[i] ? ni : (take ? id : s.hid[i]);
         }
@@ -555,16 +555,15 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
         h.st.g0 = a.dL[p];
         h.st.g1 = a.dL[P + p];
         h.st.g2 = a.dL[2 * P + p];
-        h.st.TN = a.T_in[p];
-        h.st.F0 = a.rgb_in[p] - h.st.TN * a.bg0;
-        h.st.F1 = a.rgb_in[P + p] - h.st.TN * a.bg1;
-        h.st.F2 = a.rgb_in[2 * P + p] - h.st.TN * a.bg2;
+        h.st.R0 = a.rgb_in[p];
+        h.st.R1 = a.rgb_in[P + p];
+        h.st.R2 = a.rgb_in[2 * P + p];
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         h.st.hk[i] = kInvalidKey;
         h.st.ha[i] = 0.0f;
-        if (head_keeps_ids(K)) h.st.hid[i] = 0u;
+        if (head_keeps_ids(K, MODE)) h.st.hid[i] = 0u;
     }
     h.ms = 0;
     h.mn = 0;
@@ -735,7 +734,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
 }
 
 template <int K, int MODE>
-__global__ __launch_bounds__(256) void k_render_hier(RenderArgs a) {
+__global__ __launch_bounds__(256, 3) void k_render_hier(RenderArgs a) {
     __shared__ WaveQueues s_q[4];
     __shared__ uint32_t s_consumed[4];
     __shared__ float s_acc[MODE == kBwd ? 9 * kAccSlots : 1];
@@ -832,9 +831,7 @@ __device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t s
     RenderArgs a;
     a.cam = vd.cam;
     a.n = b.n_records;
-    a.xy = b.xy;
-    a.co = b.co;
-    a.sw = b.sw;
+    a.col = b.col;
     a.pk = b.pk;
     a.zd = b.zd;
     a.vals = b.vals;
@@ -896,9 +893,9 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
 
 template <bool DEBUG>
 __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
-    __shared__ float2 s_xy[256];
-    __shared__ float4 s_co[256];
-    __shared__ float4 s_cd[256];
+    __shared__ float4 s_xc[256];  // x, y, conic a, b
+    __shared__ float2 s_co[256];  // conic c, opacity
+    __shared__ float4 s_cd[256];  // colour, |mu - o|
     __shared__ uint32_t s_id[256];
     const DevCam& cam = a.cam;
     const int tile = blockIdx.x;
@@ -923,23 +920,24 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
             uint32_t id = tl.ids[idx];
             id = id < a.n ? id : 0u;
             s_id[threadIdx.x] = id;
-            s_xy[threadIdx.x] = a.xy[id];
-            s_co[threadIdx.x] = a.co[id];
-            const float4 e = a.sw[3 * id + 2];
-            s_cd[threadIdx.x] = make_float4(e.y, e.z, e.w, a.zd[id].y);
+            const float4 p0 = a.pk[4 * (size_t)id], p1 = a.pk[4 * (size_t)id + 1];
+            s_xc[threadIdx.x] = p0;
+            s_co[threadIdx.x] = make_float2(p1.x, p1.y);
+            s_cd[threadIdx.x] = a.col[id];
         }
         __syncthreads();
         const uint32_t cnt = (end - start) < 256u ? (end - start) : 256u;
         consumed += cnt;
         for (uint32_t k = 0; k < cnt && !done; ++k) {
             Splat g;
-            g.x = s_xy[k].x;
-            g.y = s_xy[k].y;
-            const float4 c = s_co[k];
-            g.ca = c.x;
-            g.cb = c.y;
-            g.cc = c.z;
-            g.op = c.w;
+            const float4 xc = s_xc[k];
+            const float2 c = s_co[k];
+            g.x = xc.x;
+            g.y = xc.y;
+            g.ca = xc.z;
+            g.cb = xc.w;
+            g.cc = c.x;
+            g.op = c.y;
             g.lt = __int_as_float(0x7fc00000);
             float alpha;
             if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
@@ -1014,7 +1012,7 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     for (int i = 0; i < K; ++i) {
         st.hk[i] = kInvalidKey;
         st.ha[i] = 0.0f;
-        if (head_keeps_ids(K)) st.hid[i] = 0u;
+        if (head_keeps_ids(K, MODE)) st.hid[i] = 0u;
     }
     uint32_t consumed = 0;
     for (uint32_t start = begin; start < end; start += 256) {

@@ -51,7 +51,7 @@ class CConfig(C.Structure):
 
 class CLayout(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
-                ("xy", "conic_o", "sw", "splat", "zd", "rect", "touched", "kmask", "offsets", "dup_hist", "grad2d", "keys",
+                ("splat", "colour", "zd", "rect", "touched", "kmask", "offsets", "dup_hist", "grad2d", "keys",
                  "values",
                  "ranges", "counters", "pre_vals", "pre_len", "tile_flag", "entry_capacity", "total_bytes")]
 
@@ -315,12 +315,17 @@ class Renderer:
         return int(c[k].item())
 
     def records(self, n, cam):
-        """Per-Gaussian records of the last frame (device tensors)."""
+        """Per-Gaussian records of the last frame (device tensors): the packed
+        splat and colour as stored, and views of them by quantity -- xy (2D
+        mean), conic_o (a, b, c, opacity), sw (Sigma^-1, w, rgb)."""
+        splat = self.region(n, cam, "splat", torch.float32, 16 * n).view(n, 16)
+        colour = self.region(n, cam, "colour", torch.float32, 4 * n).view(n, 4)
         return dict(
-            xy=self.region(n, cam, "xy", torch.float32, 2 * n).view(n, 2),
-            conic_o=self.region(n, cam, "conic_o", torch.float32, 4 * n).view(n, 4),
-            sw=self.region(n, cam, "sw", torch.float32, 12 * n).view(n, 12),
-            splat=self.region(n, cam, "splat", torch.float32, 16 * n).view(n, 16),
+            xy=splat[:, 0:2],
+            conic_o=splat[:, 2:6],
+            sw=torch.cat([splat[:, 6:15], colour[:, 0:3]], dim=1),
+            splat=splat,
+            colour=colour,
             zd=self.region(n, cam, "zd", torch.float32, 2 * n).view(n, 2),
             rect=self.region(n, cam, "rect", torch.int32, 4 * n).view(n, 4),
             touched=self.region(n, cam, "touched", torch.int32, n),

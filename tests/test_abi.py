@@ -83,7 +83,7 @@ def test_workspace_planning_roundtrip(L):
         lay = L.layout(n, W, H, nbytes)
         assert lay.entry_capacity >= E
         assert lay.total_bytes <= nbytes
-        offs = sorted([lay.xy, lay.conic_o, lay.sw, lay.zd, lay.rect, lay.touched, lay.offsets, lay.keys,
+        offs = sorted([lay.splat, lay.colour, lay.zd, lay.rect, lay.touched, lay.offsets, lay.keys,
                        lay.values, lay.ranges, lay.counters])
         assert all(o % 256 == 0 for o in offs)
         assert len(set(offs)) == len(offs) or n == 0

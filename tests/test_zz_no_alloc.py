@@ -48,7 +48,7 @@ def test_noalloc_matches_render_twice():
 
 def test_noalloc_refuses_what_does_not_fit():
     from paper_2402_00525_amd import gsr
-    sc = synth.uniform_scene(400_000, seed=0, sh_degree=0)   # per-Gaussian regions alone exceed 64 MiB
+    sc = synth.uniform_scene(600_000, seed=0, sh_degree=0)   # per-Gaussian regions alone exceed 64 MiB
     ds = gsr.DeviceScene.from_host(sc)
     with pytest.raises(gsr.GsrError) as e:
         gsr.render_noalloc(ds, synth.orbit_camera(1920, 1080, view=0), gsr.config())
