@@ -101,6 +101,13 @@ struct WaveQueues {
 };
 
 constexpr bool head_keeps_ids(int K, int MODE) { return K <= 8 && MODE != kBwd; }
+// Large forward heads keep their alphas in LDS (one word per lane and slot),
+// not in registers: with the keys alone the K = 16 head fits three
+// wavefronts per SIMD.  Their keys' low word is then rank << 5 | slot, where
+// slot is the LDS word of the entry's alpha, so list ranks must stay below
+// kMaxPayloadRank.
+constexpr bool head_alpha_in_lds(int K, int MODE) { return K >= 12 && MODE != kBwd; }
+constexpr uint32_t kMaxPayloadRank = 1u << 27;
 
 template <int K, int MODE>
 struct PixelState {
@@ -114,9 +121,10 @@ struct PixelState {
     // slot's Gaussian, so that a blend needs no dependent load before its
     // colour load; large heads save those registers and read ids[rank].
     uint64_t hk[K];
-    float ha[K];
+    float ha[head_alpha_in_lds(K, MODE) ? 1 : K];   // alphas in registers (else in pay)
     uint32_t hid[head_keeps_ids(K, MODE) ? K : 1];  // the slots' Gaussians (small heads only)
     int hn;
+    float* pay;  // large heads: this lane's alpha of LDS slot j at pay[64 j]
     const uint32_t* ids;
     uint32_t n_ids;  // Gaussians: ids at or above are read as 0
     // backward only: dL/dC and the forward's final colour (background included)
@@ -271,37 +279,48 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
     s.T = Tn;
 }
 
-// Gaussian of a head key (see PixelState::hk).
+// List rank of a head key (see PixelState::hk).
+template <int K, int MODE>
+__device__ __forceinline__ uint32_t key_rank(uint64_t key) {
+    return head_alpha_in_lds(K, MODE) ? (uint32_t)key >> 5 : (uint32_t)key;
+}
+
+// Gaussian of a head key.
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t head_id(const PixelState<K, MODE>& s, uint64_t key) {
-    const uint32_t lo = (uint32_t)key;
+    const uint32_t lo = key_rank<K, MODE>(key);
     const uint32_t id = s.ids ? s.ids[lo] : lo;
     return id < s.n_ids ? id : 0u;
 }
 
-// Gaussian of the front slot.
+// Gaussian and alpha of the front slot.
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t front_id(const PixelState<K, MODE>& s) {
     if (head_keeps_ids(K, MODE)) return s.hid[0];
     return head_id(s, s.hk[0]);
+}
+template <int K, int MODE>
+__device__ __forceinline__ float front_alpha(const PixelState<K, MODE>& s) {
+    if (head_alpha_in_lds(K, MODE)) return s.pay[64 * ((uint32_t)s.hk[0] & 31u)];
+    return s.ha[0];
 }
 
 // Remove the front of the head and blend it.
 template <int K, int MODE>
 __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K, MODE>& s, int pix, float* acc) {
     const uint64_t k0 = s.hk[0];
-    const float a0 = s.ha[0];
+    const float a0 = front_alpha(s);
     const uint32_t i0 = front_id(s);
 #pragma unroll
     for (int i = 0; i + 1 < K; ++i) {
         s.hk[i] = s.hk[i + 1];
-        s.ha[i] = s.ha[i + 1];
+        if (!head_alpha_in_lds(K, MODE)) s.ha[i] = s.ha[i + 1];
         if (head_keeps_ids(K, MODE)) s.hid[i] = s.hid[i + 1];
     }
     s.hk[K - 1] = kInvalidKey;
-    s.ha[K - 1] = 0.0f;
+    if (!head_alpha_in_lds(K, MODE)) s.ha[K - 1] = 0.0f;
     s.hn -= 1;
-    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), (uint32_t)k0, acc);
+    blend_one<K, MODE>(a, s, pix, i0, a0, depth_from_bits((uint32_t)(k0 >> 32)), key_rank<K, MODE>(k0), acc);
 }
 
 // Insertion into the sorted head (s.hn < K on entry, so the last slot is
@@ -309,9 +328,15 @@ __device__ __forceinline__ void head_pop_blend(const RenderArgs& a, PixelState<K
 // the slots before the entry's place, slot i keeps its key if c_i, takes the
 // entry if c_(i-1) (or i = 0) and not c_i, and else its predecessor's.  Every
 // slot takes its new value by selects, never by a store at a computed slot,
-// so the head stays in registers at every K.
+// so the head stays in registers at every K.  `key` is in head form (see
+// head_push); a large head puts the alpha into LDS word s.hn, the first free
+// one (entries leave only in the drain, after the last insertion).
 template <int K, int MODE>
 __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key, uint32_t id, float alpha) {
+    if (head_alpha_in_lds(K, MODE)) {
+        s.pay[64 * s.hn] = alpha;
+        key |= (uint64_t)(uint32_t)s.hn;
+    }
     bool c[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) c[i] = s.hk[i] < key;
@@ -320,9 +345,11 @@ __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key
     for (int i = K - 1; i >= 0; --i) {
         const bool take = i == 0 || c[i - 1];
         const uint64_t pk = i > 0 ? s.hk[i - 1] : 0ull;
-        const float pa = i > 0 ? s.ha[i - 1] : 0.0f;
         s.hk[i] = c[i] ? s.hk[i] : (take ? key : pk);
-        s.ha[i] = c[i] ? s.ha[i] : (take ? alpha : pa);
+        if (!head_alpha_in_lds(K, MODE)) {
+            const float pa = i > 0 ? s.ha[i - 1] : 0.0f;
+            s.ha[i] = c[i] ? s.ha[i] : (take ? alpha : pa);
+        }
         if (head_keeps_ids(K, MODE)) {
             const uint32_t pi = i > 0 ? s.hid[i - 1] : 0u;
             s.hid[i] = c[i] ? s.hid[i] : (take ? id : pi);
@@ -337,17 +364,30 @@ __device__ __forceinline__ void head_insert(PixelState<K, MODE>& s, uint64_t key
 // front) is blended and the other K stay sorted, in one pass of selects:
 // with c_i = (slot i + 1 holds a key below the entry) and c_(-1) = (the front
 // is below the entry), slot i takes slot i + 1's key if c_i, the entry if
-// c_(i-1) and not c_i, and else keeps its own.
+// c_(i-1) and not c_i, and else keeps its own.  `key` = t_opt bits << 32 |
+// list rank; a large head stores rank << 5 | (its alpha's LDS word), the
+// word the blended front frees.
 template <int K, int MODE>
 __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MODE>& s, int pix, uint64_t key,
                                           uint32_t id, float alpha, float* acc) {
+    if (head_alpha_in_lds(K, MODE)) key = (key & 0xffffffff00000000ull) | ((key & 0xffffffffull) << 5);
     if (s.hn < K) {
         head_insert<K, MODE>(s, key, id, alpha);
         return;
     }
     const uint64_t k0 = s.hk[0];
-    const float a0 = s.ha[0];
     const bool front_goes = k0 < key;
+    float a0;
+    if (head_alpha_in_lds(K, MODE)) {
+        const uint32_t w = (uint32_t)k0 & 31u;
+        a0 = s.pay[64 * w];
+        if (front_goes) {
+            s.pay[64 * w] = alpha;
+            key |= (uint64_t)w;
+        }
+    } else {
+        a0 = s.ha[0];
+    }
     const uint32_t bid = front_goes ? front_id(s) : id;
     bool c[K];
 #pragma unroll
@@ -358,17 +398,19 @@ __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MOD
     for (int i = 0; i < K; ++i) {
         const bool take = i == 0 ? front_goes : c[i - 1];
         const uint64_t nk = i + 1 < K ? s.hk[i + 1] : 0ull;
-        const float na = i + 1 < K ? s.ha[i + 1] : 0.0f;
         s.hk[i] = c[i] ? nk : (take ? key : s.hk[i]);
-        s.ha[i] = c[i] ? na : (take ? alpha : s.ha[i]);
+        if (!head_alpha_in_lds(K, MODE)) {
+            const float na = i + 1 < K ? s.ha[i + 1] : 0.0f;
+            s.ha[i] = c[i] ? na : (take ? alpha : s.ha[i]);
+        }
         if (head_keeps_ids(K, MODE)) {
             const uint32_t ni = i + 1 < K ? s.hid[i + 1] : 0u;
             s.hid[i] = c[i] ? ni : (take ? id : s.hid[i]);
         }
     }
     const uint64_t bk = front_goes ? k0 : key;
-    blend_one<K, MODE>(a, s, pix, bid, front_goes ? a0 : alpha, depth_from_bits((uint32_t)(bk >> 32)), (uint32_t)bk,
-                       acc);
+    blend_one<K, MODE>(a, s, pix, bid, front_goes ? a0 : alpha, depth_from_bits((uint32_t)(bk >> 32)),
+                       key_rank<K, MODE>(bk), acc);
 }
 
 template <int K, int MODE>
@@ -472,7 +514,9 @@ struct HierCtx {
             wave_lds_sync();
             ms = 0;
             mn += nnew;
-            while (mn > kMidCap - kMidBatch) {
+            // at most one pop: the queue held at most kMidBatch before this
+            // sub-batch of at most kMidBatch (kMidCap = 2 kMidBatch)
+            if (mn > kMidCap - kMidBatch) {
                 push_head(kMidBatch, ms);
                 ms += kMidBatch;
                 mn -= kMidBatch;
@@ -509,7 +553,7 @@ __device__ __forceinline__ TileList tile_list(const RenderArgs& a, int t) {
 
 template <int K, int MODE>
 __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, int range_tile, int strip,
-                                                 WaveQueues& q, float* acc) {
+                                                 WaveQueues& q, float* acc, float* pay) {
     const int lane = threadIdx.x & 63, wave = strip;
     const DevCam& cam = a.cam;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -562,7 +606,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         h.st.hk[i] = kInvalidKey;
-        h.st.ha[i] = 0.0f;
+        if (!head_alpha_in_lds(K, MODE)) h.st.ha[i] = 0.0f;
         if (head_keeps_ids(K, MODE)) h.st.hid[i] = 0u;
     }
     h.ms = 0;
@@ -576,11 +620,13 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const uint32_t* list = tl.ids;
     h.st.ids = list;
     h.st.n_ids = a.n;
+    h.st.pay = pay + lane;
     // A truncated prefix is walked in whole batches only: the last, partial
     // batch of a prefix is not the batch the whole list has at that place,
     // and the pops that follow it could differ.  The strip is then flagged
     // unless its pixels finished within the whole batches.
-    const uint32_t end = tl.truncated ? (tl.len & ~(uint32_t)(kBatch - 1)) : tl.len;
+    uint32_t end = tl.truncated ? (tl.len & ~(uint32_t)(kBatch - 1)) : tl.len;
+    if (head_alpha_in_lds(K, MODE) && end > kMaxPayloadRank) end = kMaxPayloadRank;  // ranks fit 27 bits
     const bool truncated = tl.truncated;
     const uint32_t begin = 0;
     uint32_t b0 = begin;
@@ -734,8 +780,9 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
 }
 
 template <int K, int MODE>
-__global__ __launch_bounds__(256, 3) void k_render_hier(RenderArgs a) {
+__global__ __launch_bounds__(256, K <= 4 ? 3 : 2) void k_render_hier(RenderArgs a) {
     __shared__ WaveQueues s_q[4];
+    __shared__ float s_pay[head_alpha_in_lds(K, MODE) ? 4 * 64 * K : 1];
     __shared__ uint32_t s_consumed[4];
     __shared__ float s_acc[MODE == kBwd ? 9 * kAccSlots : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -755,7 +802,7 @@ __global__ __launch_bounds__(256, 3) void k_render_hier(RenderArgs a) {
         __syncthreads();
     }
     const uint32_t c = render_strip<K, MODE>(a, blockIdx.x, blockIdx.x, wave, s_q[wave],
-                                             MODE == kBwd ? s_acc : nullptr);
+                                             MODE == kBwd ? s_acc : nullptr, s_pay + wave * 64 * K);
     if (lane == 0) s_consumed[wave] = c;
     __syncthreads();
     if (MODE != kBwd && threadIdx.x == 0) {
@@ -793,11 +840,12 @@ __global__ __launch_bounds__(256, 3) void k_render_hier(RenderArgs a) {
 template <int K, int MODE>
 __global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
     __shared__ WaveQueues s_q;
+    __shared__ float s_pay[head_alpha_in_lds(K, MODE) ? 64 * K : 1];
     const uint32_t b = blockIdx.x, g = b / 32u, r = b % 32u;
     const int strip = (int)(r / 8u), tile = (int)(g * 8u + r % 8u);
     const int n_tiles = a.cam.tiles_x * a.cam.tiles_y;
     if (tile >= n_tiles) return;
-    const uint32_t c = render_strip<K, MODE>(a, tile, tile, strip, s_q, nullptr);
+    const uint32_t c = render_strip<K, MODE>(a, tile, tile, strip, s_q, nullptr, s_pay);
     if (threadIdx.x == 0) {
         uint32_t* used = a.tile_flag + n_tiles;
         uint32_t* done = used + n_tiles;
@@ -815,7 +863,8 @@ __global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
 
 // One (tile, strip) item of the batched render: slot `slot` of the work order.
 template <int K>
-__device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t slot, uint32_t strip, WaveQueues& q) {
+__device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t slot, uint32_t strip, WaveQueues& q,
+                                                  float* pay) {
     const uint32_t gt = b.order ? b.order[slot] : slot;
     // view of global tile gt: the last view whose first tile is <= gt
     int lo = 0, hi = b.n_views - 1;
@@ -859,7 +908,7 @@ __device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t s
     a.work = nullptr;
     a.fp = nullptr;
     a.status = nullptr;
-    render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)strip, q, nullptr);
+    render_strip<K, kFwdPlain>(a, (int)(gt - vd.tile_base), (int)gt, (int)strip, q, nullptr, pay);
 }
 
 // Persistent form over many views: wavefronts pull (tile, strip) work items
@@ -873,6 +922,7 @@ __device__ __forceinline__ void render_batch_item(const BatchArgs& b, uint32_t s
 template <int K>
 __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
     __shared__ WaveQueues s_q[4];
+    __shared__ float s_pay[head_alpha_in_lds(K, kFwdPlain) ? 4 * 64 * K : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t n_slots = b.n_tiles_dev ? *b.n_tiles_dev : b.n_tiles;
     const uint32_t home = blockIdx.x % (uint32_t)kBatchQueues;
@@ -886,7 +936,7 @@ __global__ __launch_bounds__(256) void k_render_hier_batch(BatchArgs b) {
             item = __builtin_amdgcn_readfirstlane(item);
             if (item >= 4u * n_x) break;
             const uint32_t slot = (item >> 2) * (uint32_t)kBatchQueues + x;
-            render_batch_item<K>(b, slot, item & 3u, s_q[wave]);
+            render_batch_item<K>(b, slot, item & 3u, s_q[wave], s_pay + wave * 64 * K);
         }
     }
 }
@@ -988,6 +1038,7 @@ template <int K, int MODE>
 __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     __shared__ Splat s_g[256];
     __shared__ uint32_t s_id[256];
+    __shared__ float s_pay[head_alpha_in_lds(K, MODE) ? 4 * 64 * K : 1];
     const DevCam& cam = a.cam;
     const int tile = blockIdx.x;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -996,7 +1047,9 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     const int pix = py * cam.W + px;
     const TileList tl = tile_list(a, tile);
     if (tl.skip) return;
-    const uint32_t begin = 0, end = tl.len;
+    const uint32_t begin = 0;
+    // list ranks are keyed; a large window keeps them below kMaxPayloadRank
+    const uint32_t end = head_alpha_in_lds(K, MODE) && tl.len > kMaxPayloadRank ? kMaxPayloadRank : tl.len;
     const float3 d = cam_ray(cam, (float)px, (float)py);
     PixelState<K, MODE> st;
     st.T = 1.0f;
@@ -1008,10 +1061,11 @@ __global__ __launch_bounds__(256) void k_render_window(RenderArgs a) {
     st.hn = 0;
     st.ids = tl.ids;
     st.n_ids = a.n;
+    st.pay = s_pay + (threadIdx.x >> 6) * 64 * K + (threadIdx.x & 63);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         st.hk[i] = kInvalidKey;
-        st.ha[i] = 0.0f;
+        if (!head_alpha_in_lds(K, MODE)) st.ha[i] = 0.0f;
         if (head_keeps_ids(K, MODE)) st.hid[i] = 0u;
     }
     uint32_t consumed = 0;
@@ -1089,16 +1143,19 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
     st.n = 0;
     st.done = !inside;
     st.hn = 0;
-    st.ids = nullptr;  // keys carry the Gaussian id itself
+    st.ids = nullptr;
     st.n_ids = a.n;
+    // the kFullSel smallest keys of a round: t_opt bits << 32 | Gaussian id
+    uint64_t fk[K];
+    float fa[K];
     bool more = true;
     uint64_t floor_key = 0;  // keys below this were blended in earlier rounds
     while (__syncthreads_or(!st.done && more)) {
         const bool active = !st.done && more;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            st.hk[i] = kInvalidKey;
-            st.ha[i] = 0.0f;
+            fk[i] = kInvalidKey;
+            fa[i] = 0.0f;
         }
         int found = 0;
         for (uint32_t start = begin; start < end; start += 256) {
@@ -1118,21 +1175,21 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
                 float alpha;
                 if (!pixel_alpha(g, (float)px, (float)py, alpha)) continue;
                 const uint64_t key = ((uint64_t)depth_bits(t_opt(g, d)) << 32) | (uint64_t)s_id[k];
-                if (key < floor_key || key >= st.hk[K - 1]) continue;
+                if (key < floor_key || key >= fk[K - 1]) continue;
                 // insertion into the sorted K smallest; the largest drops out
 #pragma unroll
                 for (int i = K - 1; i >= 1; --i) {
-                    if (st.hk[i - 1] > key) {
-                        st.hk[i] = st.hk[i - 1];
-                        st.ha[i] = st.ha[i - 1];
-                    } else if (st.hk[i] > key) {
-                        st.hk[i] = key;
-                        st.ha[i] = alpha;
+                    if (fk[i - 1] > key) {
+                        fk[i] = fk[i - 1];
+                        fa[i] = fa[i - 1];
+                    } else if (fk[i] > key) {
+                        fk[i] = key;
+                        fa[i] = alpha;
                     }
                 }
-                if (st.hk[0] > key) {
-                    st.hk[0] = key;
-                    st.ha[0] = alpha;
+                if (fk[0] > key) {
+                    fk[0] = key;
+                    fa[0] = alpha;
                 }
                 found = found < K ? found + 1 : K;
             }
@@ -1140,11 +1197,13 @@ __global__ __launch_bounds__(256) void k_render_full(RenderArgs a) {
         if (active) {
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (i < found)
-                    blend_one<K, MODE>(a, st, pix, head_id(st, st.hk[i]), st.ha[i],
-                                       depth_from_bits((uint32_t)(st.hk[i] >> 32)), 0u, nullptr);
+                if (i < found) {
+                    const uint32_t id = (uint32_t)fk[i];
+                    blend_one<K, MODE>(a, st, pix, id < a.n ? id : 0u, fa[i], depth_from_bits((uint32_t)(fk[i] >> 32)),
+                                       0u, nullptr);
+                }
             more = found == K;
-            floor_key = st.hk[K - 1] + 1ull;
+            floor_key = fk[K - 1] + 1ull;
         }
     }
     flush_colour(st);
