@@ -273,13 +273,15 @@ const float EPS_O_F = 1.0f / 255.0f;
 template <class F> inline F eps_o() { return (F)1 / (F)255; }
 
 // t_opt along unit direction d (Eq. dopt): d^T Sigma^-1 (mu - o) / d^T Sigma^-1 d.
-// A NaN quotient (degenerate inverse covariance) is read as +infinity.
+// Each dot product is one multiplication followed by fused multiply-adds, in
+// index order.  A NaN quotient (degenerate inverse covariance) is read as
+// +infinity.
 template <class F> inline F topt(const Rec<F>& g, const F d[3]) {
-    F sd0 = (g.s[0] * d[0] + g.s[1] * d[1]) + g.s[2] * d[2];
-    F sd1 = (g.s[1] * d[0] + g.s[3] * d[1]) + g.s[4] * d[2];
-    F sd2 = (g.s[2] * d[0] + g.s[4] * d[1]) + g.s[5] * d[2];
-    F num = (d[0] * g.w[0] + d[1] * g.w[1]) + d[2] * g.w[2];
-    F den = (d[0] * sd0 + d[1] * sd1) + d[2] * sd2;
+    F sd0 = std::fma(g.s[2], d[2], std::fma(g.s[1], d[1], g.s[0] * d[0]));
+    F sd1 = std::fma(g.s[4], d[2], std::fma(g.s[3], d[1], g.s[1] * d[0]));
+    F sd2 = std::fma(g.s[5], d[2], std::fma(g.s[4], d[1], g.s[2] * d[0]));
+    F num = std::fma(d[2], g.w[2], std::fma(d[1], g.w[1], d[0] * g.w[0]));
+    F den = std::fma(d[2], sd2, std::fma(d[1], sd1, d[0] * sd0));
     F t = num / den;
     if (t != t) t = (F)INFINITY;
     return t;
@@ -564,9 +566,10 @@ template <class F> inline void blend(Pixel<F>& px, const Rec<F>& g, F alpha, F t
     if (px.done) return;
     F Tn = px.T * (F(1) - alpha);
     if (Tn < F(0.0001)) { px.done = true; return; }
-    for (int ch = 0; ch < 3; ++ch) px.C[ch] = px.C[ch] + (g.rgb[ch] * alpha) * px.T;
+    // front-to-back compositing (Eq. volume_desc), each term added by a fused multiply-add
+    for (int ch = 0; ch < 3; ++ch) px.C[ch] = std::fma(g.rgb[ch] * alpha, px.T, px.C[ch]);
     F phi = depth_is_dist ? g.dist : t;
-    px.D = px.D + (phi * alpha) * px.T;
+    px.D = std::fma(phi * alpha, px.T, px.D);
     px.n += 1;
     px.T = Tn;
     px.ids.push_back(id);
@@ -980,7 +983,7 @@ void backward_blends(const Frame<FD>& fr, const F* dL, const float bg[3], std::v
                 const F a = (F)px.alphas[k];
                 const Rec<FD>& gd = fr.recs[id];
                 const Rec<F> g = rec_as<F>(gd);
-                for (int ch = 0; ch < 3; ++ch) Cacc[ch] = Cacc[ch] + (g.rgb[ch] * a) * T;
+                for (int ch = 0; ch < 3; ++ch) Cacc[ch] = std::fma(g.rgb[ch] * a, T, Cacc[ch]);
                 F ga = 0, ga_m = 0;
                 for (int ch = 0; ch < 3; ++ch) {
                     const F dl = dL[ch * P + p];

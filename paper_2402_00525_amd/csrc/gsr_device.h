@@ -129,13 +129,14 @@ __device__ __forceinline__ Splat load_packed(const float4* __restrict__ pk, uint
 }
 
 // Depth of maximum contribution along unit direction d (Eq. dopt):
-// d^T Sigma^-1 (mu - o) / d^T Sigma^-1 d; a NaN quotient reads as +inf.
+// d^T Sigma^-1 (mu - o) / d^T Sigma^-1 d, each dot product one product and
+// fused multiply-adds in index order; a NaN quotient reads as +inf.
 __device__ __forceinline__ float t_opt(const Splat& g, float3 d) {
-    const float sd0 = (g.s00 * d.x + g.s01 * d.y) + g.s02 * d.z;
-    const float sd1 = (g.s01 * d.x + g.s11 * d.y) + g.s12 * d.z;
-    const float sd2 = (g.s02 * d.x + g.s12 * d.y) + g.s22 * d.z;
-    const float num = (d.x * g.w0 + d.y * g.w1) + d.z * g.w2;
-    const float den = (d.x * sd0 + d.y * sd1) + d.z * sd2;
+    const float sd0 = fmaf(g.s02, d.z, fmaf(g.s01, d.y, g.s00 * d.x));
+    const float sd1 = fmaf(g.s12, d.z, fmaf(g.s11, d.y, g.s01 * d.x));
+    const float sd2 = fmaf(g.s22, d.z, fmaf(g.s12, d.y, g.s02 * d.x));
+    const float num = fmaf(d.z, g.w2, fmaf(d.y, g.w1, d.x * g.w0));
+    const float den = fmaf(d.z, sd2, fmaf(d.y, sd1, d.x * sd0));
     const float t = num / den;
     return (t != t) ? __int_as_float(0x7f800000) : t;
 }

@@ -148,9 +148,9 @@ struct PixelState {
 template <int K, int MODE>
 __device__ __forceinline__ void flush_colour(PixelState<K, MODE>& s) {
     if (!defer_colour(K, MODE)) return;
-    s.C0 = s.C0 + (s.pe.x * s.pa) * s.pT;
-    s.C1 = s.C1 + (s.pe.y * s.pa) * s.pT;
-    s.C2 = s.C2 + (s.pe.z * s.pa) * s.pT;
+    s.C0 = fmaf(s.pe.x * s.pa, s.pT, s.C0);
+    s.C1 = fmaf(s.pe.y * s.pa, s.pT, s.C1);
+    s.C2 = fmaf(s.pe.z * s.pa, s.pT, s.C2);
 }
 
 template <int K, int MODE>
@@ -226,16 +226,16 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
     }
     const float4 e = a.col[id];
     if (!defer_colour(K, MODE)) {
-        s.C0 = s.C0 + (e.x * alpha) * s.T;
-        s.C1 = s.C1 + (e.y * alpha) * s.T;
-        s.C2 = s.C2 + (e.z * alpha) * s.T;
+        s.C0 = fmaf(e.x * alpha, s.T, s.C0);
+        s.C1 = fmaf(e.y * alpha, s.T, s.C1);
+        s.C2 = fmaf(e.z * alpha, s.T, s.C2);
     } else {
         flush_colour(s);
         s.pe = e;
         s.pa = alpha;
         s.pT = s.T;
     }
-    s.D = s.D + (t * alpha) * s.T;
+    s.D = fmaf(t * alpha, s.T, s.D);
     if (MODE == kFwdDebug) {
         if (s.n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + s.n] = (int32_t)id;
         // sort error (Sec. 3.3): consecutive blends out of order add their
@@ -997,10 +997,10 @@ __global__ __launch_bounds__(256) void k_render_global(RenderArgs a) {
                 break;
             }
             const float4 cd = s_cd[k];
-            C0 = C0 + (cd.x * alpha) * T;
-            C1 = C1 + (cd.y * alpha) * T;
-            C2 = C2 + (cd.z * alpha) * T;
-            D = D + (cd.w * alpha) * T;
+            C0 = fmaf(cd.x * alpha, T, C0);
+            C1 = fmaf(cd.y * alpha, T, C1);
+            C2 = fmaf(cd.z * alpha, T, C2);
+            D = fmaf(cd.w * alpha, T, D);
             if (DEBUG && n < a.max_k) a.blend_ids[(size_t)pix * a.max_k + n] = (int32_t)s_id[k];
             if (DEBUG && a.delta) {
                 const float t = t_opt(load_packed(a.pk, s_id[k]), dP);
