@@ -22,9 +22,10 @@
  *    undefined; size the workspace up and call again.
  *  - A Gaussian with a non-finite parameter, a non-positive scale or an
  *    opacity below 1/255 is culled; it is not an error.
- *  - Floating point is IEEE binary32 throughout: no contraction into fused
- *    multiply-adds, correctly rounded division and square root, and one
- *    project-written exp (Cody-Waite reduction + degree-7 polynomial).
+ *  - Floating point is IEEE binary32 throughout: correctly rounded division
+ *    and square root, fused multiply-adds only where written out (t_opt's dot
+ *    products, the compositing sums, exp), and one project-written exp
+ *    (Cody-Waite reduction + degree-7 polynomial).
  */
 #ifndef GSR_H
 #define GSR_H
@@ -125,7 +126,8 @@ typedef struct gsr_camera {
  *   mid       mid capacity, 4 m + 4 with m >= 1 (8)
  *   mid_batch mid sub-batch (4)
  *   head      per-pixel head capacity K (HIER) or window size (WINDOW),
- *             one of 1, 2, 3, 4, 6, 8, 12, 16, 20, 24 (4)
+ *             one of 1, 2, 3, 4, 6, 8, 12, 16, 20, 24 (4); from 12 on, a
+ *             tile's list is walked up to its first 2^27 entries
  * lb_threshold only changes speed (tiles above which preprocessing and
  * duplication share a Gaussian across the wavefront; 64; Gaussians of at most
  * min(lb_threshold, 64) tiles share their tiles with the other lanes, those
@@ -139,9 +141,8 @@ typedef struct gsr_config {
     float bg[3];
     uint32_t flags;      /* GSR_ABLATE_* bits (GSR_MODE_HIER only), GSR_TILE_CENTRE_DEPTH
                             (GSR_MODE_GLOBAL only), else 0 */
-    int32_t sort_prefix; /* speed only: entries per tile sorted up front (1..4096;
-                            0 = 4096 for GSR_MODE_GLOBAL and GSR_MODE_WINDOW,
-                            else 1024); see gsr_render */
+    int32_t sort_prefix; /* speed only: entries per tile sorted up front (1..16384;
+                            0 = gsr_default_prefix for the image); see gsr_render */
 } gsr_config;
 
 /* Byte offsets of the regions of a workspace, for inspection and debugging.
@@ -293,6 +294,15 @@ int gsr_sort_passes(int32_t W, int32_t H);
  * tile bits above the low 5, which duplication already buckets by (0 for at
  * most 32 tiles). */
 int gsr_group_passes(int32_t W, int32_t H);
+
+/* The entries per tile that gsr_render sorts up front when
+ * gsr_config.sort_prefix is 0, for a W x H image in `mode` (speed only; the
+ * blend order never depends on it): a power of two near 2^23 / tiles (2^25 /
+ * tiles for GSR_MODE_GLOBAL and GSR_MODE_WINDOW), at least 1024 (4096) and at
+ * most 8192, and the minimum below 512 tiles -- 1024 at 1920x1080, 2048 at
+ * 1280x720, 8192 at 512x512, 1024 at 256x256.  The batch API's default is
+ * the large-frame one (1024; 4096).  GSR_EINVAL for bad arguments. */
+int gsr_default_prefix(int32_t W, int32_t H, int32_t mode);
 
 /* ---------------------------------------------------------------------------
  * Batched rendering: many views (cameras of any resolution) of several scenes

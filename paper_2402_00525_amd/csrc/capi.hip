@@ -241,12 +241,29 @@ __global__ void k_write_words(uint32_t* dst, uint4 v) {
     }
 }
 
-// Entries per tile sorted up front.  The 3DGS lists (global order, resort
-// window) keep every rectangle tile and reach deeper before their pixels
-// finish, so their default prefix is longer.
-int prefix_len(const gsr_config* cfg) {
+// Default entries per tile sorted up front for an image of `tiles` tiles:
+// about 2^23 entries over the frame (2^25 for the 3DGS lists of the global
+// order and the resort window, which keep every rectangle tile and reach
+// deeper before their pixels finish), a power of two from 1024 (4096) up to
+// 8192.  Views with fewer tiles have longer lists whose pixels reach deeper,
+// and a longer prefix spares their tiles the whole-list fallback and the
+// second render (1M-Gaussian scene, ms per frame at M = 1024 / 2048 / 8192:
+// 1280x720 2.51 / 1.70 / -, 512x512 - / 3.73 / 2.40).  Below 512 tiles a
+// dense scene's pixels reach deeper than any prefix sorted in LDS, the
+// fallback cannot be avoided, and the shortest first pass is the fastest
+// (256x256: 7.28 ms at 1024, 8.98 at 16384).
+int default_prefix(int tiles, int mode) {
+    const bool global = mode == GSR_MODE_GLOBAL || mode == GSR_MODE_WINDOW;
+    int m = global ? 4096 : 1024;
+    if (tiles < 512) return m;
+    const int64_t budget = global ? ((int64_t)1 << 25) : ((int64_t)1 << 23);
+    while (2 * m <= 8192 && (int64_t)(2 * m) * tiles <= budget) m *= 2;
+    return m;
+}
+
+int prefix_len(const gsr_config* cfg, int tiles) {
     if (cfg->sort_prefix != 0) return cfg->sort_prefix;
-    return (cfg->mode == GSR_MODE_GLOBAL || cfg->mode == GSR_MODE_WINDOW) ? 4096 : 1024;
+    return default_prefix(tiles, cfg->mode);
 }
 
 // Sort stage of a frame (or a batch): group by tile, tile ranges and each
@@ -320,7 +337,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
                      : cfg->mode == GSR_MODE_FULL ? GSR_MODE_HIER
                                                   : cfg->mode;
     const SortPlan sp = sort_plan(tiles, mode);
-    const uint32_t M = (uint32_t)prefix_len(cfg);
+    const uint32_t M = (uint32_t)prefix_len(cfg, tiles);
     gsr::SceneArgs sc{scene->n, scene->sh_degree, scene->means, scene->scales, scene->rots, scene->opacities, scene->sh};
 
     hipError_t e;
@@ -655,7 +672,8 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
                                        (uint32_t)b->rec_base[v], &g)) != hipSuccess)
             return fail_hip(e, "duplicate");
     }
-    if ((e = sort_stage(fb, tiles, GSR_MODE_HIER, (uint32_t)prefix_len(&b->cfg), s, nullptr)) != hipSuccess)
+    // a batch holds many views: its default prefix is that of a large frame
+    if ((e = sort_stage(fb, tiles, GSR_MODE_HIER, (uint32_t)prefix_len(&b->cfg, 1 << 30), s, nullptr)) != hipSuccess)
         return fail_hip(e, "sort");
     const uint32_t* order = nullptr;
     if (b->sched.cost_order) {
@@ -707,7 +725,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
 std::string batch_key(const gsr_batch* b) {
     std::ostringstream k;
     k << "gfx950-" << b->cu_count << "cu-views" << b->views.size() << "-records" << b->R << "-tiles" << b->tiles
-      << "-head" << b->cfg.head << "-prefix" << prefix_len(&b->cfg);
+      << "-head" << b->cfg.head << "-prefix" << prefix_len(&b->cfg, 1 << 30);
     return k.str();
 }
 
@@ -959,7 +977,7 @@ int gsr_check_config(const gsr_config* c) {
     if ((c->flags & GSR_TILE_CENTRE_DEPTH) != 0 && c->mode != GSR_MODE_GLOBAL)
         return fail(GSR_EINVAL, "GSR_TILE_CENTRE_DEPTH applies to GSR_MODE_GLOBAL");
     if (c->lb_threshold < 0) return fail(GSR_EINVAL, "lb_threshold must be >= 0");
-    if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..4096");
+    if (c->sort_prefix < 0 || c->sort_prefix > gsr::kMaxPrefix) return fail(GSR_EINVAL, "sort_prefix must be 0..16384");
     if (c->mode == GSR_MODE_HIER) {
         if (c->tail < 64 || (c->tail - 32) % 32 != 0) return fail(GSR_EINVAL, "tail must be 32n+32, n>=1");
         if (c->mid < 8 || (c->mid - 4) % 4 != 0) return fail(GSR_EINVAL, "mid must be 4m+4, m>=1");
@@ -1011,6 +1029,13 @@ int gsr_render_backward(const gsr_scene* scene, const gsr_camera* cam, const gsr
 int gsr_sort_passes(int32_t W, int32_t H) {
     if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
     return sort_plan(tiles_of(W, H), GSR_MODE_GLOBAL).tile_passes;
+}
+
+int gsr_default_prefix(int32_t W, int32_t H, int32_t mode) {
+    if (W <= 0 || H <= 0) return fail(GSR_EINVAL, "bad image size");
+    if (mode != GSR_MODE_GLOBAL && mode != GSR_MODE_HIER && mode != GSR_MODE_FULL && mode != GSR_MODE_WINDOW)
+        return fail(GSR_EINVAL, "unknown mode");
+    return default_prefix(tiles_of(W, H), mode);
 }
 
 int gsr_group_passes(int32_t W, int32_t H) {

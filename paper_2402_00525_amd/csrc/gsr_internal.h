@@ -102,7 +102,7 @@ hipError_t launch_sort_pairs(uint64_t* const keys[2], uint32_t* const vals[2], c
                              uint32_t* hist, uint32_t* partial, int bits, int start, int* result_buf, hipStream_t s,
                              void* const* scatter_events = nullptr, int shift0 = 0);
 // Largest supported sorted prefix per tile (LDS of k_tile_prefix).
-constexpr int kMaxPrefix = 4096;
+constexpr int kMaxPrefix = 16384;  // entries a workgroup sorts in LDS (128 KiB of keys)
 // Per tile of the tile-grouped keys[0, *n_ptr): its range [start, end) into
 // ranges, and its sorted prefix -- the C <= M entries of smallest (depth, id)
 // -- as ids at out[start + j], len[tile] = C (C = all entries when the tile

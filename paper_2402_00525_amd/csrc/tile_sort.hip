@@ -441,6 +441,9 @@ hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const 
                               uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const size_t shmem = 8 * (size_t)pow2ceil(std::max<uint32_t>(M, 1u));
+    hipError_t e = hipFuncSetAttribute((const void*)k_tile_prefix, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(8 * kMaxPrefix));
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_prefix, dim3(n_tiles), dim3(kT), shmem, s, keys, vals, n_ptr, n_tiles, ranges, out, len,
                        M);
     return hipGetLastError();
@@ -452,6 +455,9 @@ hipError_t launch_tile_sort_flagged(uint64_t* keys, const uint32_t* vals, uint64
     if (n_tiles == 0) return hipSuccess;
     const uint32_t lds_cap = kMaxPrefix;
     const unsigned grid = std::min<uint32_t>(n_tiles, 2048u);
+    hipError_t e = hipFuncSetAttribute((const void*)k_tile_sort_flagged, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(8 * lds_cap));
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_sort_flagged, dim3(grid), dim3(kT), 8 * (size_t)lds_cap, s, keys, vals, scratch, ranges,
                        flag, n_tiles, out, len, counters, flist, lds_cap);
     return hipGetLastError();

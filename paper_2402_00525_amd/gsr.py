@@ -61,7 +61,7 @@ _lib = None
 EXPORTS = ("gsr_workspace_bytes", "gsr_workspace_layout", "gsr_default_config", "gsr_check_config",
            "gsr_render", "gsr_render_debug", "gsr_render_sort_error", "gsr_render_backward", "gsr_render_staged",
            "gsr_render_work", "gsr_render_noalloc",
-           "gsr_sort_passes", "gsr_group_passes",
+           "gsr_sort_passes", "gsr_group_passes", "gsr_default_prefix",
            "gsr_probe_math",
            "gsr_last_error", "gsr_version")
 
@@ -106,6 +106,8 @@ def lib():
         L.gsr_sort_passes.argtypes = [C.c_int32, C.c_int32]
         L.gsr_group_passes.restype = C.c_int
         L.gsr_group_passes.argtypes = [C.c_int32, C.c_int32]
+        L.gsr_default_prefix.restype = C.c_int
+        L.gsr_default_prefix.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.gsr_probe_math.restype = C.c_int
         L.gsr_probe_math.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.gsr_last_error.restype = C.c_char_p

@@ -27,7 +27,7 @@ def gpu_frame(scene, cam, mode=1, head=4, max_k=0, entries_hint=None, renderer=N
                ranges=ranges.cpu().numpy().view(np.uint32), consumed=r.counter(n, cam, 1), **rec)
     res["mode"] = mode
     res["flags"] = flags
-    res["sort_prefix"] = sort_prefix or (4096 if mode in (0, 3) else 1024)
+    res["sort_prefix"] = sort_prefix or gsr.lib().gsr_default_prefix(cam.W, cam.H, mode)
     res["lists"] = r.tile_lists(n, cam)
     if max_k > 0:
         res["blend_ids"] = out.blend_ids.cpu().numpy()

@@ -41,9 +41,11 @@ def test_version_and_default_config(L):
     assert (c.mode, c.batch, c.tail, c.pop, c.mid, c.mid_batch, c.head, c.lb_threshold) == (1, 32, 64, 16, 8, 4, 4, 64)
     assert c.sort_prefix == 0
     assert L.lib().gsr_check_config(C.byref(c)) == 0
-    for m in (1, 100, 4096):
+    for m in (1, 100, 4096, 16384):
         c.sort_prefix = m
         assert L.lib().gsr_check_config(C.byref(c)) == 0
+    c.sort_prefix = 16385
+    assert L.lib().gsr_check_config(C.byref(c)) == -1
     c.sort_prefix = 0
     for f in (1, 2, 4, 7):                                # ablations of the hierarchical mode
         c.flags = f
@@ -68,7 +70,7 @@ def test_version_and_default_config(L):
 @pytest.mark.parametrize("field,value,code", [
     ("tail", 48, -1), ("tail", 96, -4), ("mid", 6, -1), ("mid", 12, -4), ("head", 0, -1), ("head", 25, -4),
     ("mode", 7, -1), ("mode", -1, -1), ("flags", 8, -1), ("flags", 16, -1), ("lb_threshold", -1, -1), ("sort_prefix", -1, -1),
-    ("sort_prefix", 4097, -1)])
+    ("sort_prefix", 16385, -1)])
 def test_config_validation(L, field, value, code):
     # Sec. 3.4: tail = 32n+32, mid = 4m+4, head >= 1; only the built sizes run.
     c = L.config()
@@ -139,3 +141,18 @@ def test_sort_pass_count(L):
     assert L.lib().gsr_group_passes(7680, 4320) == 2     # 129600 tiles, 17 bits
     assert L.lib().gsr_group_passes(16, 16) == 0
     assert L.lib().gsr_group_passes(0, 16) < 0
+
+
+def test_default_prefix_by_image_size(L):
+    # about 2^23 sorted entries per frame (2^25 for the 3DGS lists), a power
+    # of two between 1024 (4096) and 8192, the minimum below 512 tiles
+    f = L.lib().gsr_default_prefix
+    assert f(1920, 1080, L.MODE_HIER) == 1024
+    assert f(1280, 720, L.MODE_HIER) == 2048
+    assert f(512, 512, L.MODE_HIER) == 8192
+    assert f(256, 256, L.MODE_HIER) == 1024
+    assert f(3840, 2160, L.MODE_HIER) == 1024
+    assert f(1920, 1080, L.MODE_GLOBAL) == 4096
+    assert f(512, 512, L.MODE_WINDOW) == 8192
+    assert f(256, 256, L.MODE_WINDOW) == 4096
+    assert f(0, 10, L.MODE_HIER) < 0 and f(10, 10, 9) < 0

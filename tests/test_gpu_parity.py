@@ -118,7 +118,7 @@ def test_two_grouping_passes_4k_bit_exact():
     np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
 
 
-@pytest.mark.parametrize("prefix", [1, 16, 100, 4096])
+@pytest.mark.parametrize("prefix", [1, 16, 100, 4096, 16384])
 def test_prefix_fallback_bit_exact(prefix):
     """Short sorted prefixes force many tiles through the fallback sort; the
     blend order and images stay those of the full sort."""
@@ -153,19 +153,21 @@ def test_prefix_fallback_3dgs_lists_bit_exact(mode, K, prefix):
     np.testing.assert_array_equal(g["count"], o.count)
 
 
-def test_prefix_fallback_long_lists():
-    """Faint Gaussians keep pixels alive past every prefix, so tiles of more
-    than 4096 entries take the fallback's radix path."""
-    sc = synth.uniform_scene(30_000, seed=3, sh_degree=0)
+@pytest.mark.parametrize("n,longest", [(30_000, 4096), (100_000, 16384)])
+def test_prefix_fallback_long_lists(n, longest):
+    """Faint Gaussians keep pixels alive past every prefix, so whole lists of
+    more than 4096 entries are sorted by the fallback: in LDS up to 16384
+    entries, by radix passes beyond."""
+    sc = synth.uniform_scene(n, seed=3, sh_degree=0)
     sc.opacities[:] = (sc.opacities * 0.02).astype(np.float32)
     cam = synth.front_camera(64, 48)
-    say("case: long fallback lists")
+    say("case: long fallback lists", n)
     o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=64)
     g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=64, sort_prefix=256)
-    assert np.diff(o.ranges, axis=1).max() > 4096
+    assert np.diff(o.ranges, axis=1).max() > longest
     assert_sorted_equal(g, o)
     flag = g["lists"]["tile_flag"]
-    assert flag.max() > 4096
+    assert flag.max() > longest
     np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
     np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
     np.testing.assert_array_equal(g["count"], o.count)
@@ -420,10 +422,12 @@ def _bench_tile_mask(cam, flag, seed, n_random=24):
     return mask
 
 
-@pytest.mark.parametrize("n,seed,view", [(3_000_000, 2, 5), (3_000_000, 2, 24), (1_000_000, 1, 0)])
-def test_benchmark_frames_on_sampled_tiles(n, seed, view):
+@pytest.mark.parametrize("n,seed,view,W,H", [(3_000_000, 2, 5, 1920, 1080), (3_000_000, 2, 24, 1920, 1080),
+                                           (1_000_000, 1, 0, 1920, 1080), (1_000_000, 1, 3, 512, 512)])
+def test_benchmark_frames_on_sampled_tiles(n, seed, view, W, H):
     """The benchmarked frames themselves (mixture scenes of 3M and 1M
-    Gaussians at 1920x1080, orbit views) in the launch configuration the
+    Gaussians at 1920x1080, orbit views; and a 512x512 view of the 1M scene,
+    whose default prefix is 8192) in the launch configuration the
     benchmark times: per-Gaussian records and tile counts of every Gaussian,
     the ranges of every tile, and on a sample of tiles (all flagged tiles,
     part of the partial bottom row, random ones) the sorted lists, per-pixel
@@ -431,8 +435,8 @@ def test_benchmark_frames_on_sampled_tiles(n, seed, view):
     those tiles."""
     from paper_2402_00525_amd import gsr
     sc = synth.mixture_scene(n, seed=seed)
-    cam = synth.orbit_camera(1920, 1080, view)
-    say("case: benchmark frame, %d Gaussians, seed %d, view %d" % (n, seed, view))
+    cam = synth.orbit_camera(W, H, view)
+    say("case: benchmark frame, %d Gaussians, seed %d, view %d, %dx%d" % (n, seed, view, W, H))
     ds = gsr.DeviceScene.from_host(sc)
     r = gsr.Renderer(entries_hint=32 * n)
     plain = r.render(ds, cam, gsr.config())                 # the benchmarked kernels
@@ -461,7 +465,7 @@ def test_benchmark_frames_on_sampled_tiles(n, seed, view):
         if flag[t]:
             assert c == re - rb
         else:
-            assert c <= min(re - rb, 1024)
+            assert c <= min(re - rb, gsr.lib().gsr_default_prefix(W, H, gsr.MODE_HIER))
         np.testing.assert_array_equal(pre[rb:rb + c], ov[rb:rb + c])
         y0, x0 = (t // tx) * 16, (t % tx) * 16
         pix[y0:y0 + 16, x0:x0 + 16] = True
