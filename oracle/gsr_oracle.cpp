@@ -242,14 +242,17 @@ template <class F> struct Cam {
         limy = F(1.3) * ((F)H / (F(2) * fy));
     }
     // Unit world-space ray direction through image point (u, v):
-    // d_c = ((u-cx)/fx, (v-cy)/fy, 1), d_w = R^T d_c, d = d_w / |d_w|.
+    // d_c = ((u-cx)/fx, (v-cy)/fy, 1), d_w = R^T d_c, d = d_w / |d_w|; each
+    // component of d_w and |d_w|^2 by fused multiply-adds, and d_w scaled by
+    // the one reciprocal 1 / |d_w|.
     void ray(F u, F v, F d[3]) const {
-        F a = (u - cx) / fx, b = (v - cy) / fy, c = F(1);
-        F w0 = (R[0] * a + R[3] * b) + R[6] * c;
-        F w1 = (R[1] * a + R[4] * b) + R[7] * c;
-        F w2 = (R[2] * a + R[5] * b) + R[8] * c;
-        F len = std::sqrt((w0 * w0 + w1 * w1) + w2 * w2);
-        d[0] = w0 / len; d[1] = w1 / len; d[2] = w2 / len;
+        F a = (u - cx) / fx, b = (v - cy) / fy;
+        F w0 = std::fma(R[3], b, std::fma(R[0], a, R[6]));
+        F w1 = std::fma(R[4], b, std::fma(R[1], a, R[7]));
+        F w2 = std::fma(R[5], b, std::fma(R[2], a, R[8]));
+        F len = std::sqrt(std::fma(w2, w2, std::fma(w1, w1, w0 * w0)));
+        F inv = F(1) / len;
+        d[0] = w0 * inv; d[1] = w1 * inv; d[2] = w2 * inv;
     }
 };
 
@@ -289,9 +292,11 @@ template <class F> inline F topt(const Rec<F>& g, const F d[3]) {
 
 // Exponent of the 2D Gaussian at point (px, py):
 // power = -1/2 (a dx^2 + c dy^2) - b dx dy, with d = mu_2 - p.
+// (fused: -1/2 q - b dx dy with q = fma(c dy, dy, (a dx) dx) in one rounding)
 template <class F> inline F power_at(const Rec<F>& g, F px, F py) {
     F dx = g.x - px, dy = g.y - py;
-    return F(-0.5) * ((g.ca * dx) * dx + (g.cc * dy) * dy) - (g.cb * dx) * dy;
+    F q = std::fma(g.cc * dy, dy, (g.ca * dx) * dx);
+    return std::fma(F(-0.5), q, -((g.cb * dx) * dy));
 }
 
 // Algorithm 1 (App. B.1): point of the axis-aligned box [x0,x1]x[y0,y1] where
@@ -311,13 +316,13 @@ template <class F> void alg1_max_point(const Rec<F>& g, F x0, F x1, F y0, F y1, 
     F tx = F(0), ty = F(0);
     if (!in_x && ly != F(0)) {
         // t_y = d_y^T C (mu - p) / d_y^T C d_y  with d_y = (0, ly)
-        ty = sclamp((g.cb * dx + g.cc * dy) / (g.cc * ly), F(0), F(1));
+        ty = sclamp(std::fma(g.cb, dx, g.cc * dy) / (g.cc * ly), F(0), F(1));
     }
     if (!in_y && lx != F(0)) {
-        tx = sclamp((g.ca * dx + g.cb * dy) / (g.ca * lx), F(0), F(1));
+        tx = sclamp(std::fma(g.ca, dx, g.cb * dy) / (g.ca * lx), F(0), F(1));
     }
-    hx = px + tx * lx;
-    hy = py + ty * ly;
+    hx = std::fma(tx, lx, px);
+    hy = std::fma(ty, ly, py);
 }
 
 // Culling test shared by every level: the Gaussian is kept for a region iff

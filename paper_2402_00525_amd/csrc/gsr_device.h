@@ -77,15 +77,18 @@ __device__ __forceinline__ float depth_from_bits(uint32_t b) {
     return __uint_as_float((b & 0x80000000u) ? (b & 0x7fffffffu) : ~b);
 }
 
-// Unit world-space direction of the ray through image point (u, v).
+// Unit world-space direction of the ray through image point (u, v): the
+// camera-frame direction ((u - cx) / fx, (v - cy) / fy, 1) rotated to the
+// world by fused multiply-adds and scaled by the one reciprocal of its norm.
 __device__ __forceinline__ float3 cam_ray(const DevCam& c, float u, float v) {
     const float a = (u - c.cx) / c.fx;
     const float b = (v - c.cy) / c.fy;
-    const float w0 = (c.R[0] * a + c.R[3] * b) + c.R[6];
-    const float w1 = (c.R[1] * a + c.R[4] * b) + c.R[7];
-    const float w2 = (c.R[2] * a + c.R[5] * b) + c.R[8];
-    const float len = sqrtf((w0 * w0 + w1 * w1) + w2 * w2);
-    return make_float3(w0 / len, w1 / len, w2 / len);
+    const float w0 = fmaf(c.R[3], b, fmaf(c.R[0], a, c.R[6]));
+    const float w1 = fmaf(c.R[4], b, fmaf(c.R[1], a, c.R[7]));
+    const float w2 = fmaf(c.R[5], b, fmaf(c.R[2], a, c.R[8]));
+    const float len = sqrtf(fmaf(w2, w2, fmaf(w1, w1, w0 * w0)));
+    const float inv = 1.0f / len;
+    return make_float3(w0 * inv, w1 * inv, w2 * inv);
 }
 
 // The per-Gaussian data the render levels use: 2D mean, conic, opacity,
@@ -141,10 +144,14 @@ __device__ __forceinline__ float t_opt(const Splat& g, float3 d) {
     return (t != t) ? __int_as_float(0x7f800000) : t;
 }
 
-// Exponent of G_2 at (px, py): -1/2 (a dx^2 + c dy^2) - b dx dy with d = mu_2 - p.
+// Exponent of G_2 at offset d = mu_2 - p: -1/2 (a dx^2 + c dy^2) - b dx dy,
+// as -1/2 q - b dx dy with q = fma(c dy, dy, (a dx) dx), fused.
+__device__ __forceinline__ float power_at_offset(float ca, float cb, float cc, float dx, float dy) {
+    const float q = fmaf(cc * dy, dy, (ca * dx) * dx);
+    return fmaf(-0.5f, q, -((cb * dx) * dy));
+}
 __device__ __forceinline__ float splat_power(const Splat& g, float px, float py) {
-    const float dx = g.x - px, dy = g.y - py;
-    return -0.5f * ((g.ca * dx) * dx + (g.cc * dy) * dy) - (g.cb * dx) * dy;
+    return power_at_offset(g.ca, g.cb, g.cc, g.x - px, g.y - py);
 }
 
 // Algorithm 1 (App. B.1): the point of box [x0,x1] x [y0,y1] where the 2D
@@ -164,13 +171,13 @@ __device__ __forceinline__ float2 box_max_point(const Splat& g, float x0, float 
     const float dx = mx - px, dy = my - py;
     float tx = 0.0f, ty = 0.0f;
     if (FAST) {
-        if (!in_x && ly != 0.0f) ty = sel_clamp(__fdividef(g.cb * dx + g.cc * dy, g.cc * ly), 0.0f, 1.0f);
-        if (!in_y && lx != 0.0f) tx = sel_clamp(__fdividef(g.ca * dx + g.cb * dy, g.ca * lx), 0.0f, 1.0f);
+        if (!in_x && ly != 0.0f) ty = sel_clamp(__fdividef(fmaf(g.cb, dx, g.cc * dy), g.cc * ly), 0.0f, 1.0f);
+        if (!in_y && lx != 0.0f) tx = sel_clamp(__fdividef(fmaf(g.ca, dx, g.cb * dy), g.ca * lx), 0.0f, 1.0f);
     } else {
-        if (!in_x && ly != 0.0f) ty = sel_clamp((g.cb * dx + g.cc * dy) / (g.cc * ly), 0.0f, 1.0f);
-        if (!in_y && lx != 0.0f) tx = sel_clamp((g.ca * dx + g.cb * dy) / (g.ca * lx), 0.0f, 1.0f);
+        if (!in_x && ly != 0.0f) ty = sel_clamp(fmaf(g.cb, dx, g.cc * dy) / (g.cc * ly), 0.0f, 1.0f);
+        if (!in_y && lx != 0.0f) tx = sel_clamp(fmaf(g.ca, dx, g.cb * dy) / (g.ca * lx), 0.0f, 1.0f);
     }
-    return make_float2(px + tx * lx, py + ty * ly);
+    return make_float2(fmaf(tx, lx, px), fmaf(ty, ly, py));
 }
 
 // opacity * exp(p) >= eps_O, decided as that comparison.  When the exponent

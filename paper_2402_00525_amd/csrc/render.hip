@@ -264,7 +264,7 @@ __device__ __forceinline__ void blend_one(const RenderArgs& a, PixelState<K, MOD
         const float2 m = make_float2(p0.x, p0.y);
         const float4 c = make_float4(p0.z, p0.w, p1.x, p1.y);
         const float dx = m.x - s.px, dy = m.y - s.py;
-        const float pw = -0.5f * ((c.x * dx) * dx + (c.z * dy) * dy) - (c.y * dx) * dy;
+        const float pw = power_at_offset(c.x, c.y, c.z, dx, dy);
         const float G = exp_cw(pw);
         const bool live = c.w * G < kAlphaMax;  // alpha not clamped: it depends on the Gaussian
         const float gp = ga * alpha;            // d alpha / d power = o G

@@ -5,6 +5,8 @@ Coordinates whose perturbation changes a discrete decision (culling, the
 blend sequence of any pixel, a clamp, the sign of the L1 residual) are
 skipped: the image is only piecewise smooth in the parameters.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -105,15 +107,26 @@ def test_backward_single_gaussian_closed_form():
     np.testing.assert_allclose(g["sh"][0, 0, 1], alpha * 0.5 / np.sqrt(np.pi), rtol=1e-10)
 
 
+def _fma32(a, b, c):
+    """a * b + c rounded once to float32 (round to nearest, ties to even),
+    from the exact rational value."""
+    exact = Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c))
+    r = np.float32(float(exact))
+    cands = (r, np.nextafter(r, np.float32(np.inf)), np.nextafter(r, np.float32(-np.inf)))
+    return min(cands, key=lambda v: (abs(Fraction(float(v)) - exact), int(np.array(v).view(np.uint32)) & 1))
+
+
 def _alpha32(fr, i, x, y):
     """alpha of Gaussian i at pixel (x, y) in float32 arithmetic from the
     frame's float32 records (Eq. volume_desc: opacity times the 2D Gaussian,
-    clamped to 0.99)."""
+    clamped to 0.99); the exponent -1/2 q - b dx dy with
+    q = c dy dy + (a dx) dx, each of the two sums rounded once (fused)."""
     f = np.float32
     mx, my = fr.xy[i]
     ca, cb, cc, op = fr.conic_o[i]
     dx, dy = f(mx) - f(x), f(my) - f(y)
-    p = f(-0.5) * ((ca * dx) * dx + (cc * dy) * dy) - (cb * dx) * dy
+    q = _fma32(cc * dy, dy, (ca * dx) * dx)
+    p = _fma32(f(-0.5), q, -((cb * dx) * dy))
     a = f(op) * f(oracle.exp32(f(p)))
     return min(a, f(0.99))
 
