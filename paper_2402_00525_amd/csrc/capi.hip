@@ -66,9 +66,13 @@ int64_t dup_workgroups(int64_t n) { return (n + 255) / 256; }
 // workgroup), so that workgroups are numbered across the batch.
 int64_t align_records(int64_t n) { return (n + 255) & ~(int64_t)255; }
 
+// Workspace regions not published in gsr_layout.
+struct InnerLayout {
+    int64_t scan_partial, hist, keys1, vals1, chunks;
+};
+
 // Layout for a given entry capacity.
-void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_partial, int64_t* hist,
-                int64_t* keys1, int64_t* vals1) {
+void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, InnerLayout* in) {
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
         const int64_t o = off;
@@ -93,12 +97,13 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
                                           gsr::scan_partial_len((size_t)(gsr::kDupBins * dup_workgroups(n))),
                                           gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
                        2;
-    *scan_partial = take(4 * sp);
-    *hist = take(4 * gsr::kSortMaxBins * nb);
+    in->scan_partial = take(4 * sp);
+    in->hist = take(4 * gsr::kSortMaxBins * nb);
+    in->chunks = take(8 * (int64_t)gsr::flagged_chunk_capacity((size_t)cap, (size_t)tiles));
     L->keys = take(8 * cap);
-    *keys1 = take(8 * cap);
+    in->keys1 = take(8 * cap);
     L->values = take(4 * cap);
-    *vals1 = take(4 * cap);
+    in->vals1 = take(4 * cap);
     L->pre_vals = take(4 * cap);
     L->entry_capacity = cap;
     L->total_bytes = off;
@@ -106,22 +111,21 @@ void layout_for(int64_t n, int tiles, int64_t cap, gsr_layout* L, int64_t* scan_
 
 int tiles_of(int W, int H) { return ((W + 15) / 16) * ((H + 15) / 16); }
 
-int compute_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* L, int64_t* sp, int64_t* hist,
-                   int64_t* k1, int64_t* v1) {
+int compute_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* L, InnerLayout* in) {
     if (n < 0 || W <= 0 || H <= 0 || W > 32768 || H > 32768) return GSR_EINVAL;
     const int tiles = tiles_of(W, H);
     // Largest capacity whose layout fits (the layout size grows with it).
     int64_t lo = 0, hi = ((int64_t)1 << 31) - 1;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
-        layout_for(n, tiles, mid, L, sp, hist, k1, v1);
+        layout_for(n, tiles, mid, L, in);
         if (L->total_bytes <= (int64_t)ws_bytes)
             lo = mid;
         else
             hi = mid - 1;
     }
     if (lo <= 0) return GSR_ECAPACITY;
-    layout_for(n, tiles, lo, L, sp, hist, k1, v1);
+    layout_for(n, tiles, lo, L, in);
     return GSR_OK;
 }
 
@@ -163,7 +167,7 @@ int check_camera(const gsr_camera* c) {
     return GSR_OK;
 }
 
-gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t hist, int64_t k1, int64_t v1) {
+gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, const InnerLayout& in) {
     gsr::FrameBufs b;
     b.pk = (float4*)(base + L.splat);
     b.col = (float4*)(base + L.colour);
@@ -173,12 +177,12 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.kmask = (uint64_t*)(base + L.kmask);
     b.offsets = (uint32_t*)(base + L.offsets);
     b.dhist = (uint32_t*)(base + L.dup_hist);
-    b.scan_partial = (uint32_t*)(base + sp);
-    b.hist = (uint32_t*)(base + hist);
+    b.scan_partial = (uint32_t*)(base + in.scan_partial);
+    b.hist = (uint32_t*)(base + in.hist);
     b.keys[0] = (uint64_t*)(base + L.keys);
-    b.keys[1] = (uint64_t*)(base + k1);
+    b.keys[1] = (uint64_t*)(base + in.keys1);
     b.vals[0] = (uint32_t*)(base + L.values);
-    b.vals[1] = (uint32_t*)(base + v1);
+    b.vals[1] = (uint32_t*)(base + in.vals1);
     b.ranges = (uint32_t*)(base + L.ranges);
     b.counters = (uint32_t*)(base + L.counters);
     b.capacity = (uint32_t)L.entry_capacity;
@@ -186,6 +190,7 @@ gsr::FrameBufs frame_bufs(char* base, const gsr_layout& L, int64_t sp, int64_t h
     b.pre_len = (uint32_t*)(base + L.pre_len);
     b.tile_flag = (uint32_t*)(base + L.tile_flag);
     b.flist = nullptr;
+    b.chunks = (uint2*)(base + in.chunks);
     return b;
 }
 
@@ -296,7 +301,7 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
 // render flagged (counters[5] = their entries, counters[6] = their number).
 hipError_t fallback_sort(const gsr::FrameBufs& b, int tiles, hipStream_t s) {
     return gsr::launch_tile_sort_flagged(b.keys[0], b.vals[0], b.keys[1], b.ranges, b.tile_flag, (uint32_t)tiles,
-                                         b.pre_vals, b.pre_len, b.counters, b.flist, s);
+                                         b.pre_vals, b.pre_len, b.counters, b.flist, b.chunks, s);
 }
 
 void set_prefix_lists(gsr::RenderArgs& ra, const gsr::FrameBufs& b, int list_mode) {
@@ -321,12 +326,12 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
     if ((cfg->mode == GSR_MODE_HIER || cfg->mode == GSR_MODE_WINDOW) && !gsr::hier_head_supported(cfg->head))
         return fail(GSR_EUNSUPPORTED, "head size not built (1,2,3,4,6,8,12,16,20,24)");
     gsr_layout L;
-    int64_t spo, hist, k1, v1;
-    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &spo, &hist, &k1, &v1);
+    InnerLayout in;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &in);
     if (rc) return fail(rc, "workspace too small");
     char* base = (char*)ws;
     if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
-    const gsr::FrameBufs b = frame_bufs(base, L, spo, hist, k1, v1);
+    const gsr::FrameBufs b = frame_bufs(base, L, in);
 
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
@@ -453,12 +458,12 @@ int backward_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_confi
     if (!ws || !dL || !rgb || !T_final) return fail(GSR_EINVAL, "input is NULL");
     if (scene->n > 0 && (!dmeans || !dscales || !drots || !dopac || !dsh)) return fail(GSR_EINVAL, "gradient is NULL");
     gsr_layout L;
-    int64_t spo, hist, k1, v1;
-    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &spo, &hist, &k1, &v1);
+    InnerLayout in;
+    rc = compute_layout(scene->n, cam->W, cam->H, ws_bytes, &L, &in);
     if (rc) return fail(rc, "workspace too small");
     char* base = (char*)ws;
     if (((uintptr_t)base & 255) != 0) return fail(GSR_EINVAL, "workspace must be 256-byte aligned");
-    const gsr::FrameBufs b = frame_bufs(base, L, spo, hist, k1, v1);
+    const gsr::FrameBufs b = frame_bufs(base, L, in);
     float* g2 = (float*)(base + L.grad2d);
     hipStream_t s = (hipStream_t)stream;
     const gsr::DevCam dc = make_cam(cam);
@@ -504,7 +509,7 @@ constexpr int kBatchCounters = kBatchQueue0 + 2 * gsr::kBatchQueues;
 
 struct BatchLayout {
     int64_t views, pk, col, zd, rect, touched, kmask, offsets, dhist, ranges, counters;
-    int64_t pre_vals, pre_len, tile_flag, flist;
+    int64_t pre_vals, pre_len, tile_flag, flist, chunks;
     int64_t keys[2], vals[2], hist, partial;
     int64_t tkeys[2], tvals[2], thist, tpartial;
     int64_t cap, total;
@@ -544,6 +549,7 @@ void batch_layout_for(int64_t R, int64_t tiles, int64_t n_views, int64_t cap, Ba
                                               gsr::scan_partial_len((size_t)nb * gsr::kSortMaxBins)}) +
                            2));
     L->hist = take(4 * gsr::kSortMaxBins * nb);
+    L->chunks = take(8 * (int64_t)gsr::flagged_chunk_capacity((size_t)cap, (size_t)tiles));
     L->keys[0] = take(8 * cap);
     L->keys[1] = take(8 * cap);
     L->vals[0] = take(4 * cap);
@@ -629,6 +635,7 @@ int batch_render_impl(gsr_batch* b, int32_t* status_dev, hipStream_t s) {
     fb.pre_len = (uint32_t*)(base + L.pre_len);
     fb.tile_flag = (uint32_t*)(base + L.tile_flag);
     fb.flist = (uint32_t*)(base + L.flist);
+    fb.chunks = (uint2*)(base + L.chunks);
     const int tiles = (int)b->tiles;
     const SortPlan sp = sort_plan(tiles, GSR_MODE_HIER);
     const int lb = b->sched.lb_threshold;
@@ -938,15 +945,15 @@ void gsr_batch_destroy(gsr_batch* b) { delete b; }
 size_t gsr_workspace_bytes(int64_t n, int32_t W, int32_t H, int64_t entries_max) {
     if (n < 0 || W <= 0 || H <= 0 || entries_max < 1 || entries_max > ((int64_t)1 << 31) - 1) return 0;
     gsr_layout L;
-    int64_t sp, hist, k1, v1;
-    layout_for(n, tiles_of(W, H), entries_max, &L, &sp, &hist, &k1, &v1);
+    InnerLayout in;
+    layout_for(n, tiles_of(W, H), entries_max, &L, &in);
     return (size_t)L.total_bytes;
 }
 
 int gsr_workspace_layout(int64_t n, int32_t W, int32_t H, size_t ws_bytes, gsr_layout* out) {
     if (!out) return fail(GSR_EINVAL, "layout is NULL");
-    int64_t sp, hist, k1, v1;
-    const int rc = compute_layout(n, W, H, ws_bytes, out, &sp, &hist, &k1, &v1);
+    InnerLayout in;
+    const int rc = compute_layout(n, W, H, ws_bytes, out, &in);
     if (rc) return fail(rc, "workspace too small or bad size");
     return GSR_OK;
 }
@@ -1064,8 +1071,8 @@ int gsr_render_noalloc(const gsr_scene* scene, const gsr_camera* cam, const gsr_
     if (!scene || !cam) return fail(GSR_EINVAL, "scene or camera is NULL");
     {
         gsr_layout L;
-        int64_t sp, hist, k1, v1;
-        if (compute_layout(scene->n, cam->W, cam->H, kNoAllocBytes, &L, &sp, &hist, &k1, &v1) != GSR_OK)
+        InnerLayout in;
+        if (compute_layout(scene->n, cam->W, cam->H, kNoAllocBytes, &L, &in) != GSR_OK)
             return fail(GSR_ECAPACITY, "scene and image do not fit the fixed workspace of GSR_NOALLOC_BYTES");
     }
     void* ws = nullptr;

@@ -31,12 +31,14 @@ struct FrameBufs {
     uint32_t* hist;           // radix histograms, kSortMaxBins x sort blocks
     uint32_t* ranges;         // [tiles][2]
     uint32_t* counters;       // [0] entries, [1] consumed, [3] entries needed, [5] / [6] fallback entries /
-                              // tiles, [8..11] the frame's fingerprint (checked by the backward)
+                              // tiles, [7] fallback chunks, [8..11] the frame's fingerprint (checked by
+                              // the backward)
     uint32_t capacity;
     uint32_t* pre_vals;       // [capacity] sorted prefix ids at each tile's range begin
     uint32_t* pre_len;        // [tiles]
     uint32_t* tile_flag;      // [tiles] entry count of a tile rendered from the fallback, else 0
     uint32_t* flist;          // [tiles] flagged tiles (batch)
+    uint2* chunks;            // chunk list of the fallback sort
 };
 
 struct SceneArgs {
@@ -111,12 +113,16 @@ hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const 
                               uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s);
 // Whole sorted list of every flagged tile (flag[t] = its entry count) at
 // out[range begin ..], len[t] = count; `scratch` is a second key buffer of the
-// same capacity and the grouped keys are overwritten.  counters[5] += flagged
-// entries, counters[6] += flagged tiles; flagged tiles appended to flist if
-// given.
+// same capacity and the grouped keys are overwritten.  The lists are split
+// into chunks of consecutive depth bins, listed in `chunks` (room for
+// flagged_chunk_capacity(capacity, n_tiles) entries, counted in counters[7],
+// which must be 0 on entry) and sorted by many workgroups.  counters[5] +=
+// flagged entries, counters[6] += flagged tiles; flagged tiles appended to
+// flist if given.
 hipError_t launch_tile_sort_flagged(uint64_t* keys, const uint32_t* vals, uint64_t* scratch, const uint32_t* ranges,
                                     const uint32_t* flag, uint32_t n_tiles, uint32_t* out, uint32_t* len,
-                                    uint32_t* counters, uint32_t* flist, hipStream_t s);
+                                    uint32_t* counters, uint32_t* flist, uint2* chunks, hipStream_t s);
+size_t flagged_chunk_capacity(size_t entries, size_t tiles);
 // Cost keys for ordering tiles: key[t] = ~(list length of tile t), val[t] = t.
 hipError_t launch_tile_cost_keys(const uint32_t* ranges, uint32_t n_tiles, uint64_t* keys, uint32_t* vals,
                                  hipStream_t s);

@@ -70,43 +70,6 @@ __device__ __forceinline__ uint32_t wg_scan_excl(uint32_t v, uint32_t* lw, uint3
     return before + x - v;
 }
 
-// Minimum and maximum depth bits of keys[b, e), returned to every thread.
-__device__ void depth_range(const uint64_t* __restrict__ keys, uint32_t b, uint32_t e, uint32_t* red, uint32_t& lo,
-                            uint32_t& hi) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t mn = 0xffffffffu, mx = 0u;
-    uint32_t i = b + threadIdx.x;
-    for (; i + 3 * kT < e; i += 4 * kT) {
-        const uint32_t d0 = depth_of(keys[i]), d1 = depth_of(keys[i + kT]);
-        const uint32_t d2 = depth_of(keys[i + 2 * kT]), d3 = depth_of(keys[i + 3 * kT]);
-        mn = umin(mn, umin(umin(d0, d1), umin(d2, d3)));
-        mx = umax(mx, umax(umax(d0, d1), umax(d2, d3)));
-    }
-    for (; i < e; i += kT) {
-        const uint32_t d = depth_of(keys[i]);
-        mn = umin(mn, d);
-        mx = umax(mx, d);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = umin(mn, (uint32_t)__shfl_xor((int)mn, o));
-        mx = umax(mx, (uint32_t)__shfl_xor((int)mx, o));
-    }
-    if (lane == 0) {
-        red[wave] = mn;
-        red[kTW + wave] = mx;
-    }
-    __syncthreads();
-    lo = red[0];
-    hi = red[kTW];
-#pragma unroll
-    for (int w = 1; w < kTW; ++w) {
-        lo = umin(lo, red[w]);
-        hi = umax(hi, red[kTW + w]);
-    }
-    __syncthreads();
-}
-
 // Ascending bitonic sort of sk[0, C) in LDS (padded with ~0 to a power of two
 // that must fit the array).
 __device__ void lds_bitonic(uint64_t* sk, uint32_t C) {
@@ -277,28 +240,218 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     if (tid == 0) len[tile] = C;
 }
 
-// One stable LSD pass of a tile's list over 8 bits, from `shift`, of either
-// (id - lo) (by_id) or (depth - lo): src/dst hold (depth << 32 | id) except in
-// the first pass, which reads the grouped (tile << 32 | depth) keys and their
-// ids.  Keys are taken in chunks of 256 in list order; inside a chunk a key's
-// place among equal digits is its wavefront's ballot rank plus the counts of
-// the wavefronts before it.
-__device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t* __restrict__ src_ids, bool first,
-                                uint64_t* __restrict__ dst, uint32_t n, bool by_id, uint32_t lo, int shift,
-                                uint32_t* hst, uint32_t* base, uint32_t (*wc)[256], uint32_t* lw) {
+// Minimum and maximum of the high and of the low words of the (depth << 32 |
+// id) keys a[0, n), returned to every thread.
+__device__ void word_ranges(const uint64_t* __restrict__ a, uint32_t n, uint32_t* red, uint32_t& dlo, uint32_t& dhi,
+                            uint32_t& ilo, uint32_t& ihi) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t mn[2] = {0xffffffffu, 0xffffffffu}, mx[2] = {0u, 0u};
+    for (uint32_t i = threadIdx.x; i < n; i += kT) {
+        const uint64_t k = a[i];
+        const uint32_t w[2] = {(uint32_t)(k >> 32), (uint32_t)k};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            mn[h] = umin(mn[h], w[h]);
+            mx[h] = umax(mx[h], w[h]);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[h] = umin(mn[h], (uint32_t)__shfl_xor((int)mn[h], o));
+            mx[h] = umax(mx[h], (uint32_t)__shfl_xor((int)mx[h], o));
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        red[wave] = mn[0];
+        red[kTW + wave] = mx[0];
+        red[2 * kTW + wave] = mn[1];
+        red[3 * kTW + wave] = mx[1];
+    }
+    __syncthreads();
+    dlo = red[0];
+    dhi = red[kTW];
+    ilo = red[2 * kTW];
+    ihi = red[3 * kTW];
+#pragma unroll
+    for (int w = 1; w < kTW; ++w) {
+        dlo = umin(dlo, red[w]);
+        dhi = umax(dhi, red[kTW + w]);
+        ilo = umin(ilo, red[2 * kTW + w]);
+        ihi = umax(ihi, red[3 * kTW + w]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int bits_of(uint32_t span) {
+    int b = 0;
+    while (b < 32 && (span >> b) != 0u) ++b;
+    return b;
+}
+
+// Exclusive maximum over the 256 threads of a workgroup (-1 before thread 0).
+__device__ __forceinline__ int wg_max_excl(int v, uint32_t* lw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x = max(x, y);
+    }
+    if (lane == 63) lw[wave] = (uint32_t)x;
+    __syncthreads();
+    int before = -1;
+#pragma unroll
+    for (int w = 0; w < kTW; ++w)
+        if (w < wave) before = max(before, (int)lw[w]);
+    const int up = __shfl_up(x, 1);
+    __syncthreads();
+    return lane > 0 ? max(before, up) : before;
+}
+
+// The whole-list fallback runs in two launches so that the sorting is spread
+// over many workgroups:
+//
+//   k_flag_chunks  one workgroup per flagged tile (flag = its entry count):
+//                  splits the tile's list into chunks of consecutive depth
+//                  bins and writes every entry, as a (depth << 32 | id) key,
+//                  into its chunk's range of the scratch buffer, at the
+//                  entry's place in the tile's range; appends each chunk
+//                  (first position, size) to the chunk list;
+//   k_sort_chunks  grid-stride over the chunk list: sorts each chunk by
+//                  (depth, id) and writes its ids to out at the same places.
+//
+// Bins are monotone in depth, so the chunks in bin order, each sorted, are
+// the tile's list sorted.  A chunk gathers the bins whose first entry lies
+// in the same block of kChunkHalf positions of the tile's bin order, so it
+// holds fewer than kChunkHalf entries plus its last bin; one beyond
+// kChunkEntries (a bin that large) is sorted by radix passes instead of in
+// LDS.  A tile has at most n / kChunkHalf + 1 chunks.
+constexpr uint32_t kChunkEntries = 8192;
+constexpr uint32_t kChunkHalf = kChunkEntries / 2;
+
+__global__ __launch_bounds__(kT) void k_flag_chunks(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                    uint64_t* __restrict__ scratch, const uint32_t* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ flag, uint32_t n_tiles,
+                                                    uint32_t* __restrict__ len, uint32_t* __restrict__ counters,
+                                                    uint32_t* __restrict__ flist, uint2* __restrict__ chunks) {
+    __shared__ uint32_t hist[kPrefixBins];   // bin counts, then chunk fill counts
+    __shared__ uint32_t cstart[kPrefixBins];  // first position of each chunk in the tile
+    __shared__ uint16_t cmap[kPrefixBins];    // chunk of each bin
+    __shared__ uint32_t lw[kTW], s_base, s_nc;
+    const int tid = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const uint32_t n = flag[t];
+        if (n == 0u) continue;
+        const uint32_t rb = ranges[2 * (size_t)t];
+        if (tid == 0) {
+            atomicAdd(counters + 5, n);
+            const uint32_t slot = atomicAdd(counters + 6, 1u);
+            if (flist) flist[slot] = t;
+            len[t] = n;
+        }
+        if (n <= kChunkEntries) {
+            for (uint32_t i = tid; i < n; i += kT)
+                scratch[rb + i] = ((uint64_t)depth_of(keys[rb + i]) << 32) | vals[rb + i];
+            if (tid == 0) chunks[atomicAdd(counters + 7, 1u)] = make_uint2(rb, n);
+            continue;
+        }
+        for (int k = tid; k < kPrefixBins; k += kT) hist[k] = 0;
+        __syncthreads();
+        for (uint32_t i = rb + tid; i < rb + n; i += kT) atomicAdd(&hist[depth_bin(depth_of(keys[i]))], 1u);
+        __syncthreads();
+        // Thread tid owns bins [16 tid, 16 tid + 16).  A non-empty bin b
+        // belongs to block pre(b) / kChunkHalf (pre = entries of earlier
+        // bins) and starts a chunk when the last non-empty bin before it
+        // belongs to another block.
+        uint32_t h[kBinsPerThread], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kBinsPerThread; ++k) {
+            h[k] = hist[tid * kBinsPerThread + k];
+            sum += h[k];
+        }
+        uint32_t total;
+        const uint32_t pre0 = wg_scan_excl(sum, lw, total);
+        int last_block = -1;
+        {
+            uint32_t pre = pre0;
+#pragma unroll
+            for (int k = 0; k < kBinsPerThread; ++k) {
+                if (h[k]) last_block = (int)(pre / kChunkHalf);
+                pre += h[k];
+            }
+        }
+        const int prev0 = wg_max_excl(last_block, lw);
+        int prev = prev0;
+        uint32_t starts = 0;
+        {
+            uint32_t pre = pre0;
+#pragma unroll
+            for (int k = 0; k < kBinsPerThread; ++k) {
+                const int blk = (int)(pre / kChunkHalf);
+                if (h[k] && blk != prev) ++starts;
+                if (h[k]) prev = blk;
+                pre += h[k];
+            }
+        }
+        uint32_t nc;
+        const uint32_t c0 = wg_scan_excl(starts, lw, nc);
+        {
+            // chunk of each bin, and each chunk's first position
+            prev = prev0;
+            uint32_t pre = pre0, c = c0;
+#pragma unroll
+            for (int k = 0; k < kBinsPerThread; ++k) {
+                const int blk = (int)(pre / kChunkHalf);
+                if (h[k] && blk != prev) {
+                    cstart[c] = pre;
+                    ++c;
+                }
+                if (h[k]) prev = blk;
+                cmap[tid * kBinsPerThread + k] = (uint16_t)(c > 0u ? c - 1u : 0u);
+                pre += h[k];
+            }
+        }
+        if (tid == 0) {
+            s_base = atomicAdd(counters + 7, nc);
+            s_nc = nc;
+        }
+        __syncthreads();
+        for (uint32_t c = tid; c < s_nc; c += kT) {
+            const uint32_t e = c + 1u < s_nc ? cstart[c + 1] : n;
+            chunks[s_base + c] = make_uint2(rb + cstart[c], e - cstart[c]);
+            hist[c] = 0;  // fill counts
+        }
+        __syncthreads();
+        for (uint32_t i = rb + tid; i < rb + n; i += kT) {
+            const uint32_t d = depth_of(keys[i]);
+            const uint32_t c = cmap[depth_bin(d)];
+            const uint32_t slot = atomicAdd(&hist[c], 1u);
+            scratch[rb + cstart[c] + slot] = ((uint64_t)d << 32) | vals[i];
+        }
+        __syncthreads();
+    }
+}
+
+// One stable LSD pass over 8 bits, from `shift`, of (id - lo) (by_id) or
+// (depth - lo) of the (depth << 32 | id) keys src[0, n) into dst.  Keys are
+// taken in chunks of 256 in order; inside a chunk a key's place among equal
+// digits is its wavefront's ballot rank plus the counts of the wavefronts
+// before it.
+__device__ void chunk_radix_pass(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint32_t n, bool by_id,
+                                 uint32_t lo, int shift, uint32_t* hst, uint32_t* base, uint32_t (*wc)[256],
+                                 uint32_t* lw) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    auto load = [&](uint32_t i) -> uint64_t {
-        const uint64_t k = src[i];
-        return first ? (((uint64_t)depth_of(k) << 32) | src_ids[i]) : k;
-    };
     auto digit = [&](uint64_t x) -> uint32_t {
         const uint32_t v = by_id ? (uint32_t)x : (uint32_t)(x >> 32);
         return ((v - lo) >> shift) & 255u;
     };
     hst[tid] = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += kT) atomicAdd(&hst[digit(load(i))], 1u);
+    for (uint32_t i = tid; i < n; i += kT) atomicAdd(&hst[digit(src[i])], 1u);
     __syncthreads();
     uint32_t total;
     base[tid] = wg_scan_excl(hst[tid], lw, total);
@@ -306,7 +459,7 @@ __device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t
     for (uint32_t c0 = 0; c0 < n; c0 += kT) {
         const uint32_t i = c0 + tid;
         const bool valid = i < n;
-        const uint64_t x = valid ? load(i) : 0ull;
+        const uint64_t x = valid ? src[i] : 0ull;
         const uint32_t dg = digit(x);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -335,96 +488,42 @@ __device__ void tile_radix_pass(const uint64_t* __restrict__ src, const uint32_t
     }
 }
 
-// Minimum and maximum of the ids vals[b, e), returned to every thread.
-__device__ void id_range(const uint32_t* __restrict__ vals, uint32_t b, uint32_t e, uint32_t* red, uint32_t& lo,
-                         uint32_t& hi) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t mn = 0xffffffffu, mx = 0u;
-    for (uint32_t i = b + threadIdx.x; i < e; i += kT) {
-        const uint32_t v = vals[i];
-        mn = umin(mn, v);
-        mx = umax(mx, v);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = umin(mn, (uint32_t)__shfl_xor((int)mn, o));
-        mx = umax(mx, (uint32_t)__shfl_xor((int)mx, o));
-    }
-    if (lane == 0) {
-        red[wave] = mn;
-        red[kTW + wave] = mx;
-    }
-    __syncthreads();
-    lo = red[0];
-    hi = red[kTW];
-#pragma unroll
-    for (int w = 1; w < kTW; ++w) {
-        lo = umin(lo, red[w]);
-        hi = umax(hi, red[kTW + w]);
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ int bits_of(uint32_t span) {
-    int b = 0;
-    while (b < 32 && (span >> b) != 0u) ++b;
-    return b;
-}
-
-// Grid-stride over tiles; a workgroup takes every tile flagged by the prefix
-// render (flag = its entry count) and sorts its whole list by (depth, id): in
-// LDS when it fits (lds_cap entries), else by stable 8-bit LSD passes over the
-// bits that vary, ping-ponging between scratch (the tile's range of the other
-// key buffer) and the grouped keys, which are no longer needed.  Counts flagged
-// entries into counters[5] and tiles into counters[6]; appends flagged tiles
-// to flist when given.
-__global__ __launch_bounds__(kT) void k_tile_sort_flagged(uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                                          uint64_t* __restrict__ scratch,
-                                                          const uint32_t* __restrict__ ranges,
-                                                          const uint32_t* __restrict__ flag, uint32_t n_tiles,
-                                                          uint32_t* __restrict__ out, uint32_t* __restrict__ len,
-                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ flist,
-                                                          uint32_t lds_cap) {
+// Grid-stride over the chunk list (counters[7] chunks): a chunk of at most
+// kChunkEntries keys is sorted in LDS, a larger one by stable 8-bit LSD
+// passes over the bits that vary (id bits first), ping-ponging between the
+// scratch keys and the grouped keys at the same places (no longer needed).
+__global__ __launch_bounds__(kT) void k_sort_chunks(uint64_t* __restrict__ keys, uint64_t* __restrict__ scratch,
+                                                    const uint2* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ counters, uint32_t* __restrict__ out) {
     extern __shared__ uint64_t sk[];
-    __shared__ uint32_t hst[256], base[256], wc[kTW][256], lw[kTW], red[2 * kTW];
+    __shared__ uint32_t hst[256], base[256], wc[kTW][256], lw[4 * kTW];
     const int tid = threadIdx.x;
-    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const uint32_t n = flag[t];
-        if (n == 0u) continue;
-        if (tid == 0) {
-            atomicAdd(counters + 5, n);
-            const uint32_t slot = atomicAdd(counters + 6, 1u);
-            if (flist) flist[slot] = t;
-            len[t] = n;
-        }
-        const uint32_t rb = ranges[2 * (size_t)t];
-        if (n <= lds_cap) {
-            for (uint32_t i = tid; i < n; i += kT)
-                sk[i] = ((uint64_t)depth_of(keys[rb + i]) << 32) | vals[rb + i];
+    const uint32_t nc = counters[7];
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const uint2 ch = chunks[c];
+        const uint32_t pos = ch.x, n = ch.y;
+        if (n <= kChunkEntries) {
+            for (uint32_t i = tid; i < n; i += kT) sk[i] = scratch[pos + i];
             __syncthreads();
             lds_bitonic(sk, n);
-            for (uint32_t j = tid; j < n; j += kT) out[rb + j] = (uint32_t)sk[j];
+            for (uint32_t j = tid; j < n; j += kT) out[pos + j] = (uint32_t)sk[j];
             __syncthreads();
             continue;
         }
-        // Entries of a tile come in no particular order: sort by the whole
-        // (depth, id) key, least significant part first.
         uint32_t dlo, dhi, ilo, ihi;
-        depth_range(keys, rb, rb + n, red, dlo, dhi);
-        id_range(vals, rb, rb + n, red, ilo, ihi);
+        word_ranges(scratch + pos, n, lw, dlo, dhi, ilo, ihi);
         const int id_passes = (bits_of(ihi - ilo) + 7) / 8;
-        const int passes = max(1, id_passes + (bits_of(dhi - dlo) + 7) / 8);  // at least one pass packs the ids
-        uint64_t* a = keys + rb;
-        uint64_t* b = scratch + rb;
+        const int passes = id_passes + (bits_of(dhi - dlo) + 7) / 8;
+        uint64_t* a = scratch + pos;
+        uint64_t* b = keys + pos;
         for (int p = 0; p < passes; ++p) {
             const bool by_id = p < id_passes;
-            tile_radix_pass(a, vals + rb, p == 0, b, n, by_id, by_id ? ilo : dlo, 8 * (by_id ? p : p - id_passes), hst,
-                            base, wc, lw);
+            chunk_radix_pass(a, b, n, by_id, by_id ? ilo : dlo, 8 * (by_id ? p : p - id_passes), hst, base, wc, lw);
             uint64_t* tmp = a;
             a = b;
             b = tmp;
         }
-        for (uint32_t j = tid; j < n; j += kT) out[rb + j] = (uint32_t)a[j];
+        for (uint32_t j = tid; j < n; j += kT) out[pos + j] = (uint32_t)a[j];
         __syncthreads();
     }
 }
@@ -451,16 +550,20 @@ hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const 
 
 hipError_t launch_tile_sort_flagged(uint64_t* keys, const uint32_t* vals, uint64_t* scratch, const uint32_t* ranges,
                                     const uint32_t* flag, uint32_t n_tiles, uint32_t* out, uint32_t* len,
-                                    uint32_t* counters, uint32_t* flist, hipStream_t s) {
+                                    uint32_t* counters, uint32_t* flist, uint2* chunks, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
-    const uint32_t lds_cap = kMaxPrefix;
-    const unsigned grid = std::min<uint32_t>(n_tiles, 2048u);
-    hipError_t e = hipFuncSetAttribute((const void*)k_tile_sort_flagged, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(8 * lds_cap));
+    hipLaunchKernelGGL(k_flag_chunks, dim3(std::min<uint32_t>(n_tiles, 2048u)), dim3(kT), 0, s, keys, vals, scratch,
+                       ranges, flag, n_tiles, len, counters, flist, chunks);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_sort_flagged, dim3(grid), dim3(kT), 8 * (size_t)lds_cap, s, keys, vals, scratch, ranges,
-                       flag, n_tiles, out, len, counters, flist, lds_cap);
+    const int lds = 8 * (int)kChunkEntries;
+    e = hipFuncSetAttribute((const void*)k_sort_chunks, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_chunks, dim3(1024), dim3(kT), (size_t)lds, s, keys, scratch, (const uint2*)chunks,
+                       (const uint32_t*)counters, out);
     return hipGetLastError();
 }
+
+size_t flagged_chunk_capacity(size_t entries, size_t tiles) { return entries / kChunkHalf + tiles + 1; }
 
 }  // namespace gsr

@@ -173,6 +173,39 @@ def test_prefix_fallback_long_lists(n, longest):
     np.testing.assert_array_equal(g["count"], o.count)
 
 
+def test_fallback_one_depth_layer():
+    """A layer of faint Gaussians at one distance from the camera puts more
+    than 8192 entries of a tile into one depth bin (bits 16..30 of the depth
+    key): the fallback sorts that bin's chunk by radix passes over the id and
+    depth bits instead of in LDS."""
+    n = 40_000
+    rng = np.random.default_rng(11)
+    means = np.zeros((n, 3), np.float32)
+    means[:, :2] = rng.uniform(-0.08, 0.08, (n, 2)).astype(np.float32)
+    scales = np.full((n, 3), 0.01, np.float32)
+    rots = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    opac = np.full(n, 0.02, np.float32)
+    sh = rng.uniform(0.0, 1.0, (n, 1, 3)).astype(np.float32)
+    sc = synth.Scene(means, scales, rots, opac, sh, 0)
+    cam = synth.front_camera(32, 32)
+    say("case: fallback, one depth layer")
+    o = oracle.frame(sc, cam, mode=oracle.MODE_HIER, max_k=64)
+    base = np.uint64(0xBB800000)
+    deepest_bin = 0
+    for lo, hi in o.ranges.astype(np.int64):
+        d = o.keys[lo:hi] & np.uint64(0xffffffff)
+        b = (d[d >= base] - base) >> np.uint64(16)
+        if b.size:
+            deepest_bin = max(deepest_bin, int(np.bincount(b.astype(np.int64)).max()))
+    assert deepest_bin > 8192, deepest_bin
+    g = gpu_frame(sc, cam, mode=oracle.MODE_HIER, max_k=64, sort_prefix=256)
+    assert g["lists"]["fallback_entries"] > 8192
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    np.testing.assert_array_equal(g["count"], o.count)
+
+
 @pytest.mark.parametrize("K", [1, 4, 8, 16, 24])
 def test_window_mode_bit_exact(K):
     """Per-ray resorting window (Sec. 3.3) over the 3DGS lists."""
