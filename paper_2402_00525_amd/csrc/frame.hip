@@ -932,14 +932,50 @@ struct BwdArgs {
 // quaternion, opacity and SH coefficients.  The forward quantities are
 // recomputed; clamped colour channels and a clamped frustum coordinate pass
 // no gradient through the clamped variable.
-__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.sc.n) return;
+// SH coefficients of a wavefront's 64 Gaussians staged in LDS, kBwdShStride
+// floats per Gaussian (odd, so that the lanes' rows fall in distinct banks):
+// the coefficients are read and their gradients written in whole contiguous
+// runs rather than one 4-byte word per lane every 3 (d + 1)^2 words.
+constexpr int kBwdShStride = 49;  // >= 48 = 3 (3 + 1)^2
+
+// Copies the S coefficients of `cnt` consecutive Gaussians between global
+// memory (g, contiguous) and the staging (rows of kBwdShStride floats).
+__device__ __forceinline__ void sh_stage_in(float* stage, const float* __restrict__ g, int cnt, int S) {
+    if (cnt <= 0 || S <= 0) return;
+    const int lane = __lane_id(), total = cnt * S, dg = 64 / S, dk = 64 % S;
+    int gi = lane / S, k = lane - gi * S;
+    for (int j = lane; j < total; j += 64) {
+        stage[gi * kBwdShStride + k] = g[j];
+        gi += dg;
+        k += dk;
+        if (k >= S) {
+            k -= S;
+            ++gi;
+        }
+    }
+}
+__device__ __forceinline__ void sh_stage_out(const float* stage, float* __restrict__ g, int cnt, int S) {
+    if (cnt <= 0 || S <= 0) return;
+    const int lane = __lane_id(), total = cnt * S, dg = 64 / S, dk = 64 % S;
+    int gi = lane / S, k = lane - gi * S;
+    for (int j = lane; j < total; j += 64) {
+        g[j] = stage[gi * kBwdShStride + k];
+        gi += dg;
+        k += dk;
+        if (k >= S) {
+            k -= S;
+            ++gi;
+        }
+    }
+}
+
+// One Gaussian; sh holds its coefficients on entry and their gradients on
+// return (both in the staging).
+__device__ __forceinline__ void preprocess_bwd_one(const BwdArgs& a, int i, float* sh) {
     const int deg = a.sc.deg, K = (deg + 1) * (deg + 1);
-    float* dsh = a.dsh + (size_t)i * 3 * K;
     const bool vis = a.pk[4 * (size_t)i + 1].y > 0.0f;  // opacity; zero when culled
     if (!vis) {
-        for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.0f;
+        for (int k = 0; k < 3 * K; ++k) sh[k] = 0.0f;
         for (int j = 0; j < 3; ++j) a.dmeans[3 * i + j] = a.dscales[3 * i + j] = 0.0f;
         for (int j = 0; j < 4; ++j) a.drots[4 * i + j] = 0.0f;
         a.dopac[i] = 0.0f;
@@ -1002,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
     const float dx_ = dm[0] / len, dy_ = dm[1] / len, dz_ = dm[2] / len;
     float bas[16];
     sh_basis(deg, dx_, dy_, dz_, bas);
-    const float* shp = a.sc.sh + (size_t)i * 3 * K;
+    float* shp = sh;
     float gacc[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -1013,10 +1049,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
     }
     float wk[16];
     for (int k = 0; k < K; ++k) {
-        dsh[3 * k] = bas[k] * gacc[0];
-        dsh[3 * k + 1] = bas[k] * gacc[1];
-        dsh[3 * k + 2] = bas[k] * gacc[2];
         wk[k] = gacc[0] * shp[3 * k] + gacc[1] * shp[3 * k + 1] + gacc[2] * shp[3 * k + 2];
+        shp[3 * k] = bas[k] * gacc[0];  // the coefficient's gradient replaces it
+        shp[3 * k + 1] = bas[k] * gacc[1];
+        shp[3 * k + 2] = bas[k] * gacc[2];
     }
     const float3 gd = sh_basis_vjp(deg, dx_, dy_, dz_, wk);
     const float dd = dx_ * gd.x + dy_ * gd.y + dz_ * gd.z;
@@ -1098,6 +1134,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) a.dmeans[3 * i + j] = dmu[j];
     a.dopac[i] = gop;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess_bwd(BwdArgs a) {
+    __shared__ float s_sh[4][64 * kBwdShStride];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * blockDim.x + wave * 64;
+    const int S = 3 * (a.sc.deg + 1) * (a.sc.deg + 1);
+    const int cnt = a.sc.n - i0 < 64 ? a.sc.n - i0 : 64;
+    float* st = s_sh[wave];
+    sh_stage_in(st, a.sc.sh + (size_t)(i0 > 0 ? i0 : 0) * S, cnt, S);
+    wave_lds_sync();
+    if (lane < cnt) preprocess_bwd_one(a, i0 + lane, st + lane * kBwdShStride);
+    wave_lds_sync();
+    sh_stage_out(st, a.dsh + (size_t)(i0 > 0 ? i0 : 0) * S, cnt, S);
 }
 
 __global__ void k_probe_math(const float* a, const float* b, int n, float* out) {
