@@ -228,12 +228,14 @@ enum { MODE_GLOBAL = 0, MODE_HIER = 1, MODE_FULL = 2, MODE_WINDOW = 3 };
 inline bool gs_lists(int mode) { return mode == MODE_GLOBAL || mode == MODE_WINDOW; }
 
 template <class F> struct Cam {
-    F R[9], t[3], o[3], fx, fy, cx, cy, znear, limx, limy;
+    F R[9], t[3], o[3], fx, fy, cx, cy, znear, limx, limy, rfx, rfy;
     int W, H, tiles_x, tiles_y;
     explicit Cam(const OCam& c) {
         for (int i = 0; i < 9; ++i) R[i] = (F)c.R[i];
         for (int i = 0; i < 3; ++i) { t[i] = (F)c.t[i]; o[i] = (F)c.center[i]; }
         fx = c.fx; fy = c.fy; cx = c.cx; cy = c.cy; znear = c.znear;
+        rfx = F(1) / fx;
+        rfy = F(1) / fy;
         W = c.W; H = c.H;
         tiles_x = (W + 15) / 16;
         tiles_y = (H + 15) / 16;
@@ -242,11 +244,12 @@ template <class F> struct Cam {
         limy = F(1.3) * ((F)H / (F(2) * fy));
     }
     // Unit world-space ray direction through image point (u, v):
-    // d_c = ((u-cx)/fx, (v-cy)/fy, 1), d_w = R^T d_c, d = d_w / |d_w|; each
-    // component of d_w and |d_w|^2 by fused multiply-adds, and d_w scaled by
-    // the one reciprocal 1 / |d_w|.
+    // d_c = ((u-cx)/fx, (v-cy)/fy, 1), d_w = R^T d_c, d = d_w / |d_w|; the
+    // divisions by the focal lengths as products with 1/fx and 1/fy (each
+    // rounded once), each component of d_w and |d_w|^2 by fused
+    // multiply-adds, and d_w scaled by the one reciprocal 1 / |d_w|.
     void ray(F u, F v, F d[3]) const {
-        F a = (u - cx) / fx, b = (v - cy) / fy;
+        F a = (u - cx) * rfx, b = (v - cy) * rfy;
         F w0 = std::fma(R[3], b, std::fma(R[0], a, R[6]));
         F w1 = std::fma(R[4], b, std::fma(R[1], a, R[7]));
         F w2 = std::fma(R[5], b, std::fma(R[2], a, R[8]));

@@ -138,6 +138,8 @@ gsr::DevCam make_cam(const gsr_camera* c) {
     }
     d.fx = c->fx;
     d.fy = c->fy;
+    d.rfx = 1.0f / c->fx;
+    d.rfy = 1.0f / c->fy;
     d.cx = c->cx;
     d.cy = c->cy;
     d.znear = c->znear;

@@ -21,6 +21,7 @@ struct DevCam {
     float t[3];
     float o[3];
     float fx, fy, cx, cy, znear, limx, limy;
+    float rfx, rfy;  // 1 / fx, 1 / fy, each rounded once
     int W, H, tiles_x, tiles_y;
 };
 
@@ -78,11 +79,12 @@ __device__ __forceinline__ float depth_from_bits(uint32_t b) {
 }
 
 // Unit world-space direction of the ray through image point (u, v): the
-// camera-frame direction ((u - cx) / fx, (v - cy) / fy, 1) rotated to the
-// world by fused multiply-adds and scaled by the one reciprocal of its norm.
+// camera-frame direction ((u - cx) rfx, (v - cy) rfy, 1) with rfx = 1 / fx,
+// rfy = 1 / fy, rotated to the world by fused multiply-adds and scaled by the
+// one reciprocal of its norm.
 __device__ __forceinline__ float3 cam_ray(const DevCam& c, float u, float v) {
-    const float a = (u - c.cx) / c.fx;
-    const float b = (v - c.cy) / c.fy;
+    const float a = (u - c.cx) * c.rfx;
+    const float b = (v - c.cy) * c.rfy;
     const float w0 = fmaf(c.R[3], b, fmaf(c.R[0], a, c.R[6]));
     const float w1 = fmaf(c.R[4], b, fmaf(c.R[1], a, c.R[7]));
     const float w2 = fmaf(c.R[5], b, fmaf(c.R[2], a, c.R[8]));
