@@ -335,9 +335,9 @@ def cpu_baseline(scene, cam, E):
     est = pre + dup + srt + ren * tiles / int(mask.sum())
     return {"value": round(est, 1), "unit": "ms/frame", "cores": int(r.stats["threads"]), "kind": "oracle",
             "cpu": cpu_model(),
-            "sample": "one 1920x1080 frame of the same scene: all %d Gaussians preprocessed, duplicated and sorted "
+            "sample": "one %dx%d frame of the same scene: all %d Gaussians preprocessed, duplicated and sorted "
                       "(%d entries), hierarchical render on %d of %d tiles scaled to the full image; %.1f s wall"
-                      % (scene.n, r.stats["entries"], int(mask.sum()), tiles, wall),
+                      % (cam.W, cam.H, scene.n, r.stats["entries"], int(mask.sum()), tiles, wall),
             "stages_ms": {"preprocess": round(pre, 1), "duplicate": round(dup, 1), "sort": round(srt, 1),
                           "render_scaled": round(ren * tiles / int(mask.sum()), 1)}}
 
@@ -597,8 +597,10 @@ def main():
         "metric": METRIC, "value": round(h["ms"], 4), "unit": "ms/frame", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(h["ms"], 4), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%d-Gaussian mixture scene (SH degree %d), %dx%d, 60-view orbit, hierarchical "
-                               "resort 64/8/4" % (n, scene.sh_degree, W, H),
+        "config": {"workload": ("%d-Gaussian uniform scene (SH degree %d), %dx%d, one camera at distance 3, "
+                                "hierarchical resort 64/8/4" % (n, scene.sh_degree, W, H)) if args.workload == "small"
+                   else ("%d-Gaussian mixture scene (SH degree %d), %dx%d, 60-view orbit, hierarchical resort "
+                         "64/8/4" % (n, scene.sh_degree, W, H)),
                    "gaussians": n, "width": W, "height": H, "views": len(cams), "head": 4},
         "stages_ms": {k: round(v, 4) for k, v in zip(("preprocess", "duplicate", "sort", "render"), h["stages"])},
         "entries": int(h["E"]), "entries_consumed": int(h["consumed"]), "fallback_entries": int(h["fallback"]),

@@ -2,7 +2,7 @@
 oracle, per element (Sec. 3.5).
 
 The 2D gradients the render accumulates (atomics, per-tile LDS slots for the
-first 1024 list ranks and global atomics beyond) are compared with the float64
+first 512 list ranks and global atomics beyond) are compared with the float64
 oracle's sums within a rounding bound derived from each sum's own terms; the
 parameter gradients with the float64 chain rule applied to the GPU's own 2D
 gradients, within the spread of float32 evaluations of that chain (see
@@ -52,7 +52,7 @@ def _faint_scene():
     return sc, synth.front_camera(64, 48)
 
 
-def _blends_at_deep_ranks(scene, cam, slots=1024):
+def _blends_at_deep_ranks(scene, cam, slots=512):
     """Blends (pixel, Gaussian) whose Gaussian sits at list rank >= slots in
     its tile's sorted list (oracle)."""
     fr = oracle.frame(scene, cam, max_k=256)
@@ -82,7 +82,7 @@ def test_backward_matches_oracle(case):
         head = 8 if case.endswith("head8") else (2 if case.endswith("head2") else 4)
     elif case == "long_lists":
         # faint Gaussians keep pixels alive deep into lists of thousands of
-        # entries: blends at list ranks beyond the 1024 LDS gradient slots
+        # entries: blends at list ranks beyond the 512 LDS gradient slots
         # take the global atomics
         scene, cam = _faint_scene()
         prefix = 256
