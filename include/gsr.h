@@ -206,7 +206,9 @@ int gsr_check_config(const gsr_config* cfg /* host */);
  * Gaussian id) order are selected and sorted, and a tile whose pixels are
  * still unfinished when its prefix runs out has its whole list sorted and is
  * rendered again (enqueued always; tiles that need nothing exit at once): the
- * order is that of a full sort by (tile, depth, id) in every case.  The
+ * order is that of a full sort by (tile, depth, id) in every case.  When the
+ * default prefix is 0 (small images) every tile's whole list is sorted first
+ * and rendered once.  The
  * blend order is that of the mode (see GSR_MODE_*).
  *   rgb     [3,H,W] float32 out   colour + T_final * bg
  *   depth   [H,W]   float32 out   sum of t_opt alpha T (t_opt along the pixel ray in FULL and
@@ -299,9 +301,10 @@ int gsr_group_passes(int32_t W, int32_t H);
  * gsr_config.sort_prefix is 0, for a W x H image in `mode` (speed only; the
  * blend order never depends on it): a power of two near 2^23 / tiles (2^25 /
  * tiles for GSR_MODE_GLOBAL and GSR_MODE_WINDOW), at least 1024 (4096) and at
- * most 8192, and the minimum below 512 tiles -- 1024 at 1920x1080, 2048 at
- * 1280x720, 8192 at 512x512, 1024 at 256x256.  The batch API's default is
- * the large-frame one (1024; 4096).  GSR_EINVAL for bad arguments. */
+ * most 8192 -- 1024 at 1920x1080, 2048 at 1280x720, 8192 at 512x512; below
+ * 512 tiles 0: no prefix, every tile's whole list sorted before one render
+ * pass (256x256).  The batch API's default is the large-frame one (1024;
+ * 4096).  GSR_EINVAL for bad arguments. */
 int gsr_default_prefix(int32_t W, int32_t H, int32_t mode);
 
 /* ---------------------------------------------------------------------------

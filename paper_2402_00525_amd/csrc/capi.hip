@@ -256,13 +256,13 @@ __global__ void k_write_words(uint32_t* dst, uint4 v) {
 // and a longer prefix spares their tiles the whole-list fallback and the
 // second render (1M-Gaussian scene, ms per frame at M = 1024 / 2048 / 8192:
 // 1280x720 2.51 / 1.70 / -, 512x512 - / 3.73 / 2.40).  Below 512 tiles a
-// dense scene's pixels reach deeper than any prefix sorted in LDS, the
-// fallback cannot be avoided, and the shortest first pass is the fastest
-// (256x256: 7.28 ms at 1024, 8.98 at 16384).
+// dense scene's pixels reach deeper than any prefix sorted in LDS and most
+// deep tiles would be rendered twice, so 0 is returned: every tile's whole
+// list is sorted up front (by the chunked fallback sort) and rendered once.
 int default_prefix(int tiles, int mode) {
     const bool global = mode == GSR_MODE_GLOBAL || mode == GSR_MODE_WINDOW;
     int m = global ? 4096 : 1024;
-    if (tiles < 512) return m;
+    if (tiles < 512) return 0;
     const int64_t budget = global ? ((int64_t)1 << 25) : ((int64_t)1 << 23);
     while (2 * m <= 8192 && (int64_t)(2 * m) * tiles <= budget) m *= 2;
     return m;
@@ -293,7 +293,7 @@ hipError_t sort_stage(const gsr::FrameBufs& b, int tiles, int mode, uint32_t M, 
     }
     if ((e = mark(0)) != hipSuccess) return e;
     if ((e = gsr::launch_tile_prefix(b.keys[0], b.vals[0], b.counters, (uint32_t)tiles, b.ranges, b.pre_vals,
-                                     b.pre_len, M, s)) != hipSuccess)
+                                     b.pre_len, b.tile_flag, M, s)) != hipSuccess)
         return e;
     (void)mode;
     return mark(1);
@@ -419,28 +419,26 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
         if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
         if ((e = gsr::launch_render_full(ra, s)) != hipSuccess) return fail_hip(e, "render");
         if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
-    } else if (mode == GSR_MODE_HIER) {
-        set_prefix_lists(ra, b, gsr::kListPrefix);
-        if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
-        if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render");
-        if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
-        if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
-        ra.work = nullptr;  // the work of the prefix pass is counted
-        ra.list_mode = gsr::kListFlagged;
-        if ((e = gsr::launch_render_hier(ra, cfg->head, s)) != hipSuccess) return fail_hip(e, "render fallback");
     } else {
-        // The 3DGS order and the resort window over its lists: the same
-        // prefix pass and fallback as the hierarchical order.
+        // Prefix pass, then the fallback: the flagged tiles' whole lists are
+        // sorted and those tiles rendered again.  With M = 0 every tile's
+        // whole list is sorted first and one pass renders them.
         const bool window = cfg->mode == GSR_MODE_WINDOW;
+        auto render = [&]() -> hipError_t {
+            if (mode == GSR_MODE_HIER) return gsr::launch_render_hier(ra, cfg->head, s);
+            return window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
+        };
+        if (M == 0 && (e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "whole-list sort");
         set_prefix_lists(ra, b, gsr::kListPrefix);
         if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
-        e = window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
-        if (e != hipSuccess) return fail_hip(e, "render");
+        if ((e = render()) != hipSuccess) return fail_hip(e, "render");
         if ((e = kmark(3)) != hipSuccess) return fail_hip(e, "event");
-        if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
-        ra.list_mode = gsr::kListFlagged;
-        e = window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
-        if (e != hipSuccess) return fail_hip(e, "render fallback");
+        if (M != 0) {
+            if ((e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "fallback sort");
+            ra.work = nullptr;  // the work of the prefix pass is counted
+            ra.list_mode = gsr::kListFlagged;
+            if ((e = render()) != hipSuccess) return fail_hip(e, "render fallback");
+        }
     }
     if ((e = mark(4)) != hipSuccess) return fail_hip(e, "event");
     return GSR_OK;

@@ -108,9 +108,11 @@ constexpr int kMaxPrefix = 16384;  // entries a workgroup sorts in LDS (128 KiB 
 // Per tile of the tile-grouped keys[0, *n_ptr): its range [start, end) into
 // ranges, and its sorted prefix -- the C <= M entries of smallest (depth, id)
 // -- as ids at out[start + j], len[tile] = C (C = all entries when the tile
-// has at most M).  M <= kMaxPrefix.
+// has at most M).  M <= kMaxPrefix.  M = 0 sorts nothing here: every
+// non-empty tile gets flag[tile] = its entry count, for the whole-list sort.
 hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* n_ptr, uint32_t n_tiles,
-                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s);
+                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t* flag, uint32_t M,
+                              hipStream_t s);
 // Whole sorted list of every flagged tile (flag[t] = its entry count) at
 // out[range begin ..], len[t] = count; `scratch` is a second key buffer of the
 // same capacity and the grouped keys are overwritten.  The lists are split

@@ -142,7 +142,8 @@ __device__ void tile_starts(const uint64_t* __restrict__ keys, uint32_t E, uint3
 }
 
 // One workgroup per tile.  Finds the tile's range in the grouped keys (and
-// writes it to ranges), then: a list of at most M entries is taken whole;
+// writes it to ranges), then (M = 0) flags a non-empty tile for the whole-list
+// sort, or: a list of at most M entries is taken whole;
 // a longer one gets a histogram of depth_bin over its entries, and C = the
 // entries of the bins before the first bin at which the running count
 // exceeds M (the C smallest keys).  The selected (depth << 32 | id) keys are
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
                                                     const uint32_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ n_ptr, uint32_t n_tiles,
                                                     uint32_t* __restrict__ ranges, uint32_t* __restrict__ out,
-                                                    uint32_t* __restrict__ len, uint32_t M) {
+                                                    uint32_t* __restrict__ len, uint32_t* __restrict__ flag,
+                                                    uint32_t M) {
     extern __shared__ uint64_t sk[];
     __shared__ uint32_t hist[kPrefixBins];
     __shared__ uint32_t red[2 * kTW];
@@ -166,6 +168,13 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
         ranges[2 * (size_t)tile + 1] = re > rb ? re : 0u;
     }
     const uint32_t n = re - rb;
+    if (M == 0u) {  // whole lists: every non-empty tile goes to the chunked sort
+        if (tid == 0) {
+            len[tile] = 0u;
+            if (n > 0u) flag[tile] = n;
+        }
+        return;
+    }
     if (n <= M) {
         for (uint32_t i = tid; i < n; i += kT) sk[i] = ((uint64_t)depth_of(keys[rb + i]) << 32) | vals[rb + i];
         __syncthreads();
@@ -537,14 +546,15 @@ uint32_t pow2ceil(uint32_t x) {
 }  // namespace
 
 hipError_t launch_tile_prefix(const uint64_t* keys, const uint32_t* vals, const uint32_t* n_ptr, uint32_t n_tiles,
-                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t M, hipStream_t s) {
+                              uint32_t* ranges, uint32_t* out, uint32_t* len, uint32_t* flag, uint32_t M,
+                              hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     const size_t shmem = 8 * (size_t)pow2ceil(std::max<uint32_t>(M, 1u));
     hipError_t e = hipFuncSetAttribute((const void*)k_tile_prefix, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)(8 * kMaxPrefix));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_prefix, dim3(n_tiles), dim3(kT), shmem, s, keys, vals, n_ptr, n_tiles, ranges, out, len,
-                       M);
+                       flag, M);
     return hipGetLastError();
 }
 

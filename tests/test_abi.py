@@ -145,14 +145,15 @@ def test_sort_pass_count(L):
 
 def test_default_prefix_by_image_size(L):
     # about 2^23 sorted entries per frame (2^25 for the 3DGS lists), a power
-    # of two between 1024 (4096) and 8192, the minimum below 512 tiles
+    # of two between 1024 (4096) and 8192; below 512 tiles 0 (whole lists sorted up front)
     f = L.lib().gsr_default_prefix
     assert f(1920, 1080, L.MODE_HIER) == 1024
     assert f(1280, 720, L.MODE_HIER) == 2048
     assert f(512, 512, L.MODE_HIER) == 8192
-    assert f(256, 256, L.MODE_HIER) == 1024
+    assert f(256, 256, L.MODE_HIER) == 0
+    assert f(128, 128, L.MODE_HIER) == 0 and f(368, 352, L.MODE_HIER) == 0 and f(368, 368, L.MODE_HIER) == 8192
     assert f(3840, 2160, L.MODE_HIER) == 1024
     assert f(1920, 1080, L.MODE_GLOBAL) == 4096
     assert f(512, 512, L.MODE_WINDOW) == 8192
-    assert f(256, 256, L.MODE_WINDOW) == 4096
+    assert f(256, 256, L.MODE_WINDOW) == 0
     assert f(0, 10, L.MODE_HIER) < 0 and f(10, 10, 9) < 0

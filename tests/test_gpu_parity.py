@@ -63,6 +63,30 @@ def test_small_scene_bit_exact(mode):
     np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
 
 
+@pytest.mark.parametrize("mode,prefix", [(oracle.MODE_HIER, 0), (oracle.MODE_HIER, 64), (oracle.MODE_GLOBAL, 0)])
+def test_small_image_whole_lists(mode, prefix):
+    """Below 512 tiles the default sorts every tile's whole list before one
+    render pass (no prefix); an explicit prefix keeps the prefix pass and the
+    fallback.  Both give the oracle's lists and blend order."""
+    from paper_2402_00525_amd import gsr
+    sc = synth.subsample(synth.mixture_scene(100_000, seed=3), 30_000)
+    cam = synth.orbit_camera(256, 256, 11)
+    assert gsr.lib().gsr_default_prefix(256, 256, mode) == 0
+    say("case: 256x256, mode", mode, "prefix", prefix)
+    o = oracle.frame(sc, cam, mode=mode, max_k=64)
+    g = gpu_frame(sc, cam, mode=mode, max_k=64, sort_prefix=prefix)
+    L = g["lists"]
+    nonempty = int((np.diff(L["ranges"], axis=1) > 0).sum())
+    if prefix == 0:
+        assert L["fallback_tiles"] == nonempty and L["fallback_entries"] == len(g["keys"])
+    else:
+        assert 0 < L["fallback_tiles"] < nonempty
+    assert_sorted_equal(g, o)
+    np.testing.assert_array_equal(g["blend_ids"], o.blend_ids)
+    np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
+    np.testing.assert_array_equal(g["count"], o.count)
+
+
 @pytest.mark.parametrize("head", [1, 2, 3, 6, 8, 12, 16, 20, 24])
 def test_head_sizes_bit_exact(head):
     sc, cam = synth.workload_small()
