@@ -429,6 +429,7 @@ int render_impl(const gsr_scene* scene, const gsr_camera* cam, const gsr_config*
             return window ? gsr::launch_render_window(ra, cfg->head, s) : gsr::launch_render_global(ra, s);
         };
         if (M == 0 && (e = fallback_sort(b, tiles, s)) != hipSuccess) return fail_hip(e, "whole-list sort");
+        ra.deep = M == 0;  // few tiles with whole lists: one wavefront per SIMD or fewer
         set_prefix_lists(ra, b, gsr::kListPrefix);
         if ((e = kmark(2)) != hipSuccess) return fail_hip(e, "event");
         if ((e = render()) != hipSuccess) return fail_hip(e, "render");

@@ -165,6 +165,10 @@ struct RenderArgs {
     const uint32_t* pre_len;
     uint32_t* tile_flag;
     int flags;  // kAblateHierCull: no culling at the 4x4 and 2x2 levels
+    // The hierarchical forward loads every splat a level reads ahead (for
+    // views of few, deep tiles, where nothing else hides a wavefront's
+    // memory latency; more registers per lane).
+    bool deep;
     unsigned long long* work;  // if set: the hierarchical render counts its evaluations (head 4 only)
     // backward only: the fingerprint the forward left in the workspace (fp,
     // kFingerprintWords words) and the one this call expects; on a mismatch

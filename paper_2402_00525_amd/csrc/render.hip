@@ -413,7 +413,13 @@ __device__ __forceinline__ void head_push(const RenderArgs& a, PixelState<K, MOD
                        key_rank<K, MODE>(bk), acc);
 }
 
-template <int K, int MODE>
+// DEEP: the variant for views of few, deep tiles (one wavefront per SIMD or
+// fewer, so nothing else hides a wavefront's memory latency): every splat a
+// level will read is loaded ahead -- the next tail batch's while the current
+// one is merged, all of a tail pop's mid sub-batches and all of a mid pop's
+// head entries at once -- in registers that the default variant cannot spare
+// without losing occupancy.  The arithmetic and the order are the same.
+template <int K, int MODE, bool DEEP = false>
 struct HierCtx {
     const RenderArgs& a;
     WaveQueues& q;
@@ -435,6 +441,10 @@ struct HierCtx {
         // The backward keeps the whole quad in the loop: its gradient terms
         // are combined across the quad after every entry.
         if (MODE != kBwd && (st.done || !pix_ok)) return;
+        if (DEEP) {
+            push_head_all(c, ms0);
+            return;
+        }
         uint32_t idn = q.mid[gq][ms0];
         idn = idn < a.n ? idn : 0u;
         Splat gn = load_packed(a.pk, idn);  // the next entry's splat, loaded one entry ahead
@@ -461,66 +471,133 @@ struct HierCtx {
         }
     }
 
-    // Mid level: a chunk of cl tail entries of row `row`, from position cs.
-    __device__ void push_mid(int cs, int cl) {
-        if (!quad_ok) return;
-        for (int r0 = 0; r0 < cl; r0 += kMidBatch) {
-            const int idx = r0 + pl;
-            uint64_t key = kInvalidKey;
-            uint32_t id = 0;
-            if (idx < cl) {
-                const uint64_t tk = q.tkey[row][cs + idx];
-                id = q.tid[row][cs + idx];
-                id = id < a.n ? id : 0u;
-                const Splat g = load_packed(a.pk, id);
-                if (MODE == kFwdCount) ++work[kWorkMidTest];
-                if ((a.flags & kAblateHierCull) || block_clears(g, Q0, Q1, Q2, Q3)) {
-                    if (MODE == kFwdCount) ++work[kWorkMidKey];
-                    key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
+    // push_head with every entry's splat loaded up front (DEEP; forward).
+    __device__ void push_head_all(int c, int ms0) {
+        uint32_t ids[kMidBatch];
+        Splat gs[kMidBatch];
+#pragma unroll
+        for (int e = 0; e < kMidBatch; ++e) {
+            if (e < c) {
+                uint32_t id = q.mid[gq][ms0 + e];
+                ids[e] = id < a.n ? id : 0u;
+                gs[e] = load_packed(a.pk, ids[e]);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kMidBatch; ++e) {
+            if (e < c && !st.done) {
+                const uint64_t mk = q.mkey[gq][ms0 + e];
+                float alpha;
+                if (MODE == kFwdCount) ++work[kWorkHeadTest];
+                if (pixel_alpha(gs[e], (float)px, (float)py, alpha)) {
+                    if (MODE == kFwdCount) ++work[kWorkHeadKey];
+                    const float t = t_opt(gs[e], dP);
+                    head_push<K, MODE>(a, st, pix, ((uint64_t)depth_bits(t) << 32) | (mk & 0xffffffffull), ids[e],
+                                       alpha, acc);
                 }
             }
-            uint64_t qk[4];
-            quad_all(key, qk);
-            int rnk = 0, nnew = 0;
+        }
+    }
+
+    // Mid level: a chunk of cl <= kPop tail entries of row `row`, from
+    // position cs, in sub-batches of kMidBatch (one entry per lane of a quad).
+    __device__ void push_mid(int cs, int cl) {
+        if (!quad_ok) return;
+        if (DEEP) {
+            // every sub-batch's tail entry and splat loaded up front (the
+            // tail queue does not change during a pop)
+            uint64_t dtk[kPop / kMidBatch];
+            uint32_t did[kPop / kMidBatch];
+            Splat dg[kPop / kMidBatch];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                rnk += qk[m] < key ? 1 : 0;
-                nnew += qk[m] != kInvalidKey ? 1 : 0;
+            for (int sb = 0; sb < kPop / kMidBatch; ++sb) {
+                const int idx = sb * kMidBatch + pl;
+                dtk[sb] = kInvalidKey;
+                did[sb] = 0u;
+                if (idx < cl) {
+                    dtk[sb] = q.tkey[row][cs + idx];
+                    const uint32_t id = q.tid[row][cs + idx];
+                    did[sb] = id < a.n ? id : 0u;
+                    dg[sb] = load_packed(a.pk, did[sb]);
+                }
             }
-            // The queue holds mn <= 4 entries from ms: one per lane of the quad.
-            uint64_t ek = kInvalidKey;
-            uint32_t eid = 0;
-            if (pl < mn) {
-                ek = q.mkey[gq][ms + pl];
-                eid = q.mid[gq][ms + pl];
-            }
-            uint64_t qe[4];
-            quad_all(ek, qe);
-            wave_lds_sync();
-            if (pl < mn) {
-                int c = 0;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) c += qk[m] < ek ? 1 : 0;
-                q.mkey[gq][pl + c] = ek;
-                q.mid[gq][pl + c] = eid;
+            for (int sb = 0; sb < kPop / kMidBatch; ++sb) {
+                if (sb * kMidBatch >= cl) break;
+                mid_sub_batch(cl, sb * kMidBatch, dtk[sb], did[sb], dg[sb]);
             }
-            if (key != kInvalidKey) {
-                int c = 0;
+            return;
+        }
+        for (int r0 = 0; r0 < cl; r0 += kMidBatch) {
+            const int idx = r0 + pl;
+            uint64_t tk = kInvalidKey;
+            uint32_t id = 0;
+            Splat g;
+            if (idx < cl) {
+                tk = q.tkey[row][cs + idx];
+                id = q.tid[row][cs + idx];
+                id = id < a.n ? id : 0u;
+                g = load_packed(a.pk, id);
+            }
+            mid_sub_batch(cl, r0, tk, id, g);
+        }
+    }
+
+    // One sub-batch: lane pl's tail entry r0 + pl (tail key tk, Gaussian id,
+    // splat g; none when r0 + pl >= cl) is culled against the quad and keyed
+    // along its ray, merged into the quad's mid queue, and the queue pops
+    // into the heads when it holds more than kMidCap - kMidBatch.
+    __device__ __forceinline__ void mid_sub_batch(int cl, int r0, uint64_t tk, uint32_t id, const Splat& g) {
+        const int idx = r0 + pl;
+        uint64_t key = kInvalidKey;
+        if (idx < cl) {
+            if (MODE == kFwdCount) ++work[kWorkMidTest];
+            if ((a.flags & kAblateHierCull) || block_clears(g, Q0, Q1, Q2, Q3)) {
+                if (MODE == kFwdCount) ++work[kWorkMidKey];
+                key = ((uint64_t)depth_bits(t_opt(g, dQ)) << 32) | (tk & 0xffffffffull);
+            }
+        }
+        uint64_t qk[4];
+        quad_all(key, qk);
+        int rnk = 0, nnew = 0;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) c += (m < mn && qe[m] < key) ? 1 : 0;
-                q.mkey[gq][rnk + c] = key;
-                q.mid[gq][rnk + c] = id;
-            }
-            wave_lds_sync();
-            ms = 0;
-            mn += nnew;
-            // at most one pop: the queue held at most kMidBatch before this
-            // sub-batch of at most kMidBatch (kMidCap = 2 kMidBatch)
-            if (mn > kMidCap - kMidBatch) {
-                push_head(kMidBatch, ms);
-                ms += kMidBatch;
-                mn -= kMidBatch;
-            }
+        for (int m = 0; m < 4; ++m) {
+            rnk += qk[m] < key ? 1 : 0;
+            nnew += qk[m] != kInvalidKey ? 1 : 0;
+        }
+        // The queue holds mn <= 4 entries from ms: one per lane of the quad.
+        uint64_t ek = kInvalidKey;
+        uint32_t eid = 0;
+        if (pl < mn) {
+            ek = q.mkey[gq][ms + pl];
+            eid = q.mid[gq][ms + pl];
+        }
+        uint64_t qe[4];
+        quad_all(ek, qe);
+        wave_lds_sync();
+        if (pl < mn) {
+            int c = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) c += qk[m] < ek ? 1 : 0;
+            q.mkey[gq][pl + c] = ek;
+            q.mid[gq][pl + c] = eid;
+        }
+        if (key != kInvalidKey) {
+            int c = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) c += (m < mn && qe[m] < key) ? 1 : 0;
+            q.mkey[gq][rnk + c] = key;
+            q.mid[gq][rnk + c] = id;
+        }
+        wave_lds_sync();
+        ms = 0;
+        mn += nnew;
+        // at most one pop: the queue held at most kMidBatch before this
+        // sub-batch of at most kMidBatch (kMidCap = 2 kMidBatch)
+        if (mn > kMidCap - kMidBatch) {
+            push_head(kMidBatch, ms);
+            ms += kMidBatch;
+            mn -= kMidBatch;
         }
     }
 };
@@ -551,13 +628,13 @@ __device__ __forceinline__ TileList tile_list(const RenderArgs& a, int t) {
     return L;
 }
 
-template <int K, int MODE>
+template <int K, int MODE, bool DEEP = false>
 __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, int range_tile, int strip,
                                                  WaveQueues& q, float* acc, float* pay) {
     const int lane = threadIdx.x & 63, wave = strip;
     const DevCam& cam = a.cam;
     const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-    HierCtx<K, MODE> h(a, q);
+    HierCtx<K, MODE, DEEP> h(a, q);
     h.acc = acc;
     if (MODE == kFwdCount)
         for (int w = 0; w < kWorkN; ++w) h.work[w] = 0u;
@@ -630,21 +707,37 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
     const bool truncated = tl.truncated;
     const uint32_t begin = 0;
     uint32_t b0 = begin;
-    // ids of the next batch, loaded one batch ahead
-    uint32_t nx[2];
+    // ids of the next batch, loaded one batch ahead (DEEP: ids two batches
+    // ahead, splats of the next batch one batch ahead)
+    uint32_t nx[2], nx2[2];
+    Splat gnext[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
         const uint32_t e = b0 + (uint32_t)(j + 16 * hh);
         nx[hh] = e < end ? list[e] : 0u;
+        if (DEEP) {
+            if (e < end) gnext[hh] = load_packed(a.pk, nx[hh] < a.n ? nx[hh] : 0u);
+            const uint32_t e2 = e + kBatch;
+            nx2[hh] = e2 < end ? list[e2] : 0u;
+        }
     }
     for (; b0 < end; b0 += kBatch) {
         const uint64_t live = __ballot(!h.st.done);
         if (live == 0) break;
         uint32_t cur[2] = {nx[0], nx[1]};
+        Splat gcur[2];
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const uint32_t e = b0 + kBatch + (uint32_t)(j + 16 * hh);
-            nx[hh] = e < end ? list[e] : 0u;
+            if (DEEP) {
+                gcur[hh] = gnext[hh];
+                nx[hh] = nx2[hh];
+                if (e < end) gnext[hh] = load_packed(a.pk, nx[hh] < a.n ? nx[hh] : 0u);
+                const uint32_t e2 = e + kBatch;
+                nx2[hh] = e2 < end ? list[e2] : 0u;
+            } else {
+                nx[hh] = e < end ? list[e] : 0u;
+            }
         }
         const bool row_live = sub_ok && ((live >> (row * 16)) & 0xffffull) != 0;
         if (!row_live) continue;
@@ -658,7 +751,7 @@ __device__ __forceinline__ uint32_t render_strip(const RenderArgs& a, int tile, 
                 uint32_t id = cur[hh];
                 id = id < a.n ? id : 0u;
                 i2[hh] = id;
-                const Splat g = load_packed(a.pk, id);
+                const Splat g = DEEP ? gcur[hh] : load_packed(a.pk, id);
                 if (MODE == kFwdCount) ++h.work[kWorkTailTest];
                 if ((a.flags & kAblateHierCull) || block_clears(g, S0, S1, S2, S3)) {
                     if (MODE == kFwdCount) ++h.work[kWorkTailKey];
@@ -837,7 +930,7 @@ __global__ __launch_bounds__(256, K <= 4 ? 3 : 2) void k_render_hier(RenderArgs 
 // to counters[1] by the tile's last strip, through two per-tile words after
 // the flags (zeroed with them); the strips of a tile share an XCD, so their
 // atomics meet in one L2.
-template <int K, int MODE>
+template <int K, int MODE, bool DEEP>
 __global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
     __shared__ WaveQueues s_q;
     __shared__ float s_pay[head_alpha_in_lds(K, MODE) ? 64 * K : 1];
@@ -845,7 +938,7 @@ __global__ __launch_bounds__(64) void k_render_hier1(RenderArgs a) {
     const int strip = (int)(r / 8u), tile = (int)(g * 8u + r % 8u);
     const int n_tiles = a.cam.tiles_x * a.cam.tiles_y;
     if (tile >= n_tiles) return;
-    const uint32_t c = render_strip<K, MODE>(a, tile, tile, strip, s_q, nullptr, s_pay);
+    const uint32_t c = render_strip<K, MODE, DEEP>(a, tile, tile, strip, s_q, nullptr, s_pay);
     if (threadIdx.x == 0) {
         uint32_t* used = a.tile_flag + n_tiles;
         uint32_t* done = used + n_tiles;
@@ -1234,16 +1327,23 @@ hipError_t launch_window_k(const RenderArgs& a, hipStream_t s) {
 
 template <int K>
 hipError_t launch_hier_k(const RenderArgs& a, hipStream_t s) {
+    // the loads-ahead variant fits the registers (256 per lane, no spill) for heads up to 8
+    constexpr bool kDeepBuilt = K <= 8;
     const unsigned tiles = (unsigned)(a.cam.tiles_x * a.cam.tiles_y);
     if (a.work) {
         if (K != 4) return hipErrorInvalidValue;  // the counting kernel is built for the default head
         hipLaunchKernelGGL((k_render_hier<4, kFwdCount>), dim3(tiles), dim3(256), 0, s, a);
     } else if (a.grad2d)
         hipLaunchKernelGGL((k_render_hier<K, kBwd>), dim3(tiles), dim3(256), 0, s, a);
+    else if ((a.blend_ids || a.delta) && a.deep)
+        hipLaunchKernelGGL((k_render_hier1<K, kFwdDebug, kDeepBuilt>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s,
+                           a);
     else if (a.blend_ids || a.delta)
-        hipLaunchKernelGGL((k_render_hier1<K, kFwdDebug>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_render_hier1<K, kFwdDebug, false>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
+    else if (a.deep)
+        hipLaunchKernelGGL((k_render_hier1<K, kFwd, kDeepBuilt>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((k_render_hier1<K, kFwd>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_render_hier1<K, kFwd, false>), dim3((tiles + 7u) / 8u * 32u), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
