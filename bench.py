@@ -6,7 +6,8 @@ duplication, radix sort and tile ranges, hierarchical render -- for one view
 of a 60-view orbit around a synthetic 3M-Gaussian scene (degree-3 SH) at
 1920x1080, with the scene resident in HBM.  Prints ONE JSON line.
 
-Timing: W untimed frames, then K frames bracketed by torch.cuda.synchronize();
+Timing: W untimed frames, then K frames bracketed by torch.cuda.synchronize(),
+spread evenly over the orbit's views (all of them when K equals their number);
 stage and kernel durations come from HIP events recorded on the render stream
 at the stage boundaries and around every radix-scatter launch.
 
@@ -114,6 +115,12 @@ def make_events(n):
     return evs, (C.c_void_p * n)(*[e.cuda_event for e in evs])
 
 
+def timed_view(i, steps, n_views):
+    """Orbit view of timed frame i: the timed frames spread evenly over the
+    whole orbit (every view once when steps equals the number of views)."""
+    return (i * n_views) // steps if steps <= n_views else i % n_views
+
+
 def time_frames(r, ds, cams, cfg, steps, warmup, passes):
     """Render warmup + steps frames; returns per-frame stage/kernel times (ms)."""
     import torch
@@ -129,7 +136,7 @@ def time_frames(r, ds, cams, cfg, steps, warmup, passes):
     torch.cuda.synchronize()
     start.record()
     for i in range(steps):
-        r.render_async(ds, cams[(warmup + i) % len(cams)], cfg, out, events=frames[i][1])
+        r.render_async(ds, cams[timed_view(i, steps, len(cams))], cfg, out, events=frames[i][1])
     end.record()
     torch.cuda.synchronize()
     if int(r.status.item()) != 0:
@@ -156,7 +163,7 @@ def time_simple(r, ds, cams, cfg, steps, warmup):
     torch.cuda.synchronize()
     start.record()
     for i in range(steps):
-        r.render_async(ds, cams[(warmup + i) % len(cams)], cfg, out)
+        r.render_async(ds, cams[timed_view(i, steps, len(cams))], cfg, out)
     end.record()
     torch.cuda.synchronize()
     if int(r.status.item()) != 0:
@@ -528,7 +535,7 @@ def main():
         emax, consumed = plan(r, ds, cams, cfg)
         ms, stages, scatter, kernels = time_frames(r, ds, cams, cfg, args.steps, args.warmup, passes)
         # entries of the timed views (every view was rendered once while planning)
-        views = [(args.warmup + i) % len(cams) for i in range(args.steps)]
+        views = [timed_view(i, args.steps, len(cams)) for i in range(args.steps)]
         E_views, cons_views, fb_views = [], [], []
         for v in sorted(set(views)):
             r.render(ds, cams[v], cfg)
@@ -553,7 +560,7 @@ def main():
     # 19, opacity 1; t_opt 26; pixel alpha 31; blend 14).
     r = gsr.Renderer(entries_hint=40 * n)
     r.plan(n, W, H, int(h["emax"] * 1.05) + 1024)
-    timed = sorted(set((args.warmup + i) % len(cams) for i in range(args.steps)))
+    timed = sorted(set(timed_view(i, args.steps, len(cams)) for i in range(args.steps)))
     works = [r.render_work(ds, cams[v], gsr.config(mode=gsr.MODE_HIER, sort_prefix=args.sort_prefix))[1]
              for v in timed]
     work = {k: int(round(mean([w[k] for w in works]))) for k in works[0]}
@@ -634,7 +641,7 @@ def main():
         log("fwd+bwd: %s" % line["fwd_bwd"])
     if not args.no_cpu_baseline and args.workload != "small":
         log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(scene, cams[args.warmup % len(cams)], int(h["emax"]))
+        line["cpu_baseline"] = cpu_baseline(scene, cams[timed_view(0, args.steps, len(cams))], int(h["emax"]))
     elif not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, cams[0], int(h["emax"]))
     print(json.dumps(line), flush=True)

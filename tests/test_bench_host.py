@@ -69,3 +69,12 @@ def test_argument_defaults(argv, monkeypatch):
     a = bench.parse()
     assert a.gpus == 1 and a.workload == "3m_1080p"
     assert a.steps >= 1 and a.warmup >= 0
+
+
+def test_timed_views_span_the_orbit():
+    import bench
+    for steps in (1, 5, 20, 30, 60):
+        views = [bench.timed_view(i, steps, 60) for i in range(steps)]
+        assert views == sorted(set(views)) and views[0] == 0
+        assert max(views) >= 60 - 60 // steps - 1
+    assert [bench.timed_view(i, 90, 60) for i in range(90)][60:] == list(range(30))
