@@ -338,7 +338,7 @@ __device__ __forceinline__ int wg_max_excl(int v, uint32_t* lw) {
 // holds fewer than kChunkHalf entries plus its last bin; one beyond
 // kChunkEntries (a bin that large) is sorted by radix passes instead of in
 // LDS.  A tile has at most n / kChunkHalf + 1 chunks.
-constexpr uint32_t kChunkEntries = 8192;
+constexpr uint32_t kChunkEntries = 4096;
 constexpr uint32_t kChunkHalf = kChunkEntries / 2;
 
 __global__ __launch_bounds__(kT) void k_flag_chunks(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
