@@ -362,6 +362,7 @@ __global__ __launch_bounds__(kT) void k_flag_chunks(const uint64_t* __restrict__
             len[t] = n;
         }
         if (n <= kChunkEntries) {
+#pragma unroll 4
             for (uint32_t i = tid; i < n; i += kT)
                 scratch[rb + i] = ((uint64_t)depth_of(keys[rb + i]) << 32) | vals[rb + i];
             if (tid == 0) chunks[atomicAdd(counters + 7, 1u)] = make_uint2(rb, n);
@@ -369,7 +370,17 @@ __global__ __launch_bounds__(kT) void k_flag_chunks(const uint64_t* __restrict__
         }
         for (int k = tid; k < kPrefixBins; k += kT) hist[k] = 0;
         __syncthreads();
-        for (uint32_t i = rb + tid; i < rb + n; i += kT) atomicAdd(&hist[depth_bin(depth_of(keys[i]))], 1u);
+        {   // eight keys per thread in flight
+            uint32_t i = rb + tid;
+            for (; i + 7 * kT < rb + n; i += 8 * kT) {
+                uint32_t d[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d[u] = depth_of(keys[i + u * kT]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) atomicAdd(&hist[depth_bin(d[u])], 1u);
+            }
+            for (; i < rb + n; i += kT) atomicAdd(&hist[depth_bin(depth_of(keys[i]))], 1u);
+        }
         __syncthreads();
         // Thread tid owns bins [16 tid, 16 tid + 16).  A non-empty bin b
         // belongs to block pre(b) / kChunkHalf (pre = entries of earlier
@@ -434,11 +445,28 @@ __global__ __launch_bounds__(kT) void k_flag_chunks(const uint64_t* __restrict__
             hist[c] = 0;  // fill counts
         }
         __syncthreads();
-        for (uint32_t i = rb + tid; i < rb + n; i += kT) {
-            const uint32_t d = depth_of(keys[i]);
-            const uint32_t c = cmap[depth_bin(d)];
-            const uint32_t slot = atomicAdd(&hist[c], 1u);
-            scratch[rb + cstart[c] + slot] = ((uint64_t)d << 32) | vals[i];
+        {   // eight entries per thread in flight
+            uint32_t i = rb + tid;
+            for (; i + 7 * kT < rb + n; i += 8 * kT) {
+                uint32_t d[8], v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    d[u] = depth_of(keys[i + u * kT]);
+                    v[u] = vals[i + u * kT];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t c = cmap[depth_bin(d[u])];
+                    const uint32_t slot = atomicAdd(&hist[c], 1u);
+                    scratch[rb + cstart[c] + slot] = ((uint64_t)d[u] << 32) | v[u];
+                }
+            }
+            for (; i < rb + n; i += kT) {
+                const uint32_t d = depth_of(keys[i]);
+                const uint32_t c = cmap[depth_bin(d)];
+                const uint32_t slot = atomicAdd(&hist[c], 1u);
+                scratch[rb + cstart[c] + slot] = ((uint64_t)d << 32) | vals[i];
+            }
         }
         __syncthreads();
     }
@@ -512,6 +540,7 @@ __global__ __launch_bounds__(kT) void k_sort_chunks(uint64_t* __restrict__ keys,
         const uint2 ch = chunks[c];
         const uint32_t pos = ch.x, n = ch.y;
         if (n <= kChunkEntries) {
+#pragma unroll 4
             for (uint32_t i = tid; i < n; i += kT) sk[i] = scratch[pos + i];
             __syncthreads();
             lds_bitonic(sk, n);
