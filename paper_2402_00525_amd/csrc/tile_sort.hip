@@ -10,9 +10,11 @@
 //
 //   k_tile_prefix        every tile: its range [start, end) in the grouped
 //                        keys, and the first C <= M entries of that order,
-//                        sorted in LDS;
-//   k_tile_sort_flagged  tiles the renderer flagged because their pixels
-//                        outlived the prefix: the whole list, sorted.
+//                        sorted in LDS (or, M = 0, a flag for the whole-list
+//                        sort on every non-empty tile);
+//   k_flag_chunks,       tiles the renderer flagged because their pixels
+//   k_sort_chunks        outlived the prefix: the whole list, cut into
+//                        chunks of depth bins and sorted chunk by chunk.
 //
 // Both write Gaussian ids to out[range start + j] and the length to len[tile].
 #include <algorithm>
