@@ -57,7 +57,7 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 
 // Radix sort tiles
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 32;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
 inline size_t div_up(size_t a, size_t b) { return (a + b - 1) / b; }

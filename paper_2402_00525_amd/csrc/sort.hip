@@ -90,9 +90,11 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* lw, ui
     return before + x - v;
 }
 
-// The scatter of a sort tile runs 8 wavefronts of 8 rounds each: twice the
-// resident wavefronts of 4 x 16 in the same LDS.
-constexpr int kScatterWaves = 8;
+// The scatter of a sort tile (8192 keys) runs 16 wavefronts of 8 rounds
+// each, one workgroup per CU (132 KB of LDS): a digit's run in the output is
+// twice as long as with 4096-key tiles, so fewer of the written lines are
+// partial.
+constexpr int kScatterWaves = 16;
 constexpr int kScatterRounds = kSortTile / (64 * kScatterWaves);
 constexpr int kScatterThreads = 64 * kScatterWaves;
 static_assert(kScatterRounds * kScatterThreads == kSortTile, "scatter covers one sort tile");
@@ -102,7 +104,7 @@ static_assert(kScatterRounds * kScatterThreads == kSortTile, "scatter covers one
 //     lanes with equal digits are found by ballots over the digit bits, and
 //     a per-wavefront running count per digit in LDS gives each key its rank
 //     among equal digits -- no workgroup barrier inside the loop.
-//  2. Per digit: offsets of the eight wavefronts, the block's local start
+//  2. Per digit: offsets of the wavefronts, the block's local start
 //     (exclusive scan over digits) and the distance to the global start.
 //  3. Keys are placed in LDS in (digit, index) order, then written out so
 //     that consecutive lanes write consecutive addresses of a digit's run.
