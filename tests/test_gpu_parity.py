@@ -63,18 +63,21 @@ def test_small_scene_bit_exact(mode):
     np.testing.assert_array_equal(g["rgb"].view(np.uint32), o.rgb.view(np.uint32))
 
 
-@pytest.mark.parametrize("mode,prefix", [(oracle.MODE_HIER, 0), (oracle.MODE_HIER, 64), (oracle.MODE_GLOBAL, 0)])
-def test_small_image_whole_lists(mode, prefix):
+@pytest.mark.parametrize("mode,prefix,head", [(oracle.MODE_HIER, 0, 4), (oracle.MODE_HIER, 64, 4),
+                                              (oracle.MODE_GLOBAL, 0, 4), (oracle.MODE_HIER, 0, 2),
+                                              (oracle.MODE_HIER, 0, 8), (oracle.MODE_HIER, 0, 12)])
+def test_small_image_whole_lists(mode, prefix, head):
     """Below 512 tiles the default sorts every tile's whole list before one
-    render pass (no prefix); an explicit prefix keeps the prefix pass and the
-    fallback.  Both give the oracle's lists and blend order."""
+    render pass (no prefix), and the hierarchical render loads its splats
+    ahead (heads up to 8); an explicit prefix keeps the prefix pass and the
+    fallback.  All give the oracle's lists and blend order."""
     from paper_2402_00525_amd import gsr
     sc = synth.subsample(synth.mixture_scene(100_000, seed=3), 30_000)
     cam = synth.orbit_camera(256, 256, 11)
     assert gsr.lib().gsr_default_prefix(256, 256, mode) == 0
-    say("case: 256x256, mode", mode, "prefix", prefix)
-    o = oracle.frame(sc, cam, mode=mode, max_k=64)
-    g = gpu_frame(sc, cam, mode=mode, max_k=64, sort_prefix=prefix)
+    say("case: 256x256, mode", mode, "prefix", prefix, "head", head)
+    o = oracle.frame(sc, cam, mode=mode, head=head, max_k=64)
+    g = gpu_frame(sc, cam, mode=mode, head=head, max_k=64, sort_prefix=prefix)
     L = g["lists"]
     nonempty = int((np.diff(L["ranges"], axis=1) > 0).sum())
     if prefix == 0:
