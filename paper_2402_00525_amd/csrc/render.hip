@@ -207,10 +207,14 @@ __device__ __forceinline__ void quad_flush(const RenderArgs& a, PixelState<K, MO
         t = t + (rq[3] == r ? v3 : 0.0f);
         sum[c] = t;
     }
-    if (leader) {
+    // Every component is added, zero or not: a branch per component cost
+    // more than the zero adds.
+    if (leader && r < (uint32_t)kAccSlots) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c)
-            if (sum[c] != 0.0f) add_grad(a, acc, r, s.gid, c, sum[c]);
+        for (int c = 0; c < 9; ++c) atomicAdd(acc + c * kAccSlots + r, sum[c]);
+    } else if (leader) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) atomicAdd(a.grad2d + 9 * (size_t)s.gid + c, sum[c]);
     }
     s.gpend = false;
 }
