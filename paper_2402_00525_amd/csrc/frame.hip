@@ -441,11 +441,13 @@ __device__ __forceinline__ int flat_owner(const FlatStarts& f, uint32_t j, uint3
     return r > 0 ? (int)f.lane_of[(r - 1u) & 63u] : 0;
 }
 
-// SH coefficients of a workgroup's Gaussians are staged in LDS in chunks of
-// kShChunk coefficients (3 kShChunk floats per Gaussian, odd row stride so
-// that lanes reading their own rows hit distinct banks).
-constexpr int kShChunk = 8;
-constexpr int kShStride = 3 * kShChunk + 1;
+// SH coefficients of a workgroup's Gaussians are staged in LDS as whole rows
+// (3 (deg + 1)^2 floats per Gaussian), kShRows Gaussians per round, so that
+// every cache line of the coefficients is read once; rows are kShStride
+// floats apart at most, with an odd stride so that lanes reading their own
+// rows hit distinct banks.
+constexpr int kShRows = 128;
+constexpr int kShStride = 3 * 16 + 1;
 
 // Per-wavefront staging for the flat kept-tile test (reuses the SH memory).
 struct CountStage {
@@ -455,14 +457,14 @@ struct CountStage {
     uint64_t mask[64];
     FlatStarts fs;
 };
-static_assert(4 * sizeof(CountStage) <= 256 * kShStride * sizeof(float), "staging fits the SH area");
+static_assert(4 * sizeof(CountStage) <= kShRows * kShStride * sizeof(float), "staging fits the SH area");
 
 // One lane per Gaussian.  Gaussians whose rectangle holds more than
 // lane_tile_limit(lb) tiles are counted in a second phase by the whole
 // wavefront (Sec. 3.4, load balancing), one Gaussian at a time, tiles spread
 // over the lanes; the others record which rectangle tiles they keep.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
-    __shared__ __align__(16) float s_sh[256 * kShStride];
+    __shared__ __align__(16) float s_sh[kShRows * kShStride];
     __shared__ uint32_t s_dh[kDupBins];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = __lane_id();
@@ -472,46 +474,46 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
     bool vis = false;
     if (i < a.sc.n) vis = project_geom(a.sc, a.cam, a.mode, a.mode == kModeHier && !(a.flags & kAblateTileCull), i, po);
     // Colour: SH along the direction camera -> mean (App. B.4), the
-    // coefficients of the workgroup's Gaussians staged through LDS chunk by
-    // chunk with coalesced loads; each channel sums its terms in order k =
-    // 0, 1, ..., K - 1.
-    const int K = (a.sc.deg + 1) * (a.sc.deg + 1), row = 3 * K;
+    // coefficients of the workgroup's Gaussians staged through LDS, kShRows
+    // whole rows per round with coalesced loads; each channel sums its terms
+    // in order k = 0, 1, ..., K - 1.
+    const int K = (a.sc.deg + 1) * (a.sc.deg + 1), row = 3 * K, S = row | 1;
     const int b0 = blockIdx.x * blockDim.x;
     const int nloc = min((int)blockDim.x, a.sc.n - b0);
     float rgb[3] = {0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < K; k0 += kShChunk) {
-        const int kc = min(kShChunk, K - k0), ncol = 3 * kc;
+    float bas[16];
+    if (vis) sh_basis(a.sc.deg, po.dir[0], po.dir[1], po.dir[2], bas);
+    for (int r0 = 0; r0 < nloc; r0 += kShRows) {
+        const int nr = min(kShRows, nloc - r0);
         {
             // (Gaussian, column) of element f, advanced by blockDim.x per step
-            const float* src = a.sc.sh + (size_t)b0 * row + 3 * k0;
-            int gidx = (int)threadIdx.x / ncol, col = (int)threadIdx.x - gidx * ncol;
-            const int sq = (int)blockDim.x / ncol, sr = (int)blockDim.x - sq * ncol;
-            for (int f = threadIdx.x; f < nloc * ncol; f += blockDim.x) {
-                s_sh[gidx * kShStride + col] = src[(size_t)gidx * row + col];
+            const float* src = a.sc.sh + (size_t)(b0 + r0) * row;
+            int gidx = (int)threadIdx.x / row, col = (int)threadIdx.x - gidx * row;
+            const int sq = (int)blockDim.x / row, sr = (int)blockDim.x - sq * row;
+            for (int f = threadIdx.x; f < nr * row; f += blockDim.x) {
+                s_sh[gidx * S + col] = src[f];
                 gidx += sq;
                 col += sr;
-                if (col >= ncol) {
-                    col -= ncol;
+                if (col >= row) {
+                    col -= row;
                     ++gidx;
                 }
             }
         }
         __syncthreads();
-        if (vis) {
-            float bas[16];
-            sh_basis(a.sc.deg, po.dir[0], po.dir[1], po.dir[2], bas);
-            const float* shp = s_sh + threadIdx.x * kShStride;
+        const int li = (int)threadIdx.x - r0;
+        if (vis && li >= 0 && li < kShRows) {
+            const float* shp = s_sh + li * S;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                float acc = rgb[ch];
-                for (int k = 0; k < kc; ++k) {
-                    const float t = bas[k0 + k] * shp[3 * k + ch];
-                    acc = (k0 + k == 0) ? t : acc + t;
-                }
+                float acc = bas[0] * shp[ch];
+#pragma unroll
+                for (int k = 1; k < 16; ++k)
+                    if (k < K) acc = acc + bas[k] * shp[3 * k + ch];
                 rgb[ch] = acc;
             }
         }
-        __syncthreads();  // the chunk is consumed before the next is staged
+        __syncthreads();  // the rows are consumed before the next are staged
     }
     if (vis) {
 #pragma unroll

@@ -29,6 +29,8 @@ constexpr int kT = 256;              // threads per workgroup
 constexpr int kTW = kT / 64;         // wavefronts per workgroup
 constexpr int kPrefixBins = 4096;    // histogram bins of the prefix selection
 constexpr int kBinsPerThread = kPrefixBins / kT;
+constexpr int kStashRounds = 2;      // rounds of 8 depths per thread kept in registers
+constexpr uint32_t kStash = kStashRounds * 8 * kT;  // entries whose depths are kept
 
 // Fixed histogram bins over the order-preserving depth bits: bits 16..30 of
 // (key - ord(2^-8)), i.e. 128 bins per octave of depth from 2^-8 to 2^24;
@@ -188,8 +190,24 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     for (int k = tid; k < kPrefixBins; k += kT) hist[k] = 0;
     if (tid == 0) s_fill = 0;
     __syncthreads();
+    // The depths of the first kStash entries stay in registers for the
+    // selection; the rest of a longer list is read again there.
+    uint32_t st[kStashRounds][8];
+#pragma unroll
+    for (int s = 0; s < kStashRounds; ++s) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = rb + (uint32_t)(s * 8 + u) * kT + tid;
+            st[s][u] = i < re ? depth_of(keys[i]) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = rb + (uint32_t)(s * 8 + u) * kT + tid;
+            if (i < re) atomicAdd(&hist[depth_bin(st[s][u])], 1u);
+        }
+    }
     {
-        uint32_t i = rb + tid;
+        uint32_t i = rb + kStash + tid;
         for (; i + 7 * kT < re; i += 8 * kT) {
             uint32_t d[8];
 #pragma unroll
@@ -224,7 +242,23 @@ __global__ __launch_bounds__(kT) void k_tile_prefix(const uint64_t* __restrict__
     const uint32_t C = s_C, limit = s_limit;
     // Selection, eight keys per thread in flight (the order of appends does
     // not matter: the selected entries are sorted next).
-    for (uint32_t i0 = rb; i0 < re; i0 += 8 * kT) {
+#pragma unroll
+    for (int s = 0; s < kStashRounds; ++s) {
+        bool take[8];
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t i = rb + (uint32_t)(s * 8 + u) * kT + tid;
+            take[u] = i < re && depth_bin(st[s][u]) < limit;
+            v[u] = take[u] ? vals[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t slot = wave_append(take[u], &s_fill);
+            if (take[u]) sk[slot] = ((uint64_t)st[s][u] << 32) | v[u];
+        }
+    }
+    for (uint32_t i0 = rb + kStash; i0 < re; i0 += 8 * kT) {
         uint64_t k[8];
         uint32_t v[8];
         bool take[8];
