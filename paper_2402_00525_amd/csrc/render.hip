@@ -100,7 +100,10 @@ struct WaveQueues {
     uint32_t mid[16][kMidCap];
 };
 
-constexpr bool head_keeps_ids(int K, int MODE) { return K <= 8 && MODE != kBwd; }
+// Heads up to 8 keep each slot's Gaussian (forward and backward alike: the
+// backward's blend then issues its splat and colour loads without first
+// reading the tile list).
+constexpr bool head_keeps_ids(int K, int MODE) { return K <= 8; }
 // Large forward heads keep their alphas in LDS (one word per lane and slot),
 // not in registers: with the keys alone the K = 16 head fits three
 // wavefronts per SIMD.  Their keys' low word is then rank << 5 | slot, where
